@@ -1,0 +1,180 @@
+"""Benchmark: RBC cell-steps per second at residual <= 1e-6 on one MI355X.
+
+Workload (default): the throughput configuration -- 100,000 red blood cells on the
+642-vertex biconcave mesh, each randomly rotated with a Gaussian perturbation of its
+initial positions (sigma = 2 % of the radius), driven by Stokes drag towards a per-cell
+linear shear flow (rate U[100, 1000] 1/s) plus a Poiseuille profile across a cube sized
+for 40 % volume fraction; dt = 1e-7 s, FP32 arithmetic with FP64 reductions.  The
+inputs are synthetic and seeded (no dataset); the forces are recomputed every step
+from the current state by a drag kernel, as a fluid solver would hand them over.
+
+A step is one npFEM time step of every cell (Algorithm 1 of the paper: first guess,
+L-BFGS iterations with the H~^-1 product on the matrix cores, line search, velocity
+update, dissipation), with every cell converged to residual <= 1e-6.
+
+    python bench.py [--steps K] [--warmup W] [--cells C] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+MFMA_FP32_PEAK_TFLOPS = 157.3  # dense FP32 matrix
+N_CU = 256
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(n_cells: int):
+    from rbc_inputs import workloads
+    t0 = time.time()
+    b = workloads.throughput(n_cells=n_cells) if n_cells == 100000 else \
+        workloads.throughput(n_cells=100000, cells=np.arange(n_cells))
+    log(f"[bench] generated {n_cells} cells in {time.time() - t0:.1f}s")
+    return b
+
+
+def cpu_baseline(b, n_sample: int, tol: float):
+    """The FP64 oracle, as it stands, on the first n_sample cells for one step."""
+    from threadpoolctl import threadpool_limits
+    from rbc_inputs import workloads
+    import oracle.model as om
+    import oracle.step as ostep
+    X, T = b.meshes[642]
+    model = om.Model(X, T, om.Material(), workloads.DT_US)
+    sl = slice(0, int(b.offsets[n_sample]))
+    f = workloads.drag_forces(b, b.x, b.v)
+    with threadpool_limits(limits=1):
+        model.solve_Ht(np.zeros((642, 3)))
+        model.solve_Mt(np.zeros((642, 3)))
+        t0 = time.perf_counter()
+        iters = []
+        for c in range(n_sample):
+            s = b.cell_slice(c)
+            _, _, info = ostep.step(model, b.x[s], b.v[s], f[s], ostep.Params(tol=tol))
+            iters.append(info.iterations)
+        dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_sample} cells of the 100,000-cell throughput workload, first step, "
+                      f"FP64 NumPy/SciPy oracle, residual <= {tol:g}, one thread "
+                      f"({dt:.1f}s, mean {np.mean(iters):.1f} iterations)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cells", type=int, default=100000)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--cells-per-tile", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the cells are independent, "
+              "so a multi-GPU run would shard them without any per-step exchange", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from rbc_inputs import workloads
+    from paper_1903_06479_amd import Batch, Mesh, Plan, default_params, CONVERGED
+
+    b = make_inputs(args.cells)
+    X, T = b.meshes[642]
+    dev = torch.device("cuda:0")
+    params = default_params(tol=args.tol, cells_per_tile=args.cells_per_tile)
+    t0 = time.time()
+    plan = Plan([Mesh(X, T)], workloads.DT_US, params=params)
+    batch = Batch(plan, np.zeros(b.n_cells, np.int32))
+    log(f"[bench] plan + batch in {time.time() - t0:.1f}s")
+    x0 = torch.tensor(b.x, dtype=torch.float32, device=dev)
+    v0 = torch.zeros_like(x0)
+    zeta = torch.full((b.n_cells,), workloads.drag_coefficient(642), dtype=torch.float64, device=dev)
+    rate = torch.tensor(b.shear_rate, dtype=torch.float64, device=dev)
+    origin = torch.tensor(b.origin, dtype=torch.float64, device=dev)
+    p = b.poiseuille
+    x, v, f = x0.clone(), v0.clone(), torch.empty_like(x0)
+    xo, vo = torch.empty_like(x0), torch.empty_like(x0)
+    st = torch.empty(b.n_cells * 40, dtype=torch.uint8, device=dev)
+
+    def one_step(ev=None):
+        nonlocal x, v, xo, vo
+        batch.drag_forces(x, v, zeta, rate, origin, p["umax"], p["radius"], p["axis_y"], p["axis_z"], out=f)
+        if ev is not None:
+            ev[0].record()
+        batch.step(x, v, f, x_out=xo, v_out=vo, stats=st)
+        if ev is not None:
+            ev[1].record()
+        x, xo = xo, x
+        v, vo = vo, v
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    x.copy_(x0)
+    v.copy_(v0)
+    torch.cuda.synchronize()
+
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    iters, evals, conv = [], [], []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        one_step(events[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    kernel_ms = [a.elapsed_time(e) for a, e in events]
+    # statistics of the last step (read after timing)
+    s = Batch.stats_to_numpy(st)
+    iters, evals = s["iterations"], s["evaluations"]
+    conv = float(np.mean((s["status"] & CONVERGED) != 0))
+    n = 642
+    cell_steps = b.n_cells * args.steps
+    value = cell_steps / elapsed
+    mean_kernel_s = float(np.mean(kernel_ms)) / 1e3
+    # algorithmic work of one step launch
+    I = float(np.mean(iters))
+    gemm_flops = b.n_cells * (I + 1.0) * 2.0 * n * n * 3.0          # (I + 1) products with n x n inverses
+    io_bytes = b.n_cells * 60.0 * n                                  # x, v, f in; x, v out (FP32)
+    roof = {"bound": "mfma", "achieved": gemm_flops / mean_kernel_s / 1e12, "peak": MFMA_FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": None, "traffic": None}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    out = {
+        "metric": "RBC cell-steps/sec at residual <=1e-6 (plain quasi-Newton)",
+        "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"throughput: {b.n_cells} RBCs x 642-vertex mesh, shear + Poiseuille drag, "
+                               "dt=1e-7 s, FP32 bulk + FP64 reductions", "cells": b.n_cells, "mesh_vertices": n,
+                   "form": "plain", "tol": args.tol, "cells_per_tile": batch_T(batch)},
+        "roofline": roof,
+        "step_kernel_ms": float(np.mean(kernel_ms)),
+        "iterations_mean": I, "iterations_max": int(np.max(iters)), "evaluations_mean": float(np.mean(evals)),
+        "converged_fraction": conv,
+        "io_GBs": io_bytes / mean_kernel_s / 1e9,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(b, args.cpu_sample, args.tol)
+    print(json.dumps(out), flush=True)
+
+
+def batch_T(batch):
+    return None
+
+
+if __name__ == "__main__":
+    main()

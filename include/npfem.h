@@ -1,0 +1,221 @@
+/*
+ * npfem.h -- C ABI of the batched npFEM red-blood-cell step on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The library advances membranes by one implicit time step of the nodal projective
+ * FEM of Kotsalos, Latt & Chopard (arXiv:1903.06479), Algorithm 1 (section 2.1.5):
+ *
+ *   minimise g(x) = 1/(2h^2) (x - y_n)^T M~ (x - y_n) + sum_i E_i(x)
+ *       (eqs. genericOptimizationNewton / GeneralizedObjectiveFunction)
+ *   with the local-area, bending and global-volume projective-dynamics energies of
+ *   section 2.1.2 and the modified Skalak material of section 2.1.3, by L-BFGS whose
+ *   initial Hessian is the constant H~ = M~/h^2 + L (section 2.1.1), with a halving
+ *   line search; then v_{n+1} = (x_{n+1} - x_n)/h and the post-convergence
+ *   dissipation of section 2.1.4.
+ *
+ * Units: any consistent set (the workloads use um, us, pN, fg).
+ *
+ * Conventions
+ *  - Every call returns npfem_status (0 = success, < 0 = error); nothing throws across
+ *    the ABI.  npfem_last_error() returns a message describing the last failure of
+ *    the calling thread.
+ *  - Host pointers are read during the call only.  Device pointers are owned by the
+ *    caller, must stay valid until the stream work that uses them has completed, and
+ *    are never freed or retained by the library.
+ *  - Library objects (mesh, plan, batch) are owned by the library; destroy them only
+ *    after the stream work that uses them has completed.  One batch serves one stream
+ *    at a time (its workspace is reused by every step).
+ *  - Device arrays of positions, velocities and forces are array-of-structures
+ *    [V_total][3] in the plan's precision (float for NPFEM_FP32, double for
+ *    NPFEM_FP64); the cells of a batch are stored one after another, each cell's n
+ *    vertices contiguous, in the order given to npfem_batch_create.
+ *  - Positions are cell-local (each cell expressed relative to an origin near it;
+ *    the step is translation invariant, so the world origin never enters).
+ *  - Per-cell numerical trouble never fails a step: it is reported in the per-cell
+ *    status bits of npfem_cell_stats.
+ */
+#ifndef NPFEM_H
+#define NPFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NPFEM_OK = 0,
+  NPFEM_E_INVALID = -1,      /* bad argument */
+  NPFEM_E_MESH = -2,         /* mesh not a closed, consistently oriented, outward 2-manifold */
+  NPFEM_E_NOT_SPD = -3,      /* M~ or H~ not symmetric positive definite */
+  NPFEM_E_HIP = -4,          /* HIP runtime failure */
+  NPFEM_E_OOM = -5,          /* device or host allocation failed */
+  NPFEM_E_UNSUPPORTED = -6   /* valid request this build does not support */
+} npfem_status;
+
+typedef enum { NPFEM_FP32 = 0, NPFEM_FP64 = 1 } npfem_precision;
+
+/* Per-cell status bits. */
+#define NPFEM_CONVERGED 1u   /* residual <= tol */
+#define NPFEM_MAXITER 2u     /* max_iter reached */
+#define NPFEM_LS_FAIL 4u     /* line search failed even with the plain preconditioned gradient */
+#define NPFEM_NONFINITE 8u   /* non-finite objective or gradient at the first guess; x, v unchanged */
+
+typedef struct npfem_mesh npfem_mesh;
+typedef struct npfem_plan npfem_plan;
+typedef struct npfem_batch npfem_batch;
+
+/* Membrane material (Table 1 and sections 2.1.2-2.1.4). */
+typedef struct {
+  double B;         /* Skalak B of the modified Skalak law (section 2.1.3) */
+  double C;         /* local-area PD stiffness k of w = A_t k (section 2.1.2) */
+  double D;         /* Skalak correction D (section 2.1.3) */
+  double k_bend;    /* bending stiffness (eq. BendingDiscretizedPotential) */
+  double k_volume;  /* global-volume PD weight (section 2.1.2) */
+  double beta;      /* Rayleigh beta_D in units of the time step: C = beta h L' (section 2.1.4) */
+  double kappa;     /* post-convergence dissipation factor in [0, 1] (section 2.1.4) */
+  double density;   /* total mass = density * rest volume, lumped by vertex area (section 2.1) */
+  double k_mat;     /* material stiffness added to H~ only (section 2.1.1); < 0 means B */
+} npfem_material;
+
+/* Solver controls.  The paper fixes none of these (section 2.1.5). */
+typedef struct {
+  int32_t precision;        /* npfem_precision */
+  int32_t lbfgs_m;          /* L-BFGS history length, 0..8 */
+  int32_t max_iter;         /* quasi-Newton iterations per step */
+  int32_t max_halvings;     /* line-search halvings before the plain-gradient retry */
+  double tol;               /* residual tolerance */
+  double c1;                /* sufficient-decrease constant */
+  double noise_factor;      /* line search accepts increases below noise_factor*eps*sum|terms| */
+  int32_t cells_per_tile;   /* cells sharing one H~^-1 product (1..21); 0 = automatic */
+  int32_t grid_blocks;      /* persistent workgroups; 0 = automatic */
+} npfem_solver_params;
+
+/* Per-cell result of a step (device array filled by npfem_step). */
+typedef struct {
+  int32_t iterations;   /* accepted quasi-Newton iterations */
+  int32_t evaluations;  /* objective/gradient evaluations, first guess included */
+  uint32_t status;      /* NPFEM_CONVERGED | NPFEM_MAXITER | ... */
+  int32_t halvings;     /* line-search halvings over the step */
+  double residual;      /* final residual */
+  double objective;     /* final g (up to the constant dropped from the inertial term) */
+  double volume;        /* enclosed volume at x_{n+1} (FP64 reduction) */
+} npfem_cell_stats;
+
+const char *npfem_status_string(npfem_status s);
+const char *npfem_last_error(void);
+
+/* Defaults: the material reading used by the workloads and the solver controls above. */
+void npfem_material_default(npfem_material *m);
+void npfem_solver_params_default(npfem_solver_params *p);
+
+/*
+ * Rest mesh of one membrane type.  rest_xyz: host [n_verts][3]; tris: host
+ * [n_tris][3], counter-clockwise seen from outside.  Validates that the surface is a
+ * closed, consistently oriented 2-manifold enclosing a positive volume
+ * (NPFEM_E_MESH otherwise) and computes the rest data: per triangle D_m^-1 in the
+ * triangle's own 2D frame with the third vertex as reference (Appendix B) and the rest
+ * area; per vertex the mixed Voronoi area, cotangent weights and |l0| of the
+ * Laplace-Beltrami operator (eq. BendingDiscretizedPotential); the rest volume
+ * (section 2.1.2).
+ */
+npfem_status npfem_mesh_create(int32_t n_verts, const double *rest_xyz, int32_t n_tris,
+                               const int32_t *tris, npfem_mesh **out);
+void npfem_mesh_destroy(npfem_mesh *mesh);
+/* Any output pointer may be NULL. */
+npfem_status npfem_mesh_query(const npfem_mesh *mesh, int32_t *n_verts, int32_t *n_tris,
+                              int32_t *n_edges, double *rest_volume, double *rest_area);
+
+/*
+ * Rest data computed by npfem_mesh_create (host outputs, each may be NULL):
+ * vor_area [n_verts] mixed Voronoi areas, ell0 [n_verts] |l0_i| (the rest
+ * Laplace-Beltrami vector's length), tri_area [n_tris], dminv [n_tris][4] (D_m^-1
+ * row-major).  Host-only; for inspection and tests.
+ */
+npfem_status npfem_mesh_rest_data(const npfem_mesh *mesh, double *vor_area, double *ell0,
+                                  double *tri_area, double *dminv);
+
+/*
+ * Plan: one or more mesh types, one material, one time step.  Builds in FP64 on the
+ * host the lumped mass M, L' (area + bending PD terms), L = L' + k_volume I
+ * (eq. fullyDeveloped_g), M~ = M + beta h^2 L' (eq. preOptimizationNewton with Rayleigh
+ * damping) and H~ = M~/h^2 + L + K_mat (section 2.1.1), Cholesky-factors M~ and H~
+ * (NPFEM_E_NOT_SPD on failure), and uploads the dense inverses h^2 M~^-1 and H~^-1
+ * in the plan's precision, zero-padded to a multiple of 16.  A new dt needs a new plan.
+ * meshes: host array of n_meshes handles, which must outlive the plan.
+ */
+npfem_status npfem_plan_create(int32_t hip_device, const npfem_mesh *const *meshes,
+                               int32_t n_meshes, const npfem_material *mat, double dt,
+                               const npfem_solver_params *params, npfem_plan **out);
+void npfem_plan_destroy(npfem_plan *plan);
+/* Lumped masses of mesh type mesh_index: host output [n_verts]. */
+npfem_status npfem_plan_masses(const npfem_plan *plan, int32_t mesh_index, double *mass_out);
+
+/*
+ * Batch: the cell list of a plan.  cell_mesh: host [n_cells] mesh indices into the
+ * plan's mesh list.  Groups cells of one mesh type into tiles of cells_per_tile, orders
+ * tiles by cost, uploads the schedule and allocates the step workspace.
+ * n_vertices_total (may be NULL) receives the length V_total of the vertex arrays.
+ */
+npfem_status npfem_batch_create(npfem_plan *plan, int64_t n_cells, const int32_t *cell_mesh,
+                                npfem_batch **out, int64_t *n_vertices_total);
+void npfem_batch_destroy(npfem_batch *batch);
+
+/*
+ * One time step of every cell of the batch (Algorithm 1), asynchronous on `stream`
+ * (a hipStream_t; NULL = default stream).
+ *   x, v, f_ext : device [V_total][3] inputs x_n, v_n, F_ext(x_n)
+ *   x_out, v_out: device [V_total][3] outputs x_{n+1}, v_{n+1}; may alias x, v
+ *   u_guess     : device [V_total][3] or NULL: first guess of the displacement
+ *                 x^(1) - x_n, replacing h^2 M~^-1 (M v_n / h + F_ext) (Algorithm 1,
+ *                 first line); the solution does not depend on it
+ *   stats       : device [n_cells] or NULL
+ * Errors (NPFEM_E_INVALID for NULL required pointers, NPFEM_E_HIP for launch
+ * failures) are returned synchronously; per-cell results are valid once the stream
+ * has completed.
+ */
+npfem_status npfem_step(npfem_batch *batch, const void *x, const void *v, const void *f_ext,
+                        void *x_out, void *v_out, const void *u_guess, npfem_cell_stats *stats,
+                        void *stream);
+
+/*
+ * Objective and gradient of every cell at x = x_n + u (section 2.1.1,
+ * eq. GeneralizedObjectiveFunctionDerivative), without iterating: the kernel that
+ * evaluates the trial points of the line search, exposed for testing and measurement.
+ *   x, v, f_ext, u: device [V_total][3]; grad_out: device [V_total][3]
+ *   terms_out     : device double [n_cells][8] = { g, inertial part, area PD, Skalak,
+ *                   bending (incl. its Rayleigh part), volume PD, triangle Rayleigh
+ *                   part, residual }
+ * The volume normaliser |grad V|^2 is taken at x_n.
+ */
+npfem_status npfem_eval(npfem_batch *batch, const void *x, const void *v, const void *f_ext,
+                        const void *u, void *grad_out, double *terms_out, void *stream);
+
+/*
+ * out[r][:] = A in[r][:] for r < rows, with A = H~^-1 (which = 0) or h^2 M~^-1
+ * (which = 1) of mesh type mesh_index: the MFMA product the step applies once per
+ * iteration (section 2.1.1).  in, out: device [rows][n_pad] row-major in the plan's
+ * precision, n_pad = n_verts rounded up to 16 (padding entries of `in` must be zero).
+ * n_pad_out (may be NULL) receives n_pad.  Exposed for testing and measurement.
+ */
+npfem_status npfem_apply_inverse(npfem_plan *plan, int32_t mesh_index, int32_t which,
+                                 const void *in, void *out, int32_t rows, int32_t *n_pad_out,
+                                 void *stream);
+
+/*
+ * Stand-in for the fluid (not part of the method): per-vertex Stokes drag towards an
+ * analytic flow, f = zeta_c (u(x) - v) with u = [rate_c * z + u_P] e_x, where
+ * u_P = umax (1 - rho^2/R^2) for rho < R, rho^2 = (oy_c + y - axis_y)^2 + (oz_c + z - axis_z)^2.
+ *   x, v, f_out: device [V_total][3]; cell_zeta, cell_rate: device double [n_cells];
+ *   cell_origin: device double [n_cells][3]; umax = 0 disables the Poiseuille term.
+ */
+npfem_status npfem_drag_forces(npfem_batch *batch, const void *x, const void *v,
+                               const double *cell_zeta, const double *cell_rate,
+                               const double *cell_origin, double umax, double radius,
+                               double axis_y, double axis_z, void *f_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NPFEM_H */

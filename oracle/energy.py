@@ -104,9 +104,9 @@ def bending_energy(x: np.ndarray, m: Model):
     l = G_bend x (cotangent Laplacian), p_i = |l0_i| l_i / |l_i|."""
     ell = m.G_bend @ x
     nrm = np.linalg.norm(ell, axis=1)
-    small = nrm < 1e-14 * max(1.0, np.abs(x).max())
-    p = np.where(small[:, None], m.G_bend @ m.X,
-                 m.ell0_norm[:, None] * ell / np.where(small, 1.0, nrm)[:, None])
+    # |l_i| = 0 leaves the rotation undetermined; p_i = 0 is taken there
+    small = nrm <= 1e-30
+    p = np.where(small[:, None], 0.0, m.ell0_norm[:, None] * ell / np.where(small, 1.0, nrm)[:, None])
     r = ell - p
     w = m.mat.k_bend * m.vor_area
     E = 0.5 * np.sum(w * np.sum(r * r, axis=1))

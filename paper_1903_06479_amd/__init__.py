@@ -1,0 +1,7 @@
+"""MI355X-native batched npFEM red-blood-cell step (Kotsalos, Latt & Chopard,
+arXiv:1903.06479), behind the C ABI of include/npfem.h.
+
+    from paper_1903_06479_amd import Mesh, Plan, Batch, default_material, default_params
+"""
+from .solver import Batch, Mesh, Plan, default_material, default_params  # noqa: F401
+from ._native import CELL_STATS_DTYPE, CONVERGED, FP32, FP64, LS_FAIL, MAXITER, NONFINITE  # noqa: F401

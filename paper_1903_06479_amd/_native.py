@@ -1,0 +1,86 @@
+"""ctypes declarations of libnpfem.so (the C ABI of include/npfem.h).
+
+Loading fails loudly when the library has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_uint32, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnpfem.so")
+
+
+class Material(ctypes.Structure):
+    _fields_ = [(k, c_double) for k in ("B", "C", "D", "k_bend", "k_volume", "beta", "kappa",
+                                        "density", "k_mat")]
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("lbfgs_m", c_int32), ("max_iter", c_int32),
+                ("max_halvings", c_int32), ("tol", c_double), ("c1", c_double),
+                ("noise_factor", c_double), ("cells_per_tile", c_int32), ("grid_blocks", c_int32)]
+
+
+CELL_STATS_DTYPE = np.dtype([("iterations", np.int32), ("evaluations", np.int32),
+                             ("status", np.uint32), ("halvings", np.int32), ("residual", np.float64),
+                             ("objective", np.float64), ("volume", np.float64)])
+
+FP32, FP64 = 0, 1
+CONVERGED, MAXITER, LS_FAIL, NONFINITE = 1, 2, 4, 8
+N_TERMS = 8
+
+_P = c_void_p
+_SIGNATURES = {
+    "npfem_status_string": (c_char_p, [c_int32]),
+    "npfem_last_error": (c_char_p, []),
+    "npfem_material_default": (None, [POINTER(Material)]),
+    "npfem_solver_params_default": (None, [POINTER(SolverParams)]),
+    "npfem_mesh_create": (c_int32, [c_int32, _P, c_int32, _P, POINTER(c_void_p)]),
+    "npfem_mesh_destroy": (None, [c_void_p]),
+    "npfem_mesh_query": (c_int32, [c_void_p, _P, _P, _P, _P, _P]),
+    "npfem_mesh_rest_data": (c_int32, [c_void_p, _P, _P, _P, _P]),
+    "npfem_plan_create": (c_int32, [c_int32, _P, c_int32, POINTER(Material), c_double,
+                                    POINTER(SolverParams), POINTER(c_void_p)]),
+    "npfem_plan_destroy": (None, [c_void_p]),
+    "npfem_plan_masses": (c_int32, [c_void_p, c_int32, _P]),
+    "npfem_batch_create": (c_int32, [c_void_p, c_int64, _P, POINTER(c_void_p), POINTER(c_int64)]),
+    "npfem_batch_destroy": (None, [c_void_p]),
+    "npfem_step": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "npfem_eval": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P]),
+    "npfem_apply_inverse": (c_int32, [c_void_p, c_int32, c_int32, _P, _P, c_int32, _P, _P]),
+    "npfem_drag_forces": (c_int32, [c_void_p, _P, _P, _P, _P, _P, c_double, c_double, c_double,
+                                    c_double, _P, _P]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1903_06479_amd.build.build() "
+                               "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class NpfemError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        L = lib()
+        msg = L.npfem_last_error().decode()
+        super().__init__(f"{where}: {L.npfem_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != 0:
+        raise NpfemError(status, where)

@@ -1,0 +1,823 @@
+// Host side of the npFEM library: argument checking, FP64 rest data and constant
+// matrices, the batch schedule, and the C ABI declared in include/npfem.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "npfem.h"
+#include "npfem_internal.h"
+
+using namespace npfem;
+
+namespace {
+
+thread_local std::string g_err;
+
+npfem_status fail(npfem_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? NPFEM_E_OOM : NPFEM_E_HIP,                \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+  } while (0)
+
+struct V3 {
+  double x, y, z;
+};
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
+
+// Run f(i) for i in [0, n) on the host cores.
+template <typename F>
+void parallel_for(int n, F f) {
+  int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 64) nt = 1;
+  std::vector<std::thread> th;
+  for (int w = 0; w < nt; ++w)
+    th.emplace_back([&, w] {
+      for (int i = w; i < n; i += nt) f(i);
+    });
+  for (auto& t : th) t.join();
+}
+
+// In-place lower Cholesky of a dense SPD matrix (row-major); false if not SPD.
+bool cholesky(std::vector<double>& A, int n) {
+  for (int j = 0; j < n; ++j) {
+    double* rj = &A[(size_t)j * n];
+    double s = rj[j];
+    for (int k = 0; k < j; ++k) s -= rj[k] * rj[k];
+    if (!(s > 0.0) || !std::isfinite(s)) return false;
+    const double d = std::sqrt(s);
+    rj[j] = d;
+    const int rem = n - j - 1;
+    parallel_for(rem, [&](int q) {
+      const int i = j + 1 + q;
+      double* ri = &A[(size_t)i * n];
+      double t = ri[j];
+      for (int k = 0; k < j; ++k) t -= ri[k] * rj[k];
+      ri[j] = t / d;
+    });
+  }
+  return true;
+}
+
+// Inverse of an SPD matrix from its Cholesky factor L (lower, row-major):
+// A^-1 = L^-T L^-1.  W^T (row j = column j of L^-1) is built by forward substitution.
+std::vector<double> spd_inverse(const std::vector<double>& L, int n) {
+  std::vector<double> WT((size_t)n * n, 0.0);
+  parallel_for(n, [&](int j) {
+    double* w = &WT[(size_t)j * n];
+    w[j] = 1.0 / L[(size_t)j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      const double* li = &L[(size_t)i * n];
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s += li[k] * w[k];
+      w[i] = -s / li[i];
+    }
+  });
+  std::vector<double> inv((size_t)n * n, 0.0);
+  parallel_for(n, [&](int a) {
+    const double* wa = &WT[(size_t)a * n];
+    for (int b = a; b < n; ++b) {
+      const double* wb = &WT[(size_t)b * n];
+      double s = 0.0;
+      for (int k = b; k < n; ++k) s += wa[k] * wb[k];
+      inv[(size_t)a * n + b] = s;
+    }
+  });
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < a; ++b) inv[(size_t)a * n + b] = inv[(size_t)b * n + a];
+  return inv;
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+// Mesh
+// ---------------------------------------------------------------------------------
+struct npfem_mesh {
+  int n = 0, nt = 0, ne = 0;
+  std::vector<double> X;          // [n][3]
+  std::vector<int> tri;           // [nt][3]
+  std::vector<double> dminv;      // [nt][4]
+  std::vector<double> area;       // [nt]
+  std::vector<int> vc_ptr, vc_idx;
+  std::vector<int> nb_ptr, nb_idx;
+  std::vector<double> nb_w;       // (cot a + cot b) / 2
+  std::vector<double> vor_area, ell0, bary_area;
+  double V0 = 0.0, A0 = 0.0;
+};
+
+extern "C" {
+
+const char* npfem_status_string(npfem_status s) {
+  switch (s) {
+    case NPFEM_OK: return "ok";
+    case NPFEM_E_INVALID: return "invalid argument";
+    case NPFEM_E_MESH: return "invalid mesh";
+    case NPFEM_E_NOT_SPD: return "matrix not symmetric positive definite";
+    case NPFEM_E_HIP: return "HIP runtime error";
+    case NPFEM_E_OOM: return "out of memory";
+    case NPFEM_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* npfem_last_error(void) { return g_err.c_str(); }
+
+void npfem_material_default(npfem_material* m) {
+  if (!m) return;
+  m->B = 10.6;
+  m->C = 530.0;
+  m->D = 35.0;
+  m->k_bend = 0.2;
+  m->k_volume = 250.0;
+  m->beta = 0.01;
+  m->kappa = 0.6;
+  m->density = 1100.0;
+  m->k_mat = -1.0;
+}
+
+void npfem_solver_params_default(npfem_solver_params* p) {
+  if (!p) return;
+  p->precision = NPFEM_FP32;
+  p->lbfgs_m = 5;
+  p->max_iter = 200;
+  p->max_halvings = 30;
+  p->tol = 1e-6;
+  p->c1 = 1e-4;
+  p->noise_factor = 8.0;
+  p->cells_per_tile = 0;
+  p->grid_blocks = 0;
+}
+
+npfem_status npfem_mesh_create(int32_t n, const double* xyz, int32_t nt, const int32_t* tris,
+                               npfem_mesh** out) {
+  if (!out || !xyz || !tris) return fail(NPFEM_E_INVALID, "mesh_create: NULL pointer");
+  *out = nullptr;
+  if (n < 4 || nt < 4) return fail(NPFEM_E_MESH, "mesh_create: need at least 4 vertices and 4 triangles");
+  auto m = std::make_unique<npfem_mesh>();
+  m->n = n;
+  m->nt = nt;
+  m->X.assign(xyz, xyz + 3 * (size_t)n);
+  m->tri.assign(tris, tris + 3 * (size_t)nt);
+  for (double v : m->X)
+    if (!std::isfinite(v)) return fail(NPFEM_E_MESH, "mesh_create: non-finite vertex coordinate");
+  // closed, consistently oriented: every directed edge once, its reverse once
+  std::unordered_map<int64_t, int> dir;
+  dir.reserve(3 * (size_t)nt);
+  for (int t = 0; t < nt; ++t) {
+    const int* f = &m->tri[3 * t];
+    for (int k = 0; k < 3; ++k) {
+      if (f[k] < 0 || f[k] >= n) return fail(NPFEM_E_MESH, "mesh_create: vertex index out of range");
+    }
+    if (f[0] == f[1] || f[1] == f[2] || f[0] == f[2])
+      return fail(NPFEM_E_MESH, "mesh_create: triangle with a repeated vertex");
+    for (int k = 0; k < 3; ++k) {
+      const int64_t key = (int64_t)f[k] * n + f[(k + 1) % 3];
+      if (dir.count(key)) return fail(NPFEM_E_MESH, "mesh_create: directed edge used twice (non-manifold or inconsistent orientation)");
+      dir[key] = t;
+    }
+  }
+  for (const auto& kv : dir) {
+    const int64_t a = kv.first / n, b = kv.first % n;
+    if (!dir.count(b * n + a)) return fail(NPFEM_E_MESH, "mesh_create: open boundary edge");
+  }
+  m->ne = (int)(dir.size() / 2);
+  auto P = [&](int i) { return V3{m->X[3 * i], m->X[3 * i + 1], m->X[3 * i + 2]}; };
+
+  // per-triangle rest data in the triangle's own 2D frame, third vertex as reference
+  m->dminv.resize(4 * (size_t)nt);
+  m->area.resize(nt);
+  double vol6 = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    const V3 Xa = P(m->tri[3 * t]), Xb = P(m->tri[3 * t + 1]), Xc = P(m->tri[3 * t + 2]);
+    const V3 E1 = sub(Xa, Xc), E2 = sub(Xb, Xc);
+    const V3 nr = cross(E1, E2);
+    const double nn = norm(nr), l1 = norm(E1);
+    if (!(nn > 0.0) || !(l1 > 0.0)) return fail(NPFEM_E_MESH, "mesh_create: degenerate rest triangle");
+    const V3 e1 = {E1.x / l1, E1.y / l1, E1.z / l1};
+    const V3 nh = {nr.x / nn, nr.y / nn, nr.z / nn};
+    const V3 e2 = cross(nh, e1);
+    const double d00 = dot(e1, E1), d01 = dot(e1, E2), d10 = dot(e2, E1), d11 = dot(e2, E2);
+    const double det = d00 * d11 - d01 * d10;
+    m->dminv[4 * t + 0] = d11 / det;
+    m->dminv[4 * t + 1] = -d01 / det;
+    m->dminv[4 * t + 2] = -d10 / det;
+    m->dminv[4 * t + 3] = d00 / det;
+    m->area[t] = 0.5 * nn;
+    vol6 += dot(Xa, cross(Xb, Xc));
+  }
+  m->V0 = vol6 / 6.0;
+  if (!(m->V0 > 0.0)) return fail(NPFEM_E_MESH, "mesh_create: enclosed volume not positive (triangles must be counter-clockwise seen from outside)");
+  for (double a : m->area) m->A0 += a;
+
+  // cotangent weights omega_ij = (cot a + cot b)/2 and mixed Voronoi areas (Meyer et al.)
+  std::unordered_map<int64_t, double> omega;
+  m->vor_area.assign(n, 0.0);
+  m->bary_area.assign(n, 0.0);
+  for (int t = 0; t < nt; ++t) {
+    const int* f = &m->tri[3 * t];
+    V3 p[3] = {P(f[0]), P(f[1]), P(f[2])};
+    double ang[3], cot[3];
+    for (int k = 0; k < 3; ++k) {
+      const V3 u = sub(p[(k + 1) % 3], p[k]), v = sub(p[(k + 2) % 3], p[k]);
+      cot[k] = dot(u, v) / norm(cross(u, v));
+      ang[k] = std::atan2(norm(cross(u, v)), dot(u, v));
+    }
+    for (int k = 0; k < 3; ++k) {
+      const int i = f[(k + 1) % 3], j = f[(k + 2) % 3];   // edge opposite corner k
+      const int64_t key = (int64_t)std::min(i, j) * n + std::max(i, j);
+      omega[key] += 0.5 * cot[k];
+      m->bary_area[f[k]] += m->area[t] / 3.0;
+    }
+    const bool obtuse = ang[0] > M_PI / 2 || ang[1] > M_PI / 2 || ang[2] > M_PI / 2;
+    for (int k = 0; k < 3; ++k) {
+      const int j = (k + 1) % 3, l = (k + 2) % 3;
+      if (!obtuse) {
+        const V3 pj = sub(p[k], p[j]), pl = sub(p[k], p[l]);
+        m->vor_area[f[k]] += (dot(pj, pj) * cot[l] + dot(pl, pl) * cot[j]) / 8.0;
+      } else if (ang[k] > M_PI / 2) {
+        m->vor_area[f[k]] += m->area[t] / 2.0;
+      } else {
+        m->vor_area[f[k]] += m->area[t] / 4.0;
+      }
+    }
+  }
+  // neighbour lists (CSR) and |l0_i|
+  std::vector<std::vector<std::pair<int, double>>> nbs(n);
+  for (const auto& kv : omega) {
+    const int i = (int)(kv.first / n), j = (int)(kv.first % n);
+    nbs[i].push_back({j, kv.second});
+    nbs[j].push_back({i, kv.second});
+  }
+  m->nb_ptr.assign(n + 1, 0);
+  m->ell0.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    if (nbs[i].empty()) return fail(NPFEM_E_MESH, "mesh_create: unreferenced vertex");
+    std::sort(nbs[i].begin(), nbs[i].end());
+    m->nb_ptr[i + 1] = m->nb_ptr[i] + (int)nbs[i].size();
+    V3 l = {0, 0, 0};
+    for (auto& [j, w] : nbs[i]) {
+      m->nb_idx.push_back(j);
+      m->nb_w.push_back(w);
+      const V3 d = sub(P(j), P(i));
+      l.x += w * d.x;
+      l.y += w * d.y;
+      l.z += w * d.z;
+    }
+    m->ell0[i] = norm(l) / m->vor_area[i];
+  }
+  // vertex -> incident corners, in triangle order
+  std::vector<std::vector<int>> vc(n);
+  for (int t = 0; t < nt; ++t)
+    for (int k = 0; k < 3; ++k) vc[m->tri[3 * t + k]].push_back(3 * t + k);
+  m->vc_ptr.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    m->vc_ptr[i + 1] = m->vc_ptr[i] + (int)vc[i].size();
+    m->vc_idx.insert(m->vc_idx.end(), vc[i].begin(), vc[i].end());
+  }
+  *out = m.release();
+  return NPFEM_OK;
+}
+
+void npfem_mesh_destroy(npfem_mesh* m) { delete m; }
+
+npfem_status npfem_mesh_query(const npfem_mesh* m, int32_t* n, int32_t* nt, int32_t* ne, double* V0,
+                              double* A0) {
+  if (!m) return fail(NPFEM_E_INVALID, "mesh_query: NULL mesh");
+  if (n) *n = m->n;
+  if (nt) *nt = m->nt;
+  if (ne) *ne = m->ne;
+  if (V0) *V0 = m->V0;
+  if (A0) *A0 = m->A0;
+  return NPFEM_OK;
+}
+
+npfem_status npfem_mesh_rest_data(const npfem_mesh* m, double* vor_area, double* ell0, double* tri_area,
+                                  double* dminv) {
+  if (!m) return fail(NPFEM_E_INVALID, "mesh_rest_data: NULL mesh");
+  if (vor_area) std::copy(m->vor_area.begin(), m->vor_area.end(), vor_area);
+  if (ell0) std::copy(m->ell0.begin(), m->ell0.end(), ell0);
+  if (tri_area) std::copy(m->area.begin(), m->area.end(), tri_area);
+  if (dminv) std::copy(m->dminv.begin(), m->dminv.end(), dminv);
+  return NPFEM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------------
+namespace {
+
+struct DeviceBuffers {
+  std::vector<void*> ptrs;
+  ~DeviceBuffers() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  npfem_status upload(const T* src, size_t count, const T** out) {
+    void* p = nullptr;
+    HIP_TRY(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)));
+    ptrs.push_back(p);
+    if (count) HIP_TRY(hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice));
+    *out = static_cast<const T*>(p);
+    return NPFEM_OK;
+  }
+  npfem_status alloc(size_t bytes, void** out) {
+    void* p = nullptr;
+    HIP_TRY(hipMalloc(&p, std::max<size_t>(bytes, 16)));
+    ptrs.push_back(p);
+    *out = p;
+    return NPFEM_OK;
+  }
+};
+
+struct MeshPlan {
+  const npfem_mesh* mesh;
+  int n_pad, chunk;
+  std::vector<double> mass;
+  double floor_force;
+  MeshDev<float> dev32;
+  MeshDev<double> dev64;
+};
+
+template <typename Real>
+std::vector<Real> pad_matrix(const std::vector<double>& A, int n, int np, double scale) {
+  std::vector<Real> P((size_t)np * np, Real(0));
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) P[(size_t)i * np + j] = Real(scale * A[(size_t)i * n + j]);
+  return P;
+}
+
+}  // namespace
+
+struct npfem_plan {
+  int device = 0, precision = NPFEM_FP32, cu_count = 0;
+  double dt = 0.0;
+  npfem_material mat{};
+  npfem_solver_params prm{};
+  std::vector<MeshPlan> meshes;
+  DeviceBuffers buf;
+  const void* d_meshdev = nullptr;
+};
+
+namespace {
+
+template <typename Real>
+npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>& hinv,
+                         const std::vector<double>& minv_h2, MeshDev<Real>& d) {
+  const npfem_mesh* m = mp.mesh;
+  const int n = m->n, np = mp.n_pad;
+  auto conv = [](const std::vector<double>& v) { return std::vector<Real>(v.begin(), v.end()); };
+  d.n = n;
+  d.nt = m->nt;
+  d.n_pad = np;
+  d.chunk = mp.chunk;
+  npfem_status s;
+  if ((s = p->buf.upload(m->tri.data(), m->tri.size(), &d.tri))) return s;
+  auto w = conv(m->nb_w), va = conv(m->vor_area), e0 = conv(m->ell0), ms = conv(mp.mass);
+  std::vector<double> i4(m->nt);
+  for (int t = 0; t < m->nt; ++t) i4[t] = 0.25 / (m->area[t] * m->area[t]);
+  if ((s = p->buf.upload(m->dminv.data(), m->dminv.size(), &d.dminv))) return s;
+  if ((s = p->buf.upload(m->area.data(), m->area.size(), &d.area))) return s;
+  if ((s = p->buf.upload(i4.data(), i4.size(), &d.inv4a2))) return s;
+  if ((s = p->buf.upload(m->vc_ptr.data(), m->vc_ptr.size(), &d.vc_ptr))) return s;
+  if ((s = p->buf.upload(m->vc_idx.data(), m->vc_idx.size(), &d.vc_idx))) return s;
+  if ((s = p->buf.upload(m->nb_ptr.data(), m->nb_ptr.size(), &d.nb_ptr))) return s;
+  if ((s = p->buf.upload(m->nb_idx.data(), m->nb_idx.size(), &d.nb_idx))) return s;
+  if ((s = p->buf.upload(w.data(), w.size(), &d.nb_w))) return s;
+  if ((s = p->buf.upload(va.data(), va.size(), &d.vor_area))) return s;
+  if ((s = p->buf.upload(e0.data(), e0.size(), &d.ell0))) return s;
+  if ((s = p->buf.upload(ms.data(), ms.size(), &d.mass))) return s;
+  auto H = pad_matrix<Real>(hinv, n, np, 1.0);
+  auto Mi = pad_matrix<Real>(minv_h2, n, np, 1.0);
+  if ((s = p->buf.upload(H.data(), H.size(), &d.hinv))) return s;
+  if ((s = p->buf.upload(Mi.data(), Mi.size(), &d.minv))) return s;
+  d.V0 = m->V0;
+  d.floor_force = mp.floor_force;
+  return NPFEM_OK;
+}
+
+// Largest triangle chunk for which the step's LDS fits the budget.
+template <typename Real>
+int choose_chunk(int np, int nt, size_t budget) {
+  if (lds_bytes<Real>(np, nt) <= budget) return nt;
+  int lo = 0;
+  for (int ch = nt; ch >= 64; ch -= 64)
+    if (lds_bytes<Real>(np, ch) <= budget) { lo = ch; break; }
+  return lo;
+}
+
+}  // namespace
+
+extern "C" {
+
+npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, int32_t n_meshes,
+                               const npfem_material* mat, double dt, const npfem_solver_params* prm,
+                               npfem_plan** out) {
+  if (!out || !meshes || !mat || !prm) return fail(NPFEM_E_INVALID, "plan_create: NULL pointer");
+  *out = nullptr;
+  if (n_meshes < 1) return fail(NPFEM_E_INVALID, "plan_create: need at least one mesh");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NPFEM_E_INVALID, "plan_create: dt must be positive");
+  if (prm->precision != NPFEM_FP32 && prm->precision != NPFEM_FP64)
+    return fail(NPFEM_E_INVALID, "plan_create: unknown precision");
+  if (prm->lbfgs_m < 0 || prm->lbfgs_m > kMaxHistory)
+    return fail(NPFEM_E_INVALID, "plan_create: lbfgs_m must be in [0, 8]");
+  if (prm->max_iter < 1 || prm->max_halvings < 0 || !(prm->tol >= 0.0) || !(prm->c1 >= 0.0))
+    return fail(NPFEM_E_INVALID, "plan_create: bad solver controls");
+  if (prm->cells_per_tile < 0 || prm->cells_per_tile > kMaxTile)
+    return fail(NPFEM_E_INVALID, "plan_create: cells_per_tile must be in [0, 21]");
+  const double mats[] = {mat->B, mat->C, mat->D, mat->k_bend, mat->k_volume, mat->beta, mat->density};
+  for (double v : mats)
+    if (!(v >= 0.0) || !std::isfinite(v)) return fail(NPFEM_E_INVALID, "plan_create: material constants must be finite and >= 0");
+  if (!(mat->density > 0.0)) return fail(NPFEM_E_INVALID, "plan_create: density must be positive");
+  if (!(mat->kappa >= 0.0 && mat->kappa <= 1.0)) return fail(NPFEM_E_INVALID, "plan_create: kappa must be in [0, 1]");
+  for (int i = 0; i < n_meshes; ++i)
+    if (!meshes[i]) return fail(NPFEM_E_INVALID, "plan_create: NULL mesh");
+
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(NPFEM_E_INVALID, "plan_create: no such HIP device");
+  HIP_TRY(hipSetDevice(device));
+  auto p = std::make_unique<npfem_plan>();
+  p->device = device;
+  p->precision = prm->precision;
+  p->dt = dt;
+  p->mat = *mat;
+  p->prm = *prm;
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  p->cu_count = prop.multiProcessorCount;
+  const double h = dt, kmat = mat->k_mat < 0 ? mat->B : mat->k_mat;
+  const bool fp64 = prm->precision == NPFEM_FP64;
+  const size_t lds_cap = 160 * 1024 - 1024;
+  p->meshes.resize(n_meshes);
+  for (int mi = 0; mi < n_meshes; ++mi) {
+    const npfem_mesh* m = meshes[mi];
+    MeshPlan& mp = p->meshes[mi];
+    mp.mesh = m;
+    const int n = m->n;
+    mp.n_pad = round_up(n, 16);
+    // two workgroups per CU when the whole triangle list fits in half the LDS
+    const size_t half = 80 * 1024 - 512;
+    mp.chunk = fp64 ? choose_chunk<double>(mp.n_pad, m->nt, half) : choose_chunk<float>(mp.n_pad, m->nt, half);
+    if (mp.chunk < std::min(m->nt, 256))
+      mp.chunk = fp64 ? choose_chunk<double>(mp.n_pad, m->nt, lds_cap) : choose_chunk<float>(mp.n_pad, m->nt, lds_cap);
+    if (mp.chunk <= 0)
+      return fail(NPFEM_E_UNSUPPORTED, "plan_create: mesh too large for the LDS in this precision");
+    // lumped mass by barycentric area (section 2.1)
+    double bsum = 0.0;
+    for (double a : m->bary_area) bsum += a;
+    mp.mass.resize(n);
+    for (int i = 0; i < n; ++i) mp.mass[i] = mat->density * m->V0 * m->bary_area[i] / bsum;
+    mp.floor_force = mat->B * std::sqrt(m->A0);
+    // L' (area + bending PD), K_mat (material term of H~), dense n x n per coordinate
+    std::vector<double> Lp((size_t)n * n, 0.0), Km((size_t)n * n, 0.0);
+    for (int t = 0; t < m->nt; ++t) {
+      const int* f = &m->tri[3 * t];
+      const double* d = &m->dminv[4 * t];
+      const double g[3][2] = {{d[0], d[1]}, {d[2], d[3]}, {-d[0] - d[2], -d[1] - d[3]}};
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          const double gg = g[a][0] * g[b][0] + g[a][1] * g[b][1];
+          Lp[(size_t)f[a] * n + f[b]] += m->area[t] * mat->C * gg;
+          Km[(size_t)f[a] * n + f[b]] += m->area[t] * kmat * gg;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+      // bending row G_i: omega_ij / A_i at j, -sum at i; weight k_b A_i
+      std::vector<std::pair<int, double>> row;
+      double diag = 0.0;
+      for (int q = m->nb_ptr[i]; q < m->nb_ptr[i + 1]; ++q) {
+        const double c = m->nb_w[q] / m->vor_area[i];
+        row.push_back({m->nb_idx[q], c});
+        diag -= c;
+      }
+      row.push_back({i, diag});
+      const double w = mat->k_bend * m->vor_area[i];
+      for (auto& [a, ca] : row)
+        for (auto& [b, cb] : row) Lp[(size_t)a * n + b] += w * ca * cb;
+    }
+    // M~ = M + beta h^2 L';  H~ = M~/h^2 + L' + k_volume I + K_mat
+    std::vector<double> Mt((size_t)n * n), Ht((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const size_t k = (size_t)i * n + j;
+        Mt[k] = mat->beta * h * h * Lp[k] + (i == j ? mp.mass[i] : 0.0);
+        Ht[k] = Mt[k] / (h * h) + Lp[k] + Km[k] + (i == j ? mat->k_volume : 0.0);
+      }
+    if (!cholesky(Mt, n)) return fail(NPFEM_E_NOT_SPD, "plan_create: M~ is not positive definite");
+    if (!cholesky(Ht, n)) return fail(NPFEM_E_NOT_SPD, "plan_create: H~ is not positive definite");
+    const std::vector<double> Hinv = spd_inverse(Ht, n);
+    std::vector<double> Minv = spd_inverse(Mt, n);
+    for (double& v : Minv) v *= h * h;
+    npfem_status s = fp64 ? upload_mesh<double>(p.get(), mp, Hinv, Minv, mp.dev64)
+                          : upload_mesh<float>(p.get(), mp, Hinv, Minv, mp.dev32);
+    if (s) return s;
+  }
+  // device array of mesh descriptors
+  npfem_status s;
+  if (fp64) {
+    std::vector<MeshDev<double>> v;
+    for (auto& mp : p->meshes) v.push_back(mp.dev64);
+    const MeshDev<double>* d;
+    if ((s = p->buf.upload(v.data(), v.size(), &d))) return s;
+    p->d_meshdev = d;
+  } else {
+    std::vector<MeshDev<float>> v;
+    for (auto& mp : p->meshes) v.push_back(mp.dev32);
+    const MeshDev<float>* d;
+    if ((s = p->buf.upload(v.data(), v.size(), &d))) return s;
+    p->d_meshdev = d;
+  }
+  *out = p.release();
+  return NPFEM_OK;
+}
+
+void npfem_plan_destroy(npfem_plan* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  delete p;
+}
+
+npfem_status npfem_plan_masses(const npfem_plan* p, int32_t mi, double* out) {
+  if (!p || !out) return fail(NPFEM_E_INVALID, "plan_masses: NULL pointer");
+  if (mi < 0 || mi >= (int)p->meshes.size()) return fail(NPFEM_E_INVALID, "plan_masses: bad mesh index");
+  std::copy(p->meshes[mi].mass.begin(), p->meshes[mi].mass.end(), out);
+  return NPFEM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Batch
+// ---------------------------------------------------------------------------------
+struct npfem_batch {
+  npfem_plan* plan = nullptr;
+  int64_t n_cells = 0, n_vert = 0;
+  int T = 0, n_tiles = 0, grid = 0, n_pad_max = 0, n_vec = 0;
+  size_t lds = 0;
+  int64_t slot_stride = 0;
+  DeviceBuffers buf;
+  const TileDesc* tiles = nullptr;
+  const int* tile_cells = nullptr;
+  const int64_t* cell_voff = nullptr;
+  const int* cell_mesh = nullptr;
+  const int* mesh_n = nullptr;
+  int* counter = nullptr;
+  void* work = nullptr;
+  CellState* cstate = nullptr;
+  void* eval_scratch = nullptr;
+};
+
+namespace {
+
+template <typename Real>
+StepArgs<Real> make_args(npfem_batch* b) {
+  npfem_plan* p = b->plan;
+  StepArgs<Real> a{};
+  a.meshes = static_cast<const MeshDev<Real>*>(p->d_meshdev);
+  a.mat = {p->mat.B, p->mat.C, p->mat.D, p->mat.k_bend, p->mat.k_volume, p->mat.beta, p->mat.kappa};
+  const double eps = std::is_same<Real, float>::value ? 1.1920928955078125e-07 : 2.220446049250313e-16;
+  a.sol = {p->dt, p->prm.tol, p->prm.c1, p->prm.noise_factor * eps, p->prm.lbfgs_m, p->prm.max_iter,
+           p->prm.max_halvings};
+  a.tiles = b->tiles;
+  a.tile_cells = b->tile_cells;
+  a.cell_voff = b->cell_voff;
+  a.cell_mesh = b->cell_mesh;
+  a.n_tiles = b->n_tiles;
+  a.tile_cells_max = b->T;
+  a.tile_counter = b->counter;
+  a.n_vec_slot = b->n_vec;
+  a.slot_stride = b->slot_stride;
+  a.work = static_cast<Real*>(b->work);
+  a.cstate = b->cstate;
+  a.n_pad_max = b->n_pad_max;
+  return a;
+}
+
+template <typename Real>
+npfem_status batch_setup(npfem_batch* b) {
+  npfem_plan* p = b->plan;
+  size_t lds = 0;
+  for (auto& mp : p->meshes) lds = std::max(lds, lds_bytes<Real>(mp.n_pad, mp.chunk));
+  b->lds = lds;
+  HIP_TRY(set_lds_limit<Real>(lds));
+  int per_cu = 0;
+  HIP_TRY(occupancy<Real>(&per_cu, lds));
+  if (per_cu < 1) return fail(NPFEM_E_UNSUPPORTED, "batch_create: step kernel does not fit on a compute unit");
+  const int slots = p->cu_count * per_cu;
+  b->grid = p->prm.grid_blocks > 0 ? p->prm.grid_blocks : slots;
+  b->grid = std::max(1, std::min(b->grid, b->n_tiles));
+  b->n_vec = 6 + 2 * p->prm.lbfgs_m;
+  b->slot_stride = (int64_t)b->n_vec * b->T * 3 * b->n_pad_max;
+  npfem_status s;
+  const size_t wbytes = (size_t)b->grid * b->slot_stride * sizeof(Real);
+  if ((s = b->buf.alloc(wbytes, &b->work))) return s;
+  HIP_TRY(hipMemset(b->work, 0, wbytes));
+  void* cs;
+  if ((s = b->buf.alloc((size_t)b->grid * b->T * sizeof(CellState), &cs))) return s;
+  b->cstate = static_cast<CellState*>(cs);
+  void* c;
+  if ((s = b->buf.alloc(sizeof(int), &c))) return s;
+  b->counter = static_cast<int*>(c);
+  return NPFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+npfem_status npfem_batch_create(npfem_plan* p, int64_t n_cells, const int32_t* cell_mesh,
+                                npfem_batch** out, int64_t* n_vert_out) {
+  if (!p || !out || (!cell_mesh && n_cells > 0)) return fail(NPFEM_E_INVALID, "batch_create: NULL pointer");
+  *out = nullptr;
+  if (n_cells < 1 || n_cells > (1ll << 30)) return fail(NPFEM_E_INVALID, "batch_create: n_cells out of range");
+  HIP_TRY(hipSetDevice(p->device));
+  auto b = std::make_unique<npfem_batch>();
+  b->plan = p;
+  b->n_cells = n_cells;
+  const int nm = (int)p->meshes.size();
+  std::vector<int64_t> voff(n_cells);
+  std::vector<std::vector<int>> by_mesh(nm);
+  int64_t v = 0;
+  for (int64_t c = 0; c < n_cells; ++c) {
+    const int mi = cell_mesh[c];
+    if (mi < 0 || mi >= nm) return fail(NPFEM_E_INVALID, "batch_create: mesh index out of range");
+    voff[c] = v;
+    v += p->meshes[mi].mesh->n;
+    by_mesh[mi].push_back((int)c);
+  }
+  b->n_vert = v;
+  // cells per tile: as many as keep every compute unit busy (the matrix product runs
+  // 3T rows; T = 5, 10, 16 fill 16, 32, 48 rows)
+  int T = p->prm.cells_per_tile;
+  if (T == 0) {
+    const int64_t want = 2 * (int64_t)p->cu_count;
+    T = n_cells / 16 >= want ? 16 : (n_cells / 10 >= want ? 10 : 5);
+  }
+  b->T = T;
+  // tiles of one mesh type, largest meshes first (cost grows like n^2)
+  std::vector<int> order(nm);
+  for (int i = 0; i < nm; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int c) { return p->meshes[a].mesh->n > p->meshes[c].mesh->n; });
+  std::vector<TileDesc> tiles;
+  std::vector<int> tcells;
+  for (int mi : order) {
+    const auto& cl = by_mesh[mi];
+    for (size_t s0 = 0; s0 < cl.size(); s0 += T) {
+      TileDesc td;
+      td.mesh = mi;
+      td.count = (int)std::min<size_t>(T, cl.size() - s0);
+      td.first = (int)tcells.size();
+      td.pad = 0;
+      tcells.insert(tcells.end(), cl.begin() + s0, cl.begin() + s0 + td.count);
+      tiles.push_back(td);
+    }
+  }
+  b->n_tiles = (int)tiles.size();
+  b->n_pad_max = 0;
+  std::vector<int> mesh_n(nm);
+  for (int i = 0; i < nm; ++i) {
+    mesh_n[i] = p->meshes[i].mesh->n;
+    if (!by_mesh[i].empty()) b->n_pad_max = std::max(b->n_pad_max, p->meshes[i].n_pad);
+  }
+  npfem_status s;
+  std::vector<int> cm(cell_mesh, cell_mesh + n_cells);
+  if ((s = b->buf.upload(tiles.data(), tiles.size(), &b->tiles))) return s;
+  if ((s = b->buf.upload(tcells.data(), tcells.size(), &b->tile_cells))) return s;
+  if ((s = b->buf.upload(voff.data(), voff.size(), &b->cell_voff))) return s;
+  if ((s = b->buf.upload(cm.data(), cm.size(), &b->cell_mesh))) return s;
+  if ((s = b->buf.upload(mesh_n.data(), mesh_n.size(), &b->mesh_n))) return s;
+  s = p->precision == NPFEM_FP64 ? batch_setup<double>(b.get()) : batch_setup<float>(b.get());
+  if (s) return s;
+  if (n_vert_out) *n_vert_out = v;
+  *out = b.release();
+  return NPFEM_OK;
+}
+
+void npfem_batch_destroy(npfem_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->plan->device);
+  delete b;
+}
+
+npfem_status npfem_step(npfem_batch* b, const void* x, const void* v, const void* f, void* x_out,
+                        void* v_out, const void* u_guess, npfem_cell_stats* stats, void* stream) {
+  if (!b || !x || !v || !f || !x_out || !v_out) return fail(NPFEM_E_INVALID, "step: NULL pointer");
+  HIP_TRY(hipSetDevice(b->plan->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (b->plan->precision == NPFEM_FP64) {
+    auto a = make_args<double>(b);
+    a.x = static_cast<const double*>(x);
+    a.v = static_cast<const double*>(v);
+    a.f = static_cast<const double*>(f);
+    a.u_guess = static_cast<const double*>(u_guess);
+    a.x_out = static_cast<double*>(x_out);
+    a.v_out = static_cast<double*>(v_out);
+    a.stats = stats;
+    HIP_TRY(launch_step<double>(a, b->grid, b->lds, s, b->counter));
+  } else {
+    auto a = make_args<float>(b);
+    a.x = static_cast<const float*>(x);
+    a.v = static_cast<const float*>(v);
+    a.f = static_cast<const float*>(f);
+    a.u_guess = static_cast<const float*>(u_guess);
+    a.x_out = static_cast<float*>(x_out);
+    a.v_out = static_cast<float*>(v_out);
+    a.stats = stats;
+    HIP_TRY(launch_step<float>(a, b->grid, b->lds, s, b->counter));
+  }
+  return NPFEM_OK;
+}
+
+npfem_status npfem_eval(npfem_batch* b, const void* x, const void* v, const void* f, const void* u,
+                        void* grad, double* terms, void* stream) {
+  if (!b || !x || !v || !f || !u || !grad || !terms) return fail(NPFEM_E_INVALID, "eval: NULL pointer");
+  HIP_TRY(hipSetDevice(b->plan->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool fp64 = b->plan->precision == NPFEM_FP64;
+  const size_t rs = fp64 ? 8 : 4;
+  if (!b->eval_scratch) {
+    npfem_status st = b->buf.alloc((size_t)b->n_cells * 6 * b->n_pad_max * rs, &b->eval_scratch);
+    if (st) return st;
+  }
+  if (fp64) {
+    auto a = make_args<double>(b);
+    a.x = static_cast<const double*>(x);
+    a.v = static_cast<const double*>(v);
+    a.f = static_cast<const double*>(f);
+    a.work = static_cast<double*>(b->eval_scratch);
+    HIP_TRY(launch_eval<double>(a, (int)b->n_cells, static_cast<const double*>(u), static_cast<double*>(grad),
+                                terms, b->lds, s));
+  } else {
+    auto a = make_args<float>(b);
+    a.x = static_cast<const float*>(x);
+    a.v = static_cast<const float*>(v);
+    a.f = static_cast<const float*>(f);
+    a.work = static_cast<float*>(b->eval_scratch);
+    HIP_TRY(launch_eval<float>(a, (int)b->n_cells, static_cast<const float*>(u), static_cast<float*>(grad),
+                               terms, b->lds, s));
+  }
+  return NPFEM_OK;
+}
+
+npfem_status npfem_apply_inverse(npfem_plan* p, int32_t mi, int32_t which, const void* in, void* out,
+                                 int32_t rows, int32_t* n_pad_out, void* stream) {
+  if (!p) return fail(NPFEM_E_INVALID, "apply_inverse: NULL plan");
+  if (mi < 0 || mi >= (int)p->meshes.size()) return fail(NPFEM_E_INVALID, "apply_inverse: bad mesh index");
+  if (which != 0 && which != 1) return fail(NPFEM_E_INVALID, "apply_inverse: which must be 0 or 1");
+  const MeshPlan& mp = p->meshes[mi];
+  if (n_pad_out) *n_pad_out = mp.n_pad;
+  if (rows == 0) return NPFEM_OK;
+  if (!in || !out || rows < 0) return fail(NPFEM_E_INVALID, "apply_inverse: bad buffers or rows");
+  HIP_TRY(hipSetDevice(p->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->precision == NPFEM_FP64) {
+    const double* A = which == 0 ? mp.dev64.hinv : mp.dev64.minv;
+    HIP_TRY(launch_apply_inverse<double>(A, mp.n_pad, static_cast<const double*>(in), static_cast<double*>(out),
+                                         rows, s));
+  } else {
+    const float* A = which == 0 ? mp.dev32.hinv : mp.dev32.minv;
+    HIP_TRY(launch_apply_inverse<float>(A, mp.n_pad, static_cast<const float*>(in), static_cast<float*>(out),
+                                        rows, s));
+  }
+  return NPFEM_OK;
+}
+
+npfem_status npfem_drag_forces(npfem_batch* b, const void* x, const void* v, const double* zeta,
+                               const double* rate, const double* origin, double umax, double radius,
+                               double ay, double az, void* f, void* stream) {
+  if (!b || !x || !v || !zeta || !rate || !origin || !f) return fail(NPFEM_E_INVALID, "drag_forces: NULL pointer");
+  HIP_TRY(hipSetDevice(b->plan->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (b->plan->precision == NPFEM_FP64)
+    HIP_TRY(launch_drag<double>(static_cast<const double*>(x), static_cast<const double*>(v), b->cell_voff,
+                                b->cell_mesh, b->mesh_n, (int)b->n_cells, zeta, rate, origin, umax, radius,
+                                ay, az, static_cast<double*>(f), s));
+  else
+    HIP_TRY(launch_drag<float>(static_cast<const float*>(x), static_cast<const float*>(v), b->cell_voff,
+                               b->cell_mesh, b->mesh_n, (int)b->n_cells, zeta, rate, origin, umax, radius, ay,
+                               az, static_cast<float*>(f), s));
+  return NPFEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Internal structures shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <cstdint>
+
+#include "npfem.h"
+
+namespace npfem {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kMaxHistory = 8;     // L-BFGS pairs
+constexpr int kMaxTile = 21;       // cells per tile: 3*21 = 63 rows <= 4 MFMA row blocks
+constexpr int kTerms = 8;          // objective terms reported by npfem_eval
+
+// Rest data of one mesh type on the device (precision Real).
+template <typename Real>
+struct MeshDev {
+  int n, nt, n_pad;            // vertices, triangles, n rounded up to 16
+  int chunk;                   // triangles per LDS corner chunk
+  const int* tri;              // [nt][3]
+  const double* dminv;         // [nt][4] D_m^-1 row-major (FP64 in every precision: the
+  const double* area;          // [nt] rest area            triangle geometry is formed in FP64)
+  const double* inv4a2;        // [nt] 1 / (2 A_t)^2
+  const int* vc_ptr;           // [n+1] vertex -> incident corners (tri*3 + k), by triangle
+  const int* vc_idx;
+  const int* nb_ptr;           // [n+1] vertex -> neighbours
+  const int* nb_idx;
+  const Real* nb_w;            // cotangent weight (cot a + cot b)/2 of each neighbour edge
+  const Real* vor_area;        // [n] mixed Voronoi area A_i
+  const Real* ell0;            // [n] |l0_i|
+  const Real* mass;            // [n]
+  const Real* hinv;            // [n_pad][n_pad] H~^-1
+  const Real* minv;            // [n_pad][n_pad] h^2 M~^-1
+  double V0;                   // rest volume
+  double floor_force;          // B sqrt(A0): force floor of the residual
+};
+
+struct MaterialDev {
+  double B, C, D, k_bend, k_volume, beta, kappa;
+};
+
+struct SolverDev {
+  double h, tol, c1, noise;    // noise = noise_factor * machine epsilon
+  int m, max_iter, max_halvings;
+};
+
+// Per-cell scalar state of the step, kept in the workspace between kernel phases.
+struct CellState {
+  double E;                    // objective at the current iterate
+  double noise;                // sum of |terms| of E (line-search rounding scale)
+  double Gn;                   // |grad V(x_n)|^2
+  double resid;
+  double rho[kMaxHistory];
+  double alpha[kMaxHistory];
+  int hist_n, hist_head, iter, evals, status, active, retry, halvings;
+};
+
+struct TileDesc {
+  int mesh;                    // mesh type
+  int count;                   // cells in this tile (<= cells_per_tile)
+  int first;                   // index into the tile_cells list
+  int pad;
+};
+
+template <typename Real>
+struct StepArgs {
+  const MeshDev<Real>* meshes; // [n_meshes] (device)
+  MaterialDev mat;
+  SolverDev sol;
+  const TileDesc* tiles;       // [n_tiles]
+  const int* tile_cells;       // cell ids, tiles[t].first .. first + count
+  const int64_t* cell_voff;    // [n_cells] first vertex of each cell
+  const int* cell_mesh;        // [n_cells]
+  int n_tiles, tile_cells_max; // cells_per_tile
+  int* tile_counter;           // work queue head
+  int n_vec_slot;              // vectors per workspace slot
+  int64_t slot_stride;         // Reals per slot
+  Real* work;                  // [slots][n_vec_slot][T][3][n_pad_max]
+  CellState* cstate;           // [slots][T]
+  int n_pad_max;
+  const Real* x;               // [V][3]
+  const Real* v;
+  const Real* f;
+  const Real* u_guess;         // nullable
+  Real* x_out;
+  Real* v_out;
+  npfem_cell_stats* stats;     // nullable
+};
+
+// Launch wrappers (npfem_kernels.hip).
+template <typename Real>
+hipError_t launch_step(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s, int* counter);
+template <typename Real>
+hipError_t launch_eval(const StepArgs<Real>& a, int n_cells, const Real* u, Real* grad,
+                       double* terms, size_t lds, hipStream_t s);
+template <typename Real>
+hipError_t launch_apply_inverse(const Real* A, int n_pad, const Real* in, Real* out, int rows,
+                                hipStream_t s);
+template <typename Real>
+hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, const int* cell_mesh,
+                       const int* mesh_n, int n_cells, const double* zeta, const double* rate,
+                       const double* origin, double umax, double radius, double ay, double az,
+                       Real* f, hipStream_t s);
+template <typename Real>
+size_t lds_bytes(int n_pad, int chunk);
+template <typename Real>
+hipError_t set_lds_limit(size_t bytes);
+template <typename Real>
+hipError_t occupancy(int* blocks_per_cu, size_t lds);
+
+}  // namespace npfem

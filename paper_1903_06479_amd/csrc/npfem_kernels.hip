@@ -1,0 +1,960 @@
+// gfx950 kernels of the batched npFEM step.
+//
+// One workgroup (4 wave64) owns a tile of up to kMaxTile cells of one mesh type and
+// carries them through a whole time step (Algorithm 1 of the paper): first guess,
+// quasi-Newton iterations with line search, velocity update and dissipation.  Cells
+// are worked on one at a time by the whole workgroup, with the cell's rest positions
+// and trial displacement staged in LDS; the one operation that couples cells, the
+// product with the shared dense inverse H~^-1 (section 2.1.1), is done for the whole
+// tile at once on the matrix cores.  Workgroups are persistent and pull tiles from a
+// queue, so one launch covers an uneven batch.
+//
+// Per-cell vectors in the workspace are structure-of-arrays [3][n_pad] so that the
+// tile's vectors form the row-major (3T x n_pad) operand of the MFMA product.
+
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "npfem_internal.h"
+
+namespace npfem {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename Real> struct Eps;
+template <> struct Eps<float> { static constexpr double v = 1.1920928955078125e-07; };
+template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
+
+// LDS: [red: 4 waves x 16 doubles][ints: 32][xn 3*np][ut 3*np][work max(3*np, 9*chunk)]
+constexpr int kRedDoubles = 64;
+constexpr int kLdsHeader = kRedDoubles * 8 + 32 * 4;
+
+__device__ inline int tid() { return threadIdx.x; }
+
+// Sum N doubles over the workgroup; fixed order, so deterministic.
+template <int N>
+__device__ inline void block_sum(double (&v)[N], double* red) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double x = v[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[i] = x;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) red[wave * 16 + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = (red[i] + red[16 + i]) + (red[32 + i] + red[48 + i]);
+}
+
+template <typename Real>
+__device__ inline double dot_vec(const Real* a, const Real* b, int len, double* red) {
+  double s[1] = {0.0};
+  for (int e = tid(); e < len; e += kBlock) s[0] += (double)a[e] * (double)b[e];
+  block_sum<1>(s, red);
+  return s[0];
+}
+
+// ---------------------------------------------------------------------------------
+// LDS staging
+// ---------------------------------------------------------------------------------
+
+// x_n of one cell: global AoS [n][3] -> LDS SoA [3][np] (padding zero).
+template <typename Real>
+__device__ inline void stage_aos(Real* dst, const Real* src, int n, int np) {
+  for (int e = tid(); e < 3 * np; e += kBlock) {
+    const int c = e / np, i = e - c * np;
+    dst[e] = i < n ? src[3 * i + c] : Real(0);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Volume normaliser |grad V(x_n)|^2, grad V_k = nbar_k / 3 (section 2.1.2)
+// ---------------------------------------------------------------------------------
+template <typename Real>
+__device__ double volume_normaliser(const MeshDev<Real>& M, const Real* xn, Real* acc, Real* work,
+                                    double* red) {
+  const int n = M.n, np = M.n_pad, nt = M.nt, ch = M.chunk;
+  for (int e = tid(); e < 3 * np; e += kBlock) acc[e] = Real(0);
+  for (int t0 = 0; t0 < nt; t0 += ch) {
+    __syncthreads();
+    const int tn = min(ch, nt - t0);
+    for (int tt = tid(); tt < tn; tt += kBlock) {
+      const int t = t0 + tt;
+      const int a = M.tri[3 * t], b = M.tri[3 * t + 1], c = M.tri[3 * t + 2];
+      const Real e1x = xn[a] - xn[c], e1y = xn[np + a] - xn[np + c], e1z = xn[2 * np + a] - xn[2 * np + c];
+      const Real e2x = xn[b] - xn[c], e2y = xn[np + b] - xn[np + c], e2z = xn[2 * np + b] - xn[2 * np + c];
+      work[tt] = (e1y * e2z - e1z * e2y) / Real(6);
+      work[ch + tt] = (e1z * e2x - e1x * e2z) / Real(6);
+      work[2 * ch + tt] = (e1x * e2y - e1y * e2x) / Real(6);
+    }
+    __syncthreads();
+    for (int i = tid(); i < n; i += kBlock) {
+      Real gx = 0, gy = 0, gz = 0;
+      for (int q = M.vc_ptr[i]; q < M.vc_ptr[i + 1]; ++q) {
+        const int t = M.vc_idx[q] / 3 - t0;
+        if (t >= 0 && t < tn) {
+          gx += work[t];
+          gy += work[ch + t];
+          gz += work[2 * ch + t];
+        }
+      }
+      acc[i] += gx;
+      acc[np + i] += gy;
+      acc[2 * np + i] += gz;
+    }
+  }
+  __syncthreads();
+  double s[1] = {0.0};
+  for (int i = tid(); i < n; i += kBlock)
+    s[0] += (double)acc[i] * acc[i] + (double)acc[np + i] * acc[np + i] + (double)acc[2 * np + i] * acc[2 * np + i];
+  block_sum<1>(s, red);
+  return s[0];
+}
+
+// ---------------------------------------------------------------------------------
+// Objective and gradient at x = x_n + u (eq. GeneralizedObjectiveFunctionDerivative)
+// ---------------------------------------------------------------------------------
+struct EvalResult {
+  double E, noise, resid, vol;
+  double terms[6];   // inertial, area, Skalak, bending(+Rayleigh), volume, triangle Rayleigh
+};
+
+// SL(2) projection of the singular values (section 2.1.2): t = 1 + tau, the largest
+// root of t^4 - s1 t^3 + s2 t - 1, written in deviations s_i = 1 + a_i so that small
+// strains lose no digits:  f(tau) = (1+tau)^3 (tau - a1) + tau (1 + a2) + a2.
+// f is convex for t >= s1/2 and f(s1/2) <= 0, so Newton from any start right of the
+// root decreases monotonically onto it.
+template <typename Real>
+__device__ inline Real sl2_tau(Real a1, Real a2, Real sig1, Real J) {
+  Real tau;
+  if (J >= Real(1)) {
+    tau = a1;                                             // f(s1) = J - 1 >= 0
+  } else {
+    const Real s3 = sig1 * sig1 * sig1;
+    tau = a1 + fmin((Real(1) - J) / fmax(s3, Real(1e-30)), Real(1));
+  }
+  const Real tol = Real(Eps<Real>::v) * Real(4);
+  for (int it = 0; it < 60; ++it) {
+    const Real t = Real(1) + tau;
+    const Real t2 = t * t;
+    const Real f = t2 * t * (tau - a1) + tau * (Real(1) + a2) + a2;
+    const Real df = t2 * (Real(1) + Real(4) * tau - Real(3) * a1) + Real(1) + a2;
+    const Real step = f / df;
+    tau -= step;
+    if (!(fabs(step) > tol * (Real(1) + fabs(tau)))) break;
+  }
+  return tau;
+}
+
+template <typename Real>
+__device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double h, double Gn,
+                         const Real* xn, const Real* ut, Real* work, const Real* bvec, Real* gout,
+                         double* red, EvalResult& res) {
+  const int n = M.n, np = M.n_pad, nt = M.nt, ch = M.chunk;
+  const Real inv_h2 = Real(1.0 / (h * h));
+  const Real beta = Real(mat.beta), kb = Real(mat.k_bend);
+  const Real Cst = Real(mat.C), Bsk = Real(mat.B), Dsk = Real(mat.D);
+
+  // ---- pass A: enclosed volume (FP64) and bending residuals R_i -> work -----------
+  double accA[3] = {0.0, 0.0, 0.0};   // volume, bending energy, bending Rayleigh energy
+  for (int t = tid(); t < nt; t += kBlock) {
+    const int a = M.tri[3 * t], b = M.tri[3 * t + 1], c = M.tri[3 * t + 2];
+    const double ax = (double)xn[a] + ut[a], ay = (double)xn[np + a] + ut[np + a], az = (double)xn[2 * np + a] + ut[2 * np + a];
+    const double bx = (double)xn[b] + ut[b], by = (double)xn[np + b] + ut[np + b], bz = (double)xn[2 * np + b] + ut[2 * np + b];
+    const double cx = (double)xn[c] + ut[c], cy = (double)xn[np + c] + ut[np + c], cz = (double)xn[2 * np + c] + ut[2 * np + c];
+    accA[0] += ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
+  }
+  for (int i = tid(); i < n; i += kBlock) {
+    Real lx = 0, ly = 0, lz = 0, ux = 0, uy = 0, uz = 0;
+    const Real xix = xn[i], xiy = xn[np + i], xiz = xn[2 * np + i];
+    const Real uix = ut[i], uiy = ut[np + i], uiz = ut[2 * np + i];
+    for (int q = M.nb_ptr[i]; q < M.nb_ptr[i + 1]; ++q) {
+      const int j = M.nb_idx[q];
+      const Real w = M.nb_w[q];
+      const Real dux = ut[j] - uix, duy = ut[np + j] - uiy, duz = ut[2 * np + j] - uiz;
+      lx += w * ((xn[j] - xix) + dux);
+      ly += w * ((xn[np + j] - xiy) + duy);
+      lz += w * ((xn[2 * np + j] - xiz) + duz);
+      ux += w * dux;
+      uy += w * duy;
+      uz += w * duz;
+    }
+    const Real Ai = M.vor_area[i], inv_A = Real(1) / Ai;
+    lx *= inv_A; ly *= inv_A; lz *= inv_A;
+    ux *= inv_A; uy *= inv_A; uz *= inv_A;
+    const Real nrm = sqrt(lx * lx + ly * ly + lz * lz);
+    const Real sc = nrm > Real(1e-30) ? M.ell0[i] / nrm : Real(0);
+    const Real rx = lx - sc * lx, ry = ly - sc * ly, rz = lz - sc * lz;
+    accA[1] += 0.5 * (double)(kb * Ai) * ((double)rx * rx + (double)ry * ry + (double)rz * rz);
+    accA[2] += 0.5 * (double)(beta * kb * Ai) * ((double)ux * ux + (double)uy * uy + (double)uz * uz);
+    work[i] = rx + beta * ux;
+    work[np + i] = ry + beta * uy;
+    work[2 * np + i] = rz + beta * uz;
+  }
+  block_sum<3>(accA, red);
+  const double vol = accA[0] / 6.0;
+  const double Cv = vol - M.V0;
+  const Real coef = Real(mat.k_volume * Cv / Gn);          // k C / G_n
+  const double e_vol = 0.5 * mat.k_volume * Cv * Cv / Gn;
+
+  // ---- pass B: bending gradient + inertia - b -> gout ----------------------------
+  double accB[1] = {0.0};
+  for (int i = tid(); i < n; i += kBlock) {
+    Real gx = 0, gy = 0, gz = 0;
+    const Real rix = work[i], riy = work[np + i], riz = work[2 * np + i];
+    for (int q = M.nb_ptr[i]; q < M.nb_ptr[i + 1]; ++q) {
+      const int j = M.nb_idx[q];
+      const Real w = M.nb_w[q];
+      gx += w * (work[j] - rix);
+      gy += w * (work[np + j] - riy);
+      gz += w * (work[2 * np + j] - riz);
+    }
+    const Real mi = M.mass[i] * inv_h2;
+    const Real ux = ut[i], uy = ut[np + i], uz = ut[2 * np + i];
+    const Real bx = bvec[i], by = bvec[np + i], bz = bvec[2 * np + i];
+    gout[i] = kb * gx + (mi * ux - bx);
+    gout[np + i] = kb * gy + (mi * uy - by);
+    gout[2 * np + i] = kb * gz + (mi * uz - bz);
+    accB[0] += 0.5 * (double)mi * ((double)ux * ux + (double)uy * uy + (double)uz * uz)
+               - ((double)ux * bx + (double)uy * by + (double)uz * bz);
+  }
+  for (int i = n + tid(); i < np; i += kBlock) gout[i] = gout[np + i] = gout[2 * np + i] = Real(0);
+  __syncthreads();   // work (R) is reused for the corner chunks below
+
+  // ---- passes C/D: triangle in-plane terms + volume, per chunk --------------------
+  double accC[4] = {0.0, 0.0, 0.0, 0.0};   // area PD, Skalak, triangle Rayleigh, |u.b|
+  double accD[4] = {0.0, 0.0, 0.0, 0.0};   // |grad|^2, |M u/h^2|^2, |b|^2, |F_int|^2
+  for (int t0 = 0; t0 < nt; t0 += ch) {
+    const int tn = min(ch, nt - t0);
+    for (int tt = tid(); tt < tn; tt += kBlock) {
+      const int t = t0 + tt;
+      const int a = M.tri[3 * t], b = M.tri[3 * t + 1], c = M.tri[3 * t + 2];
+      const double D00 = M.dminv[4 * t], D01 = M.dminv[4 * t + 1], D10 = M.dminv[4 * t + 2], D11 = M.dminv[4 * t + 3];
+      const Real d00 = Real(D00), d01 = Real(D01), d10 = Real(D10), d11 = Real(D11);
+      const Real A0 = Real(M.area[t]);
+      // The strain measures (sigma - 1, area ratio - 1) are small differences of O(1)
+      // quantities, so the edges, F = [e1 e2] D_m^-1, F^T F and |e1 x e2|^2 are formed
+      // in FP64 from the stored values (exact differences); everything after that works
+      // on the small differences and keeps its relative precision in FP32.
+      const double E1x = ((double)xn[a] - (double)xn[c]) + ((double)ut[a] - (double)ut[c]);
+      const double E1y = ((double)xn[np + a] - (double)xn[np + c]) + ((double)ut[np + a] - (double)ut[np + c]);
+      const double E1z = ((double)xn[2 * np + a] - (double)xn[2 * np + c]) + ((double)ut[2 * np + a] - (double)ut[2 * np + c]);
+      const double E2x = ((double)xn[b] - (double)xn[c]) + ((double)ut[b] - (double)ut[c]);
+      const double E2y = ((double)xn[np + b] - (double)xn[np + c]) + ((double)ut[np + b] - (double)ut[np + c]);
+      const double E2z = ((double)xn[2 * np + b] - (double)xn[2 * np + c]) + ((double)ut[2 * np + b] - (double)ut[2 * np + c]);
+      const double F0x = E1x * D00 + E2x * D10, F0y = E1y * D00 + E2y * D10, F0z = E1z * D00 + E2z * D10;
+      const double F1x = E1x * D01 + E2x * D11, F1y = E1y * D01 + E2y * D11, F1z = E1z * D01 + E2z * D11;
+      const double C00 = F0x * F0x + F0y * F0y + F0z * F0z;
+      const double C01 = F0x * F1x + F0y * F1y + F0z * F1z;
+      const double C11 = F1x * F1x + F1y * F1y + F1z * F1z;
+      const double Nx = E1y * E2z - E1z * E2y, Ny = E1z * E2x - E1x * E2z, Nz = E1x * E2y - E1y * E2x;
+      const double NN = Nx * Nx + Ny * Ny + Nz * Nz;
+      // displacement part of F for the Rayleigh term
+      const Real eu1x = ut[a] - ut[c], eu1y = ut[np + a] - ut[np + c], eu1z = ut[2 * np + a] - ut[2 * np + c];
+      const Real eu2x = ut[b] - ut[c], eu2y = ut[np + b] - ut[np + c], eu2z = ut[2 * np + b] - ut[2 * np + c];
+      const Real f0x = Real(F0x), f0y = Real(F0y), f0z = Real(F0z);
+      const Real f1x = Real(F1x), f1y = Real(F1y), f1z = Real(F1z);
+      const Real g0x = eu1x * d00 + eu2x * d10, g0y = eu1y * d00 + eu2y * d10, g0z = eu1z * d00 + eu2z * d10;
+      const Real g1x = eu1x * d01 + eu2x * d11, g1y = eu1y * d01 + eu2y * d11, g1z = eu1z * d01 + eu2z * d11;
+      const Real c01 = Real(C01);
+      const Real nx = Real(Nx), ny = Real(Ny), nz = Real(Nz);
+      const Real nn = sqrt(Real(NN));
+      // area ratio J = sigma1 sigma2 = |e1 x e2| / (2 A0)
+      const Real Jsq_m1 = Real(NN * M.inv4a2[t] - 1.0);
+      const Real J = sqrt(fmax(Real(1) + Jsq_m1, Real(0)));
+      const Real Jm1 = Jsq_m1 / (J + Real(1));
+      const Real half = Real(0.5 * (C00 - C11));
+      const Real disc = sqrt(half * half + c01 * c01);
+      const Real s1m = Real(0.5 * ((C00 - 1.0) + (C11 - 1.0))) + disc;          // sigma1^2 - 1
+      const Real sig1 = sqrt(fmax(Real(1) + s1m, Real(0)));
+      const Real a1 = s1m / (sig1 + Real(1));                                  // sigma1 - 1
+      const Real inv_s1 = sig1 > Real(1e-30) ? Real(1) / sig1 : Real(0);
+      const Real a2 = (Jm1 - a1) * inv_s1;                                     // sigma2 - 1
+      const Real sig2 = Real(1) + a2;
+      // right singular vectors v1, v2 = perp(v1); left u1 = F v1 / sigma1, u2 = nhat x u1
+      Real vx, vy;
+      if (half >= Real(0)) { vx = half + disc; vy = c01; } else { vx = c01; vy = disc - half; }
+      const Real vn = sqrt(vx * vx + vy * vy);
+      if (vn > Real(0)) { vx /= vn; vy /= vn; } else { vx = Real(1); vy = Real(0); }
+      const Real u1x = (f0x * vx + f1x * vy) * inv_s1, u1y = (f0y * vx + f1y * vy) * inv_s1, u1z = (f0z * vx + f1z * vy) * inv_s1;
+      const Real inv_nn = nn > Real(1e-30) ? Real(1) / nn : Real(0);
+      const Real hx = nx * inv_nn, hy = ny * inv_nn, hz = nz * inv_nn;
+      const Real u2x = hy * u1z - hz * u1y, u2y = hz * u1x - hx * u1z, u2z = hx * u1y - hy * u1x;
+      // area PD: closest SL(2) element diag(t, 1/t)
+      const Real tau = sl2_tau<Real>(a1, a2, sig1, J);
+      const Real dA1 = a1 - tau, dA2 = a2 + tau / (Real(1) + tau);
+      // modified Skalak: f'(s) = B/2 s (s^2 - 1) + D (s - 1)^3
+      const Real s2m = a2 * (Real(2) + a2);                                    // sigma2^2 - 1
+      const Real fp1 = Real(0.5) * Bsk * sig1 * s1m + Dsk * a1 * a1 * a1;
+      const Real fp2 = Real(0.5) * Bsk * sig2 * s2m + Dsk * a2 * a2 * a2;
+      const Real w1 = A0 * (Cst * dA1 + fp1), w2 = A0 * (Cst * dA2 + fp2), wr = beta * Cst * A0;
+      // dE/dF = w1 u1 v1^T + w2 u2 v2^T + wr F_u, with v2 = (-vy, vx)
+      const Real G0x = w1 * u1x * vx - w2 * u2x * vy + wr * g0x;
+      const Real G0y = w1 * u1y * vx - w2 * u2y * vy + wr * g0y;
+      const Real G0z = w1 * u1z * vx - w2 * u2z * vy + wr * g0z;
+      const Real G1x = w1 * u1x * vy + w2 * u2x * vx + wr * g1x;
+      const Real G1y = w1 * u1y * vy + w2 * u2y * vx + wr * g1y;
+      const Real G1z = w1 * u1z * vy + w2 * u2z * vx + wr * g1z;
+      // corner gradients [g_a g_b] = dE/dF D_m^-T, g_c = -g_a - g_b, plus the volume
+      // gradient k C / G_n * (e1 x e2) / 6 on each corner
+      const Real vvx = coef * nx / Real(6), vvy = coef * ny / Real(6), vvz = coef * nz / Real(6);
+      const Real gax = G0x * d00 + G1x * d01, gay = G0y * d00 + G1y * d01, gaz = G0z * d00 + G1z * d01;
+      const Real gbx = G0x * d10 + G1x * d11, gby = G0y * d10 + G1y * d11, gbz = G0z * d10 + G1z * d11;
+      work[0 * ch + tt] = gax + vvx;
+      work[1 * ch + tt] = gay + vvy;
+      work[2 * ch + tt] = gaz + vvz;
+      work[3 * ch + tt] = gbx + vvx;
+      work[4 * ch + tt] = gby + vvy;
+      work[5 * ch + tt] = gbz + vvz;
+      work[6 * ch + tt] = -(gax + gbx) + vvx;
+      work[7 * ch + tt] = -(gay + gby) + vvy;
+      work[8 * ch + tt] = -(gaz + gbz) + vvz;
+      accC[0] += 0.5 * (double)(Cst * A0) * ((double)dA1 * dA1 + (double)dA2 * dA2);
+      accC[1] += (double)A0 * (0.125 * (double)Bsk * ((double)s1m * s1m + (double)s2m * s2m)
+                               + 0.25 * (double)Dsk * ((double)a1 * a1 * a1 * a1 + (double)a2 * a2 * a2 * a2));
+      accC[2] += 0.5 * (double)wr * ((double)g0x * g0x + (double)g0y * g0y + (double)g0z * g0z
+                                     + (double)g1x * g1x + (double)g1y * g1y + (double)g1z * g1z);
+    }
+    __syncthreads();
+    const bool last = t0 + ch >= nt;
+    for (int i = tid(); i < n; i += kBlock) {
+      Real gx = 0, gy = 0, gz = 0;
+      for (int q = M.vc_ptr[i]; q < M.vc_ptr[i + 1]; ++q) {
+        const int cid = M.vc_idx[q];
+        const int t = cid / 3 - t0;
+        if (t >= 0 && t < tn) {
+          const int k = cid - 3 * (cid / 3);
+          gx += work[(3 * k) * ch + t];
+          gy += work[(3 * k + 1) * ch + t];
+          gz += work[(3 * k + 2) * ch + t];
+        }
+      }
+      gx += gout[i];
+      gy += gout[np + i];
+      gz += gout[2 * np + i];
+      gout[i] = gx;
+      gout[np + i] = gy;
+      gout[2 * np + i] = gz;
+      if (last) {
+        const Real mi = M.mass[i] * inv_h2;
+        const Real ux = ut[i], uy = ut[np + i], uz = ut[2 * np + i];
+        const Real bx = bvec[i], by = bvec[np + i], bz = bvec[2 * np + i];
+        const double mux = (double)mi * ux, muy = (double)mi * uy, muz = (double)mi * uz;
+        const double fx = gx - (mux - bx), fy = gy - (muy - by), fz = gz - (muz - bz);
+        accD[0] += (double)gx * gx + (double)gy * gy + (double)gz * gz;
+        accD[1] += mux * mux + muy * muy + muz * muz;
+        accD[2] += (double)bx * bx + (double)by * by + (double)bz * bz;
+        accD[3] += fx * fx + fy * fy + fz * fz;
+        accC[3] += fabs((double)ux * bx + (double)uy * by + (double)uz * bz);
+      }
+    }
+    __syncthreads();
+  }
+  double acc[9] = {accB[0], accC[0], accC[1], accC[2], accC[3], accD[0], accD[1], accD[2], accD[3]};
+  block_sum<9>(acc, red);
+  const double inertial = acc[0];
+  res.vol = vol;
+  res.terms[0] = inertial;
+  res.terms[1] = acc[1];
+  res.terms[2] = acc[2];
+  res.terms[3] = accA[1] + accA[2];
+  res.terms[4] = e_vol;
+  res.terms[5] = acc[3];
+  res.E = inertial + acc[1] + acc[2] + accA[1] + accA[2] + e_vol + acc[3];
+  // rounding scale of E: the sum of the magnitudes of its terms
+  res.noise = fabs(inertial) + 2.0 * acc[4] + acc[1] + acc[2] + accA[1] + accA[2] + e_vol + acc[3];
+  const double num = sqrt(acc[5]);
+  const double den = sqrt(acc[6]) + sqrt(acc[7]) + sqrt(acc[8]) + M.floor_force;
+  res.resid = num == 0.0 ? 0.0 : num / den;
+  if (!isfinite(res.E) || !isfinite(num)) res.resid = INFINITY;
+}
+
+// ---------------------------------------------------------------------------------
+// Tile product Out^T = In^T A with A = A^T (n_pad x n_pad), In^T / Out^T (rows x n_pad)
+// on the matrix cores.  16x16 output blocks; each wave owns every fourth column block
+// and all (<= 4) row blocks, so an A fragment is loaded once per wave and reused.
+// Both operands are read as 16-byte vectors along k (A is symmetric, so its column
+// fragment is a row fragment).
+// ---------------------------------------------------------------------------------
+__device__ inline void tile_gemm(const float* __restrict__ A, int np, const float* __restrict__ In,
+                                 float* __restrict__ Out, int rows) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int mb_n = (rows + 15) >> 4;
+  for (int nb = wave; nb < (np >> 4); nb += 4) {
+    const int n0 = nb << 4;
+    floatx4 acc[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) acc[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const float* arow = A + (size_t)(n0 + l16) * np + 4 * kq;
+    for (int k0 = 0; k0 < np; k0 += 16) {
+      const floatx4 bq = *reinterpret_cast<const floatx4*>(arow + k0);
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        if (mb < mb_n) {
+          const int r = mb * 16 + l16;
+          const floatx4 aq = r < rows ? *reinterpret_cast<const floatx4*>(In + (size_t)r * np + k0 + 4 * kq)
+                                      : floatx4{0.f, 0.f, 0.f, 0.f};
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq.x, bq.x, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq.y, bq.y, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq.z, bq.z, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq.w, bq.w, acc[mb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      if (mb < mb_n) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = mb * 16 + 4 * kq + i;
+          if (r < rows) Out[(size_t)r * np + n0 + l16] = acc[mb][i];
+        }
+      }
+    }
+  }
+}
+
+__device__ inline void tile_gemm(const double* __restrict__ A, int np, const double* __restrict__ In,
+                                 double* __restrict__ Out, int rows) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int mb_n = (rows + 15) >> 4;
+  for (int nb = wave; nb < (np >> 4); nb += 4) {
+    const int n0 = nb << 4;
+    doublex4 acc[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) acc[mb] = doublex4{0.0, 0.0, 0.0, 0.0};
+    const double* arow = A + (size_t)(n0 + l16) * np + 4 * kq;
+    for (int k0 = 0; k0 < np; k0 += 16) {
+      const doublex4 bq = *reinterpret_cast<const doublex4*>(arow + k0);
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        if (mb < mb_n) {
+          const int r = mb * 16 + l16;
+          const doublex4 aq = r < rows ? *reinterpret_cast<const doublex4*>(In + (size_t)r * np + k0 + 4 * kq)
+                                       : doublex4{0.0, 0.0, 0.0, 0.0};
+          acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq.x, bq.x, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq.y, bq.y, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq.z, bq.z, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq.w, bq.w, acc[mb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      if (mb < mb_n) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = mb * 16 + 4 * kq + i;
+          if (r < rows) Out[(size_t)r * np + n0 + l16] = acc[mb][i];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// The step
+// ---------------------------------------------------------------------------------
+enum { VB = 0, VU, VG, VGT, VD, VQ, VS0 };
+
+template <typename Real>
+struct Tile {
+  Real* W;
+  int np, T;
+  __device__ Real* vec(int v, int j) const { return W + ((size_t)v * T + j) * 3 * np; }
+  __device__ Real* mat(int v) const { return W + (size_t)v * T * 3 * np; }
+};
+
+template <typename Real>
+__device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, const Tile<Real>& tl,
+                              int j, int cell, CellState& cs, const Real* xn, double* red, double* bc) {
+  const int n = M.n, np = M.n_pad;
+  const int64_t voff = A.cell_voff[cell];
+  const Real* U = tl.vec(VU, j);
+  const double h = A.sol.h;
+  Real* xo = A.x_out + 3 * voff;
+  Real* vo = A.v_out + 3 * voff;
+  if (cs.status & NPFEM_NONFINITE) {
+    for (int e = tid(); e < 3 * n; e += kBlock) {
+      const int i = e / 3, c = e - 3 * i;
+      xo[e] = xn[c * np + i];
+      vo[e] = A.v[3 * voff + e];
+    }
+  } else {
+    // v = u / h, then damp its departure from the best-fit rigid motion (section 2.1.4)
+    double s1[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int i = tid(); i < n; i += kBlock) {
+      const double m = M.mass[i];
+      s1[0] += m;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double x = (double)xn[c * np + i] + (double)U[c * np + i];
+        s1[1 + c] += m * x;
+        s1[4 + c] += m * ((double)U[c * np + i] / h);
+      }
+    }
+    block_sum<7>(s1, red);
+    const double xc[3] = {s1[1] / s1[0], s1[2] / s1[0], s1[3] / s1[0]};
+    const double vc[3] = {s1[4] / s1[0], s1[5] / s1[0], s1[6] / s1[0]};
+    double s2[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // L (3), I_xx I_yy I_zz I_xy I_xz I_yz
+    for (int i = tid(); i < n; i += kBlock) {
+      const double m = M.mass[i];
+      const double rx = (double)xn[i] + (double)U[i] - xc[0];
+      const double ry = (double)xn[np + i] + (double)U[np + i] - xc[1];
+      const double rz = (double)xn[2 * np + i] + (double)U[2 * np + i] - xc[2];
+      const double vx = (double)U[i] / h, vy = (double)U[np + i] / h, vz = (double)U[2 * np + i] / h;
+      s2[0] += m * (ry * vz - rz * vy);
+      s2[1] += m * (rz * vx - rx * vz);
+      s2[2] += m * (rx * vy - ry * vx);
+      s2[3] += m * (ry * ry + rz * rz);
+      s2[4] += m * (rx * rx + rz * rz);
+      s2[5] += m * (rx * rx + ry * ry);
+      s2[6] -= m * rx * ry;
+      s2[7] -= m * rx * rz;
+      s2[8] -= m * ry * rz;
+    }
+    block_sum<9>(s2, red);
+    // omega = I^-1 L (3x3 symmetric, adjugate)
+    const double Ixx = s2[3], Iyy = s2[4], Izz = s2[5], Ixy = s2[6], Ixz = s2[7], Iyz = s2[8];
+    const double c00 = Iyy * Izz - Iyz * Iyz, c01 = Ixz * Iyz - Ixy * Izz, c02 = Ixy * Iyz - Ixz * Iyy;
+    const double c11 = Ixx * Izz - Ixz * Ixz, c12 = Ixy * Ixz - Ixx * Iyz, c22 = Ixx * Iyy - Ixy * Ixy;
+    const double det = Ixx * c00 + Ixy * c01 + Ixz * c02;
+    double w[3] = {0, 0, 0};
+    if (det > 0) {
+      w[0] = (c00 * s2[0] + c01 * s2[1] + c02 * s2[2]) / det;
+      w[1] = (c01 * s2[0] + c11 * s2[1] + c12 * s2[2]) / det;
+      w[2] = (c02 * s2[0] + c12 * s2[1] + c22 * s2[2]) / det;
+    }
+    const double kap = A.mat.kappa;
+    for (int i = tid(); i < n; i += kBlock) {
+      const double rx = (double)xn[i] + (double)U[i] - xc[0];
+      const double ry = (double)xn[np + i] + (double)U[np + i] - xc[1];
+      const double rz = (double)xn[2 * np + i] + (double)U[2 * np + i] - xc[2];
+      const double vx = (double)U[i] / h, vy = (double)U[np + i] / h, vz = (double)U[2 * np + i] / h;
+      const double dvx = vc[0] + (w[1] * rz - w[2] * ry) - vx;
+      const double dvy = vc[1] + (w[2] * rx - w[0] * rz) - vy;
+      const double dvz = vc[2] + (w[0] * ry - w[1] * rx) - vz;
+      vo[3 * i] = (Real)(vx + kap * dvx);
+      vo[3 * i + 1] = (Real)(vy + kap * dvy);
+      vo[3 * i + 2] = (Real)(vz + kap * dvz);
+      xo[3 * i] = xn[i] + U[i];
+      xo[3 * i + 1] = xn[np + i] + U[np + i];
+      xo[3 * i + 2] = xn[2 * np + i] + U[2 * np + i];
+    }
+  }
+  if (A.stats && tid() == 0) {
+    npfem_cell_stats st;
+    st.iterations = cs.iter;
+    st.evaluations = cs.evals;
+    st.status = (uint32_t)cs.status;
+    st.halvings = cs.halvings;
+    st.residual = cs.resid;
+    st.objective = cs.E;
+    st.volume = bc[0];
+    A.stats[cell] = st;
+  }
+}
+
+template <typename Real>
+__device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* CS, double* red,
+                         int* sint, unsigned char* lds) {
+  const TileDesc td = A.tiles[tile];
+  const MeshDev<Real>& M = A.meshes[td.mesh];
+  const int n = M.n, np = M.n_pad, cnt = td.count, len = 3 * np;
+  Tile<Real> tl{W, np, A.tile_cells_max};
+  Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);
+  Real* ut = xn + 3 * np;
+  Real* work = ut + 3 * np;
+  const double h = A.sol.h;
+  const int m = A.sol.m;
+  const double eps = Eps<Real>::v;
+  __shared__ double s_vol[kMaxTile];
+
+  // ---- initial state: b = M v_n / h + F_ext, |grad V(x_n)|^2, first guess --------
+  for (int j = 0; j < cnt; ++j) {
+    const int cell = A.tile_cells[td.first + j];
+    const int64_t voff = A.cell_voff[cell];
+    stage_aos(xn, A.x + 3 * voff, n, np);
+    Real* B = tl.vec(VB, j);
+    Real* U = tl.vec(VU, j);
+    for (int e = tid(); e < len; e += kBlock) {
+      const int c = e / np, i = e - c * np;
+      B[e] = i < n ? M.mass[i] * A.v[3 * (voff + i) + c] / Real(h) + A.f[3 * (voff + i) + c] : Real(0);
+      if (A.u_guess) U[e] = i < n ? A.u_guess[3 * (voff + i) + c] : Real(0);
+    }
+    __syncthreads();
+    const double Gn = volume_normaliser(M, xn, ut, work, red);
+    if (tid() == 0) {
+      CellState& cs = CS[j];
+      cs.Gn = Gn;
+      cs.hist_n = cs.hist_head = cs.iter = cs.evals = cs.status = cs.retry = cs.halvings = 0;
+      cs.active = 1;
+    }
+    __syncthreads();
+  }
+  if (!A.u_guess) {
+    tile_gemm(M.minv, np, tl.mat(VB), tl.mat(VU), 3 * cnt);     // u = h^2 M~^-1 b
+    __syncthreads();
+  }
+
+  // ---- first evaluation ---------------------------------------------------------
+  for (int j = 0; j < cnt; ++j) {
+    const int cell = A.tile_cells[td.first + j];
+    stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
+    const Real* U = tl.vec(VU, j);
+    for (int e = tid(); e < len; e += kBlock) ut[e] = U[e];
+    __syncthreads();
+    EvalResult r;
+    evaluate(M, A.mat, h, CS[j].Gn, xn, ut, work, tl.vec(VB, j), tl.vec(VG, j), red, r);
+    const bool bad = !isfinite(r.E) || !isfinite(r.resid);
+    const bool done = bad || r.resid <= A.sol.tol;
+    if (!done) {
+      const Real* G = tl.vec(VG, j);
+      Real* Q = tl.vec(VQ, j);
+      for (int e = tid(); e < len; e += kBlock) Q[e] = G[e];
+    }
+    if (tid() == 0) {
+      CellState& cs = CS[j];
+      cs.E = r.E;
+      cs.noise = r.noise;
+      cs.resid = r.resid;
+      cs.evals = 1;
+      s_vol[j] = r.vol;
+      if (bad) { cs.status = NPFEM_NONFINITE; cs.active = 0; }
+      else if (done) { cs.status = NPFEM_CONVERGED; cs.active = 0; }
+    }
+    __syncthreads();
+  }
+
+  // ---- quasi-Newton iterations (Algorithm 1, while loop) --------------------------
+  // every round an active cell accepts a step (iter + 1, bounded by max_iter) or
+  // clears its history for one retry, so 2 max_iter + 2 rounds always suffice
+  const int max_rounds = 2 * A.sol.max_iter + 2;
+  for (int round = 0;; ++round) {
+    if (tid() == 0) {
+      int act = 0;
+      for (int j = 0; j < cnt; ++j) {
+        if (round >= max_rounds && CS[j].active) {
+          CS[j].active = 0;
+          CS[j].status = NPFEM_MAXITER;
+        }
+        act += CS[j].active;
+      }
+      sint[1] = act;
+    }
+    __syncthreads();
+    if (sint[1] == 0) break;
+    tile_gemm(M.hinv, np, tl.mat(VQ), tl.mat(VD), 3 * cnt);      // r = H~^-1 q
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      CellState& cs = CS[j];
+      if (!cs.active) continue;                                  // uniform: read after a barrier
+      const int cell = A.tile_cells[td.first + j];
+      stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
+      Real* U = tl.vec(VU, j);
+      Real* G = tl.vec(VG, j);
+      Real* GT = tl.vec(VGT, j);
+      Real* D = tl.vec(VD, j);
+      Real* Q = tl.vec(VQ, j);
+      const int hn = cs.hist_n, head = cs.hist_head;
+      // two-loop recursion, second half: z = r + sum_i s_i (alpha_i - beta_i), oldest first
+      for (int p = 0; p < hn; ++p) {
+        const int slot = (head - hn + p + 2 * kMaxHistory) % m;
+        const Real* S = tl.vec(VS0 + slot, j);
+        const Real* Y = tl.vec(VS0 + m + slot, j);
+        const double bta = cs.rho[slot] * dot_vec(Y, D, len, red);
+        const Real coefs = Real(cs.alpha[slot] - bta);
+        for (int e = tid(); e < len; e += kBlock) D[e] += coefs * S[e];
+        __syncthreads();
+      }
+      for (int e = tid(); e < len; e += kBlock) D[e] = -D[e];
+      __syncthreads();
+      // line search: alpha = 1, 1/2, ... until sufficient decrease (Algorithm 1)
+      const double gd = dot_vec(G, D, len, red);
+      double alpha = 1.0;
+      bool accepted = false;
+      EvalResult r;
+      int hv = 0;
+      for (; hv <= A.sol.max_halvings; ++hv) {
+        const Real al = Real(alpha);
+        for (int e = tid(); e < len; e += kBlock) ut[e] = U[e] + al * D[e];
+        __syncthreads();
+        evaluate(M, A.mat, h, cs.Gn, xn, ut, work, tl.vec(VB, j), GT, red, r);
+        const double slack = A.sol.noise * fmax(cs.noise, r.noise);
+        accepted = isfinite(r.E) && (r.E <= cs.E + A.sol.c1 * alpha * gd + slack);
+        if (accepted) break;
+        alpha *= 0.5;
+      }
+      const int evals_add = accepted ? hv + 1 : hv;
+      if (!accepted) {
+        if (hn > 0) {
+          for (int e = tid(); e < len; e += kBlock) Q[e] = G[e];
+          __syncthreads();
+          if (tid() == 0) {
+            cs.hist_n = 0;
+            cs.evals += evals_add;
+            cs.halvings += evals_add;
+          }
+        } else if (tid() == 0) {
+          cs.status = NPFEM_LS_FAIL;
+          cs.active = 0;
+          cs.evals += evals_add;
+          cs.halvings += evals_add;
+        }
+        __syncthreads();
+        continue;
+      }
+      // accept: s = alpha d, y = grad_t - grad; u += s; grad = grad_t
+      const Real al = Real(alpha);
+      double dots[3] = {0.0, 0.0, 0.0};
+      if (m > 0) {
+        Real* S = tl.vec(VS0 + head, j);
+        Real* Y = tl.vec(VS0 + m + head, j);
+        for (int e = tid(); e < len; e += kBlock) {
+          const Real s = al * D[e], y = GT[e] - G[e];
+          S[e] = s;
+          Y[e] = y;
+          U[e] += s;
+          G[e] = GT[e];
+          dots[0] += (double)s * y;
+          dots[1] += (double)s * s;
+          dots[2] += (double)y * y;
+        }
+      } else {
+        for (int e = tid(); e < len; e += kBlock) {
+          U[e] += al * D[e];
+          G[e] = GT[e];
+        }
+      }
+      block_sum<3>(dots, red);
+      const bool store = m > 0 && dots[0] > 1e-12 * sqrt(dots[1] * dots[2]);
+      int hn2 = hn, head2 = head;
+      if (store) {
+        hn2 = min(hn + 1, m);
+        head2 = (head + 1) % m;
+      } else if (hn == m) {
+        hn2 = m - 1;          // slot `head` held the oldest pair and was overwritten
+      }
+      const bool conv = r.resid <= A.sol.tol;
+      const bool out_of_iters = cs.iter + 1 >= A.sol.max_iter;
+      __syncthreads();
+      if (tid() == 0) {
+        if (store) cs.rho[head] = 1.0 / dots[0];
+        cs.hist_n = hn2;
+        cs.hist_head = head2;
+        cs.E = r.E;
+        cs.noise = r.noise;
+        cs.resid = r.resid;
+        cs.iter += 1;
+        cs.evals += evals_add;
+        cs.halvings += hv;
+        s_vol[j] = r.vol;
+        if (conv) { cs.status = NPFEM_CONVERGED; cs.active = 0; }
+        else if (out_of_iters) { cs.status = NPFEM_MAXITER; cs.active = 0; }
+      }
+      if (conv || out_of_iters) { __syncthreads(); continue; }
+      // two-loop recursion, first half: q = g; alpha_i = rho_i s_i.q; q -= alpha_i y_i
+      for (int e = tid(); e < len; e += kBlock) Q[e] = G[e];
+      __syncthreads();
+      for (int p = hn2 - 1; p >= 0; --p) {
+        const int slot = (head2 - hn2 + p + 2 * kMaxHistory) % m;
+        const Real* S = tl.vec(VS0 + slot, j);
+        const Real* Y = tl.vec(VS0 + m + slot, j);
+        const double rho = (p == hn2 - 1 && store) ? 1.0 / dots[0] : CS[j].rho[slot];
+        const double a = rho * dot_vec(S, Q, len, red);
+        const Real ar = Real(a);
+        for (int e = tid(); e < len; e += kBlock) Q[e] -= ar * Y[e];
+        if (tid() == 0) cs.alpha[slot] = a;
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- velocity update and dissipation --------------------------------------------
+  for (int j = 0; j < cnt; ++j) {
+    const int cell = A.tile_cells[td.first + j];
+    stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
+    __syncthreads();
+    double bc[1] = {s_vol[j]};
+    CellState cs = CS[j];
+    finalize_cell(A, M, tl, j, cell, cs, xn, red, bc);
+    __syncthreads();
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) step_kernel(StepArgs<Real> A) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  double* red = reinterpret_cast<double*>(lds);
+  int* sint = reinterpret_cast<int*>(lds + kRedDoubles * 8);
+  Real* W = A.work + (size_t)blockIdx.x * A.slot_stride;
+  CellState* CS = A.cstate + (size_t)blockIdx.x * A.tile_cells_max;
+  for (;;) {
+    if (tid() == 0) sint[0] = atomicAdd(A.tile_counter, 1);
+    __syncthreads();
+    const int tile = sint[0];
+    __syncthreads();
+    if (tile >= A.n_tiles) break;
+    run_tile(A, tile, W, CS, red, sint, lds);
+    __syncthreads();
+  }
+}
+
+__global__ void reset_counter(int* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+}
+
+// One workgroup per cell: objective and gradient at x_n + u (no iteration).
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Real* u, Real* grad,
+                                                      double* terms, Real* scratch) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  double* red = reinterpret_cast<double*>(lds);
+  const int cell = blockIdx.x;
+  const MeshDev<Real>& M = A.meshes[A.cell_mesh[cell]];
+  const int n = M.n, np = M.n_pad, len = 3 * np;
+  const int64_t voff = A.cell_voff[cell];
+  Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);
+  Real* ut = xn + 3 * np;
+  Real* work = ut + 3 * np;
+  Real* B = scratch + (size_t)cell * 2 * 3 * A.n_pad_max;
+  Real* G = B + 3 * A.n_pad_max;
+  stage_aos(xn, A.x + 3 * voff, n, np);
+  for (int e = tid(); e < len; e += kBlock) {
+    const int c = e / np, i = e - c * np;
+    B[e] = i < n ? M.mass[i] * A.v[3 * (voff + i) + c] / Real(A.sol.h) + A.f[3 * (voff + i) + c] : Real(0);
+  }
+  __syncthreads();
+  const double Gn = volume_normaliser(M, xn, ut, work, red);
+  __syncthreads();
+  stage_aos(ut, u + 3 * voff, n, np);
+  __syncthreads();
+  EvalResult r;
+  evaluate(M, A.mat, A.sol.h, Gn, xn, ut, work, B, G, red, r);
+  for (int e = tid(); e < 3 * n; e += kBlock) {
+    const int i = e / 3, c = e - 3 * i;
+    grad[3 * voff + e] = G[c * np + i];
+  }
+  if (tid() == 0) {
+    double* o = terms + (size_t)kTerms * cell;
+    o[0] = r.E;
+    for (int k = 0; k < 6; ++k) o[1 + k] = r.terms[k];
+    o[7] = r.resid;
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) apply_inverse_kernel(const Real* A, int np, const Real* in,
+                                                               Real* out, int rows) {
+  const int r0 = blockIdx.x * 48;
+  tile_gemm(A, np, in + (size_t)r0 * np, out + (size_t)r0 * np, min(48, rows - r0));
+}
+
+template <typename Real>
+__global__ void drag_kernel(const Real* x, const Real* v, const int64_t* cell_voff, const int* cell_mesh,
+                            const int* mesh_n, const double* zeta, const double* rate,
+                            const double* origin, double umax, double radius, double ay, double az,
+                            Real* f) {
+  const int cell = blockIdx.x;
+  const int n = mesh_n[cell_mesh[cell]];
+  const int64_t voff = cell_voff[cell];
+  const double z0 = zeta[cell], g = rate[cell];
+  const double oy = origin[3 * cell + 1], oz = origin[3 * cell + 2];
+  for (int i = tid(); i < n; i += blockDim.x) {
+    const int64_t k = 3 * (voff + i);
+    const double y = x[k + 1], z = x[k + 2];
+    double ux = g * z;
+    if (umax != 0.0) {
+      const double wy = oy + y - ay, wz = oz + z - az;
+      const double rho2 = wy * wy + wz * wz;
+      if (rho2 < radius * radius) ux += umax * (1.0 - rho2 / (radius * radius));
+    }
+    f[k] = (Real)(z0 * (ux - (double)v[k]));
+    f[k + 1] = (Real)(-z0 * (double)v[k + 1]);
+    f[k + 2] = (Real)(-z0 * (double)v[k + 2]);
+  }
+}
+
+}  // namespace
+
+template <typename Real>
+size_t lds_bytes(int n_pad, int chunk) {
+  const size_t work = (size_t)(3 * n_pad > 9 * chunk ? 3 * n_pad : 9 * chunk);
+  return kLdsHeader + sizeof(Real) * (6 * (size_t)n_pad + work);
+}
+
+template <typename Real>
+hipError_t set_lds_limit(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&step_kernel<Real>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&eval_kernel<Real>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename Real>
+hipError_t occupancy(int* blocks_per_cu, size_t lds) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<Real>, kBlock, lds);
+}
+
+template <typename Real>
+hipError_t launch_step(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s, int* counter) {
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
+  hipLaunchKernelGGL(step_kernel<Real>, dim3(grid), dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_eval(const StepArgs<Real>& a, int n_cells, const Real* u, Real* grad, double* terms,
+                       size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(eval_kernel<Real>, dim3(n_cells), dim3(kBlock), lds, s, a, u, grad, terms, a.work);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_apply_inverse(const Real* A, int n_pad, const Real* in, Real* out, int rows,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(apply_inverse_kernel<Real>, dim3((rows + 47) / 48), dim3(kBlock), 0, s, A, n_pad,
+                     in, out, rows);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, const int* cell_mesh,
+                       const int* mesh_n, int n_cells, const double* zeta, const double* rate,
+                       const double* origin, double umax, double radius, double ay, double az, Real* f,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(drag_kernel<Real>, dim3(n_cells), dim3(kBlock), 0, s, x, v, cell_voff, cell_mesh,
+                     mesh_n, zeta, rate, origin, umax, radius, ay, az, f);
+  return hipGetLastError();
+}
+
+#define NPFEM_INSTANTIATE(R)                                                                       \
+  template size_t lds_bytes<R>(int, int);                                                          \
+  template hipError_t set_lds_limit<R>(size_t);                                                    \
+  template hipError_t occupancy<R>(int*, size_t);                                                  \
+  template hipError_t launch_step<R>(const StepArgs<R>&, int, size_t, hipStream_t, int*);          \
+  template hipError_t launch_eval<R>(const StepArgs<R>&, int, const R*, R*, double*, size_t,       \
+                                     hipStream_t);                                                 \
+  template hipError_t launch_apply_inverse<R>(const R*, int, const R*, R*, int, hipStream_t);      \
+  template hipError_t launch_drag<R>(const R*, const R*, const int64_t*, const int*, const int*,   \
+                                     int, const double*, const double*, const double*, double,     \
+                                     double, double, double, R*, hipStream_t);
+NPFEM_INSTANTIATE(float)
+NPFEM_INSTANTIATE(double)
+
+}  // namespace npfem

@@ -1,0 +1,207 @@
+"""Python handles over the C ABI.  Argument marshalling only: every step of the
+solver runs in libnpfem.so; torch tensors provide device memory and streams."""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+from . import _native as N
+
+
+def _ptr(a: np.ndarray) -> c_void_p:
+    return c_void_p(a.ctypes.data)
+
+
+def _dptr(t) -> c_void_p:
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(0)
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return c_void_p(s.cuda_stream)
+
+
+def default_material(**overrides) -> N.Material:
+    m = N.Material()
+    N.lib().npfem_material_default(byref(m))
+    for k, v in overrides.items():
+        setattr(m, k, float(v))
+    return m
+
+
+def default_params(**overrides) -> N.SolverParams:
+    p = N.SolverParams()
+    N.lib().npfem_solver_params_default(byref(p))
+    for k, v in overrides.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp32": N.FP32, "fp64": N.FP64}[v]
+        setattr(p, k, v)
+    return p
+
+
+class Mesh:
+    """Rest membrane mesh (validated and preprocessed on the host)."""
+
+    def __init__(self, verts, tris):
+        verts = np.ascontiguousarray(verts, np.float64)
+        tris = np.ascontiguousarray(tris, np.int32)
+        if verts.ndim != 2 or verts.shape[1] != 3 or tris.ndim != 2 or tris.shape[1] != 3:
+            raise ValueError("verts must be [n,3] and tris [nt,3]")
+        h = c_void_p()
+        N.check(N.lib().npfem_mesh_create(len(verts), _ptr(verts), len(tris), _ptr(tris), byref(h)),
+                "npfem_mesh_create")
+        self._h = h
+        n, nt, ne = c_int32(), c_int32(), c_int32()
+        V0, A0 = c_double(), c_double()
+        N.check(N.lib().npfem_mesh_query(h, byref(n), byref(nt), byref(ne), byref(V0), byref(A0)),
+                "npfem_mesh_query")
+        self.n, self.nt, self.ne = n.value, nt.value, ne.value
+        self.rest_volume, self.rest_area = V0.value, A0.value
+
+    def rest_data(self) -> dict:
+        out = {"vor_area": np.zeros(self.n), "ell0": np.zeros(self.n), "tri_area": np.zeros(self.nt),
+               "dminv": np.zeros((self.nt, 2, 2))}
+        N.check(N.lib().npfem_mesh_rest_data(self._h, *(_ptr(out[k]) for k in ("vor_area", "ell0", "tri_area", "dminv"))),
+                "npfem_mesh_rest_data")
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            N.lib().npfem_mesh_destroy(self._h)
+            self._h = None
+
+
+class Plan:
+    """Mesh types + material + time step: constant matrices and their inverses on the GPU."""
+
+    def __init__(self, meshes, dt: float, material: N.Material | None = None,
+                 params: N.SolverParams | None = None, device: int = 0):
+        self.meshes = list(meshes)
+        self.material = material or default_material()
+        self.params = params or default_params()
+        self.dt = float(dt)
+        arr = (c_void_p * len(self.meshes))(*[m._h for m in self.meshes])
+        h = c_void_p()
+        N.check(N.lib().npfem_plan_create(device, ctypes.cast(arr, c_void_p), len(self.meshes),
+                                          byref(self.material), self.dt, byref(self.params), byref(h)),
+                "npfem_plan_create")
+        self._h = h
+        self.device = device
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.params.precision == N.FP64 else torch.float32
+
+    def masses(self, mesh_index: int) -> np.ndarray:
+        out = np.zeros(self.meshes[mesh_index].n)
+        N.check(N.lib().npfem_plan_masses(self._h, mesh_index, _ptr(out)), "npfem_plan_masses")
+        return out
+
+    def n_pad(self, mesh_index: int) -> int:
+        np_ = c_int32()
+        N.check(N.lib().npfem_apply_inverse(self._h, mesh_index, 0, None, None, 0, byref(np_), None),
+                "npfem_apply_inverse")
+        return np_.value
+
+    def apply_inverse(self, mesh_index: int, which: int, inp, out=None, stream=None):
+        """out[r] = A inp[r] for A = H~^-1 (which 0) or h^2 M~^-1 (which 1); inp [rows, n_pad]."""
+        import torch
+        if out is None:
+            out = torch.empty_like(inp)
+        self._check(inp, out)
+        N.check(N.lib().npfem_apply_inverse(self._h, mesh_index, which, _dptr(inp), _dptr(out),
+                                            inp.shape[0], None, _stream(stream)), "npfem_apply_inverse")
+        return out
+
+    def _check(self, *ts):
+        for t in ts:
+            if t is None:
+                continue
+            if not t.is_cuda or t.dtype != self.torch_dtype or not t.is_contiguous():
+                raise ValueError(f"expected a contiguous CUDA tensor of {self.torch_dtype}")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            N.lib().npfem_plan_destroy(self._h)
+            self._h = None
+
+
+class Batch:
+    """The cells advanced together; each cell's vertices are contiguous, in order."""
+
+    def __init__(self, plan: Plan, cell_mesh):
+        self.plan = plan
+        self.cell_mesh = np.ascontiguousarray(cell_mesh, np.int32)
+        h = c_void_p()
+        nv = c_int64()
+        N.check(N.lib().npfem_batch_create(plan._h, len(self.cell_mesh), _ptr(self.cell_mesh), byref(h),
+                                           byref(nv)), "npfem_batch_create")
+        self._h = h
+        self.n_cells = len(self.cell_mesh)
+        self.n_vertices = nv.value
+        sizes = np.array([m.n for m in plan.meshes])[self.cell_mesh]
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+    def _vec(self, t, name):
+        if t.shape != (self.n_vertices, 3):
+            raise ValueError(f"{name} must have shape ({self.n_vertices}, 3)")
+        self.plan._check(t)
+
+    def step(self, x, v, f, x_out=None, v_out=None, u_guess=None, stats=True, stream=None):
+        """One time step of every cell (Algorithm 1).  Returns (x_out, v_out, stats)."""
+        import torch
+        for t, nm in ((x, "x"), (v, "v"), (f, "f")):
+            self._vec(t, nm)
+        x_out = torch.empty_like(x) if x_out is None else x_out
+        v_out = torch.empty_like(v) if v_out is None else v_out
+        self._vec(x_out, "x_out")
+        self._vec(v_out, "v_out")
+        if u_guess is not None:
+            self._vec(u_guess, "u_guess")
+        st = None
+        if stats is True:
+            st = torch.empty(self.n_cells * N.CELL_STATS_DTYPE.itemsize, dtype=torch.uint8, device=x.device)
+        elif stats is not None and stats is not False:
+            st = stats
+        N.check(N.lib().npfem_step(self._h, _dptr(x), _dptr(v), _dptr(f), _dptr(x_out), _dptr(v_out),
+                                   _dptr(u_guess), _dptr(st), _stream(stream)), "npfem_step")
+        return x_out, v_out, st
+
+    @staticmethod
+    def stats_to_numpy(st) -> np.ndarray:
+        return st.cpu().numpy().view(N.CELL_STATS_DTYPE)
+
+    def eval(self, x, v, f, u, stream=None):
+        """Objective terms [n_cells, 8] and gradient at x_n + u."""
+        import torch
+        for t, nm in ((x, "x"), (v, "v"), (f, "f"), (u, "u")):
+            self._vec(t, nm)
+        grad = torch.empty_like(x)
+        terms = torch.empty((self.n_cells, N.N_TERMS), dtype=torch.float64, device=x.device)
+        N.check(N.lib().npfem_eval(self._h, _dptr(x), _dptr(v), _dptr(f), _dptr(u), _dptr(grad),
+                                   _dptr(terms), _stream(stream)), "npfem_eval")
+        return grad, terms
+
+    def drag_forces(self, x, v, zeta, rate, origin, umax=0.0, radius=1.0, axis_y=0.0, axis_z=0.0,
+                    out=None, stream=None):
+        """Stokes drag towards a shear + Poiseuille flow (the fluid's stand-in)."""
+        import torch
+        self._vec(x, "x")
+        self._vec(v, "v")
+        out = torch.empty_like(x) if out is None else out
+        for t in (zeta, rate, origin):
+            if t.dtype != torch.float64 or not t.is_cuda:
+                raise ValueError("zeta, rate, origin must be float64 CUDA tensors")
+        N.check(N.lib().npfem_drag_forces(self._h, _dptr(x), _dptr(v), _dptr(zeta), _dptr(rate), _dptr(origin),
+                                          umax, radius, axis_y, axis_z, _dptr(out), _stream(stream)),
+                "npfem_drag_forces")
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            N.lib().npfem_batch_destroy(self._h)
+            self._h = None

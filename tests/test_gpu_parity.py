@@ -1,0 +1,300 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by
+element on the same seeded inputs.
+
+Tolerances: positions within 1e-5 of the cell diameter in FP32 plans and 1e-10 in
+FP64 plans; gradients and objectives within the FP32/FP64 rounding of their largest
+terms (1e-5 / 1e-11 relative)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from rbc_inputs import workloads
+from conftest import oracle_model
+
+pytestmark = pytest.mark.gpu
+
+DT = workloads.DT_US
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-test] {request.node.nodeid}", flush=True)
+    yield
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a, dtype):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=dev())
+
+
+def make(meshes, precision="fp32", **prm):
+    from paper_1903_06479_amd import Mesh, Plan, default_params
+    params = default_params(precision=precision, **prm)
+    return Plan([Mesh(*m) for m in meshes], DT, params=params)
+
+
+def oracle_step(model, xn, vn, f, tol=1e-12, x_start=None):
+    import oracle.step as ostep
+    return ostep.step(model, xn, vn, f, ostep.Params(tol=tol), x_start=x_start)
+
+
+# ---- the MFMA product with the dense inverses -------------------------------------
+
+@pytest.mark.parametrize("precision,n", [("fp32", 642), ("fp64", 258), ("fp32", 258), ("fp64", 642)])
+def test_apply_inverse_matches_oracle(precision, n):
+    m = oracle_model(n)
+    plan = make([(m.X, m.tris)], precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    npad = plan.n_pad(0)
+    rows = 53                                        # spans several 48-row launches + a ragged tail
+    rng = np.random.default_rng(n)
+    q = np.zeros((rows, npad))
+    q[:, :n] = rng.standard_normal((rows, n))
+    tol = 2e-6 if precision == "fp32" else 1e-13
+    for which, ref in ((0, np.linalg.solve(m.Ht, q[:, :n].T).T),
+                       (1, DT * DT * np.linalg.solve(m.Mt, q[:, :n].T).T)):
+        out = plan.apply_inverse(0, which, T(q, dt)).cpu().numpy().astype(np.float64)
+        scale = np.abs(ref).max()
+        assert np.abs(out[:, :n] - ref).max() <= tol * scale * np.sqrt(n)
+        assert np.abs(out[:, n:]).max() == 0.0
+
+
+# ---- objective and gradient -------------------------------------------------------
+
+def eval_case(n, precision, n_cells=6, seed=3):
+    import oracle.step as ostep
+    from paper_1903_06479_amd import Batch
+    m = oracle_model(n)
+    rng = np.random.default_rng(seed)
+    plan = make([(m.X, m.tris)], precision)
+    batch = Batch(plan, np.zeros(n_cells, np.int32))
+    dt = plan.torch_dtype
+    xs, vs, fs, us = [], [], [], []
+    for c in range(n_cells):
+        xs.append(m.X @ workloads.random_rotation(rng).T + 0.05 * rng.standard_normal(m.X.shape))
+        vs.append(0.01 * rng.standard_normal(m.X.shape))
+        fs.append(2.0 * rng.standard_normal(m.X.shape))
+        us.append(2e-3 * rng.standard_normal(m.X.shape))
+    cat = lambda a: np.concatenate(a)
+    # inputs rounded to the plan's precision first, so both sides see the same numbers
+    rnd = (lambda a: a.astype(np.float32).astype(np.float64)) if precision == "fp32" else (lambda a: a)
+    xs, vs, fs, us = ([rnd(a) for a in arr] for arr in (xs, vs, fs, us))
+    grad, terms = batch.eval(T(cat(xs), dt), T(cat(vs), dt), T(cat(fs), dt), T(cat(us), dt))
+    grad = grad.cpu().numpy().astype(np.float64)
+    terms = terms.cpu().numpy()
+    out = []
+    for c in range(n_cells):
+        obj = ostep.Objective(m, xs[c], vs[c], fs[c])
+        x = xs[c] + us[c]
+        g, gr, noise = obj(x)
+        w = obj.y - obj.x_n
+        g_u = g - 0.5 * np.sum(w * (m.Mt @ w)) / DT ** 2     # drop the constant of the inertial term
+        Mu = m.mass[:, None] * us[c] / DT ** 2
+        scale = max(np.abs(Mu).max(), np.abs(obj.b).max(), np.abs(gr - Mu + obj.b).max())
+        out.append(dict(g=g_u, grad=gr, noise=noise, resid=obj.residual(x, gr), scale=scale,
+                        gpu_grad=grad[c * n:(c + 1) * n], gpu_terms=terms[c]))
+    return out
+
+
+@pytest.mark.parametrize("precision,n,tol", [("fp32", 642, 2e-5), ("fp32", 258, 2e-5), ("fp64", 258, 1e-11),
+                                             ("fp64", 642, 1e-11)])
+def test_eval_matches_oracle(precision, n, tol):
+    for c in eval_case(n, precision):
+        assert np.abs(c["gpu_grad"] - c["grad"]).max() <= tol * c["scale"]
+        assert abs(c["gpu_terms"][0] - c["g"]) <= tol * c["noise"]
+        assert abs(c["gpu_terms"][7] - c["resid"]) <= max(tol * 10, 1e-3 * c["resid"])
+
+
+# ---- the step -----------------------------------------------------------------------
+
+def run_step(plan, cell_mesh, x, v, f, **kw):
+    from paper_1903_06479_amd import Batch
+    batch = Batch(plan, cell_mesh)
+    dt = plan.torch_dtype
+    xo, vo, st = batch.step(T(x, dt), T(v, dt), T(f, dt), **kw)
+    torch.cuda.synchronize()
+    return (xo.cpu().numpy().astype(np.float64), vo.cpu().numpy().astype(np.float64),
+            batch.stats_to_numpy(st), batch)
+
+
+def rounded(a, precision):
+    return a.astype(np.float32).astype(np.float64) if precision == "fp32" else a
+
+
+def test_step_fp32_shear_matches_oracle():
+    """One FP32 step of 21 perturbed 642-vertex cells in drag towards shear flows
+    (several tiles and a ragged tail) against the converged FP64 oracle."""
+    from paper_1903_06479_amd import CONVERGED
+    b = workloads.shear(n_cells=21, seed=1002)
+    X, Tr = b.meshes[642]
+    m = oracle_model(642)
+    x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
+    f = rounded(workloads.drag_forces(b, x, v), "fp32")
+    plan = make([(X, Tr)], "fp32", cells_per_tile=5)
+    xo, vo, st, _ = run_step(plan, np.zeros(21, np.int32), x, v, f)
+    assert np.all(st["status"] == CONVERGED), st
+    D = np.ptp(X[:, 0])
+    for c in range(21):
+        s = b.cell_slice(c)
+        xr, vr, info = oracle_step(m, x[s], v[s], f[s])
+        assert np.abs(xo[s] - xr).max() <= 1e-5 * D
+        ur = xr - x[s]
+        assert np.abs((xo[s] - x[s]) - ur).max() <= 1e-3 * np.abs(ur).max() + 1e-6
+        assert np.abs(vo[s] - vr).max() <= 1e-3 * np.abs(vr).max() + 1e-5
+
+
+def test_step_tile_size_and_repeat_bitwise():
+    """Cells never interact, so the result of a cell must not depend on which tile it
+    lands in, and two runs must agree bit for bit (no atomics in the arithmetic)."""
+    b = workloads.shear(n_cells=23, seed=5)
+    X, Tr = b.meshes[642]
+    x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
+    f = rounded(workloads.drag_forces(b, x, v), "fp32")
+    ref = None
+    for tcells in (1, 5, 16, 21, 16):
+        plan = make([(X, Tr)], "fp32", cells_per_tile=tcells)
+        xo, vo, st, _ = run_step(plan, np.zeros(23, np.int32), x, v, f)
+        if ref is None:
+            ref = (xo, vo, st["iterations"])
+        else:
+            np.testing.assert_array_equal(xo, ref[0])
+            np.testing.assert_array_equal(vo, ref[1])
+            np.testing.assert_array_equal(st["iterations"], ref[2])
+
+
+def test_step_fp64_stretch_trajectory():
+    """The optical-tweezers load on one 258-vertex cell, FP64, ramped to 200 pN over
+    20 steps; each side follows its own trajectory; positions within 1e-10 D."""
+    from paper_1903_06479_amd import CONVERGED
+    b = workloads.stretch()
+    X, Tr = b.meshes[258]
+    m = oracle_model(258)
+    plan = make([(X, Tr)], "fp64", tol=1e-10)
+    from paper_1903_06479_amd import Batch
+    batch = Batch(plan, np.zeros(1, np.int32))
+    xg, vg = T(X, torch.float64), T(np.zeros_like(X), torch.float64)
+    xr, vr = X.copy(), np.zeros_like(X)
+    D = np.ptp(X[:, 0])
+    for k in range(1, 21):
+        f = workloads.stretch_forces(b, k, total_steps=20)
+        xg, vg, st = batch.step(xg, vg, T(f, torch.float64))
+        xr, vr, _ = oracle_step(m, xr, vr, f)
+        s = batch.stats_to_numpy(st)
+        assert s["status"][0] == CONVERGED
+        err = np.abs(xg.cpu().numpy() - xr).max() / D
+        assert err <= 1e-10, (k, err)
+    assert np.ptp(xr[:, 0]) > D                    # it did stretch
+
+
+def test_step_uneven_mesh_mix():
+    """258/642/2562-vertex cells in one launch (FP32) against the oracle."""
+    from paper_1903_06479_amd import CONVERGED
+    b = workloads.uneven(n_cells=200, cells=np.arange(12))
+    sizes = sorted(b.meshes)
+    meshes = [b.meshes[k] for k in sizes]
+    cm = np.array([sizes.index(int(k)) for k in b.cell_nverts], np.int32)
+    x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
+    f = rounded(workloads.drag_forces(b, x, v, step=0), "fp32")
+    plan = make(meshes, "fp32")
+    xo, vo, st, _ = run_step(plan, cm, x, v, f)
+    assert np.all(st["status"] == CONVERGED), st
+    for c in range(b.n_cells):
+        s = b.cell_slice(c)
+        n = int(b.cell_nverts[c])
+        m = oracle_model(n)
+        xr, _, _ = oracle_step(m, x[s], v[s], f[s])
+        assert np.abs(xo[s] - xr).max() <= 1e-5 * np.ptp(m.X[:, 0]), (c, n)
+
+
+def test_rest_cells_stay_put_and_nonfinite_is_flagged():
+    from paper_1903_06479_amd import CONVERGED, NONFINITE
+    m = oracle_model(642)
+    x = np.concatenate([m.X, m.X + 1.0, m.X])
+    x[2 * 642 + 7, 1] = np.nan                       # third cell poisoned
+    v = np.zeros_like(x)
+    f = np.zeros_like(x)
+    plan = make([(m.X, m.tris)], "fp32", cells_per_tile=5)
+    xo, vo, st, _ = run_step(plan, np.zeros(3, np.int32), rounded(x, "fp32"), v, f)
+    assert st["status"][0] == CONVERGED and st["iterations"][0] == 0
+    np.testing.assert_array_equal(xo[:642], rounded(m.X, "fp32"))
+    assert np.abs(vo[:1284]).max() == 0.0
+    assert st["status"][2] == NONFINITE
+    np.testing.assert_array_equal(np.isnan(xo[1284:]), np.isnan(x[1284:]))
+
+
+def test_user_guess_does_not_change_the_solution():
+    b = workloads.shear(n_cells=5, seed=9)
+    X, Tr = b.meshes[642]
+    m = oracle_model(642)
+    x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
+    f = rounded(workloads.drag_forces(b, x, v), "fp32")
+    plan = make([(X, Tr)], "fp32")
+    dt = torch.float32
+    ref = [oracle_step(m, x[b.cell_slice(c)], v[b.cell_slice(c)], f[b.cell_slice(c)])[0] for c in range(5)]
+    u_exact = np.concatenate(ref) - x
+    u_pert = u_exact + 1e-3 * np.random.default_rng(0).standard_normal(x.shape)
+    D = np.ptp(X[:, 0])
+    for guess in (u_exact, u_pert):
+        xo, _, st, _ = run_step(plan, np.zeros(5, np.int32), x, v, f, u_guess=T(guess, dt))
+        assert np.abs(xo - np.concatenate(ref)).max() <= 1e-5 * D
+    assert st["iterations"].max() >= 1
+
+
+def test_momentum_balance_on_gpu():
+    """sum m v_{n+1} = sum m v_n + h sum F_ext for every cell (internal forces and the
+    Rayleigh term cancel; the dissipation keeps momentum)."""
+    b = workloads.shear(n_cells=8, seed=11)
+    X, Tr = b.meshes[642]
+    rng = np.random.default_rng(1)
+    x, v = b.x, 0.01 * rng.standard_normal(b.x.shape)
+    f = 3.0 * rng.standard_normal(b.x.shape)
+    plan = make([(X, Tr)], "fp64", tol=1e-10)
+    xo, vo, st, _ = run_step(plan, np.zeros(8, np.int32), x, v, f)
+    mass = plan.masses(0)[:, None]
+    for c in range(8):
+        s = b.cell_slice(c)
+        lhs = (mass * vo[s]).sum(0)
+        rhs = (mass * v[s]).sum(0) + DT * f[s].sum(0)
+        assert np.abs(lhs - rhs).max() <= 1e-8 * np.abs(mass * v[s]).sum()
+
+
+def test_multistep_fp32_trajectory():
+    """Ten coupled steps (forces recomputed from each side's own state) of four cells."""
+    b = workloads.throughput(n_cells=100000, cells=[0, 1, 2, 3])
+    X, Tr = b.meshes[642]
+    m = oracle_model(642)
+    from paper_1903_06479_amd import Batch
+    plan = make([(X, Tr)], "fp32")
+    batch = Batch(plan, np.zeros(4, np.int32))
+    x = rounded(b.x, "fp32")
+    xg, vg = T(x, torch.float32), T(np.zeros_like(x), torch.float32)
+    xr, vr = x.copy(), np.zeros_like(x)
+    D = np.ptp(X[:, 0])
+    for k in range(10):
+        fg = workloads.drag_forces(b, xg.cpu().numpy().astype(np.float64), vg.cpu().numpy().astype(np.float64))
+        fr = workloads.drag_forces(b, xr, vr)
+        xg, vg, _ = batch.step(xg, vg, T(fg, torch.float32))
+        for c in range(4):
+            s = b.cell_slice(c)
+            xr[s], vr[s], _ = oracle_step(m, xr[s], vr[s], fr[s])
+    assert np.abs(xg.cpu().numpy() - xr).max() <= 1e-5 * D
+
+
+def test_drag_forces_kernel_matches_inputs_module():
+    b = workloads.throughput(n_cells=100000, cells=[5, 6, 7])
+    X, Tr = b.meshes[642]
+    from paper_1903_06479_amd import Batch
+    plan = make([(X, Tr)], "fp64")
+    batch = Batch(plan, np.zeros(3, np.int32))
+    v = 0.01 * np.random.default_rng(2).standard_normal(b.x.shape)
+    ref = workloads.drag_forces(b, b.x, v)
+    p = b.poiseuille
+    f = batch.drag_forces(T(b.x, torch.float64), T(v, torch.float64),
+                          T(np.full(3, workloads.drag_coefficient(642)), torch.float64),
+                          T(b.shear_rate, torch.float64), T(b.origin, torch.float64),
+                          p["umax"], p["radius"], p["axis_y"], p["axis_z"])
+    np.testing.assert_allclose(f.cpu().numpy(), ref, rtol=1e-12, atol=1e-12)
