@@ -384,8 +384,10 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
 // Tile product Out^T = In^T A with A = A^T (n_pad x n_pad), In^T / Out^T (rows x n_pad)
 // on the matrix cores.  16x16 output blocks; each wave owns every fourth column block
 // and all (<= 4) row blocks, so an A fragment is loaded once per wave and reused.
-// Both operands are read as 16-byte vectors along k (A is symmetric, so its column
-// fragment is a row fragment).
+// Both operands are read as vectors along k (A is symmetric, so its column fragment is
+// a row fragment).  Operand lanes: lane l supplies row l%16, k-slot l/16 of A_op and
+// k-slot l/16, column l%16 of B_op; result slot i of lane l is row 4(l/16) + i (f32)
+// or row 4i + l/16 (f64), column l%16 (measured on gfx950).
 // ---------------------------------------------------------------------------------
 __device__ inline void tile_gemm(const float* __restrict__ A, int np, const float* __restrict__ In,
                                  float* __restrict__ Out, int rows) {
@@ -457,7 +459,7 @@ __device__ inline void tile_gemm(const double* __restrict__ A, int np, const dou
       if (mb < mb_n) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int r = mb * 16 + 4 * kq + i;
+          const int r = mb * 16 + 4 * i + kq;   // f64 result: slot i of lane l is row 4i + l/16
           if (r < rows) Out[(size_t)r * np + n0 + l16] = acc[mb][i];
         }
       }
@@ -672,7 +674,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
       const int hn = cs.hist_n, head = cs.hist_head;
       // two-loop recursion, second half: z = r + sum_i s_i (alpha_i - beta_i), oldest first
       for (int p = 0; p < hn; ++p) {
-        const int slot = (head - hn + p + 2 * kMaxHistory) % m;
+        const int slot = (head - hn + p + m) % m;       // p = 0 is the oldest pair
         const Real* S = tl.vec(VS0 + slot, j);
         const Real* Y = tl.vec(VS0 + m + slot, j);
         const double bta = cs.rho[slot] * dot_vec(Y, D, len, red);
@@ -770,7 +772,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
       for (int e = tid(); e < len; e += kBlock) Q[e] = G[e];
       __syncthreads();
       for (int p = hn2 - 1; p >= 0; --p) {
-        const int slot = (head2 - hn2 + p + 2 * kMaxHistory) % m;
+        const int slot = (head2 - hn2 + p + m) % m;
         const Real* S = tl.vec(VS0 + slot, j);
         const Real* Y = tl.vec(VS0 + m + slot, j);
         const double rho = (p == hn2 - 1 && store) ? 1.0 / dots[0] : CS[j].rho[slot];
@@ -913,6 +915,7 @@ hipError_t occupancy(int* blocks_per_cu, size_t lds) {
 
 template <typename Real>
 hipError_t launch_step(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s, int* counter) {
+  (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
   hipLaunchKernelGGL(step_kernel<Real>, dim3(grid), dim3(kBlock), lds, s, a);
   return hipGetLastError();
@@ -921,6 +924,7 @@ hipError_t launch_step(const StepArgs<Real>& a, int grid, size_t lds, hipStream_
 template <typename Real>
 hipError_t launch_eval(const StepArgs<Real>& a, int n_cells, const Real* u, Real* grad, double* terms,
                        size_t lds, hipStream_t s) {
+  (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
   hipLaunchKernelGGL(eval_kernel<Real>, dim3(n_cells), dim3(kBlock), lds, s, a, u, grad, terms, a.work);
   return hipGetLastError();
 }
@@ -928,6 +932,7 @@ hipError_t launch_eval(const StepArgs<Real>& a, int n_cells, const Real* u, Real
 template <typename Real>
 hipError_t launch_apply_inverse(const Real* A, int n_pad, const Real* in, Real* out, int rows,
                                 hipStream_t s) {
+  (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
   hipLaunchKernelGGL(apply_inverse_kernel<Real>, dim3((rows + 47) / 48), dim3(kBlock), 0, s, A, n_pad,
                      in, out, rows);
   return hipGetLastError();
@@ -938,6 +943,7 @@ hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, c
                        const int* mesh_n, int n_cells, const double* zeta, const double* rate,
                        const double* origin, double umax, double radius, double ay, double az, Real* f,
                        hipStream_t s) {
+  (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
   hipLaunchKernelGGL(drag_kernel<Real>, dim3(n_cells), dim3(kBlock), 0, s, x, v, cell_voff, cell_mesh,
                      mesh_n, zeta, rate, origin, umax, radius, ay, az, f);
   return hipGetLastError();

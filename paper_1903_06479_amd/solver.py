@@ -69,9 +69,9 @@ class Mesh:
         return out
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            N.lib().npfem_mesh_destroy(self._h)
-            self._h = None
+        h, self._h = getattr(self, "_h", None), None
+        if h and N is not None and N._lib is not None:
+            N._lib.npfem_mesh_destroy(h)
 
 
 class Plan:
@@ -125,9 +125,9 @@ class Plan:
                 raise ValueError(f"expected a contiguous CUDA tensor of {self.torch_dtype}")
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            N.lib().npfem_plan_destroy(self._h)
-            self._h = None
+        h, self._h = getattr(self, "_h", None), None
+        if h and N is not None and N._lib is not None:
+            N._lib.npfem_plan_destroy(h)
 
 
 class Batch:
@@ -202,6 +202,6 @@ class Batch:
         return out
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            N.lib().npfem_batch_destroy(self._h)
-            self._h = None
+        h, self._h = getattr(self, "_h", None), None
+        if h and N is not None and N._lib is not None:
+            N._lib.npfem_batch_destroy(h)

@@ -211,19 +211,31 @@ def test_step_uneven_mesh_mix():
 
 
 def test_rest_cells_stay_put_and_nonfinite_is_flagged():
+    """Zero force at the rest shape: a cell at rest with v = 0, F = 0 converges at the
+    first guess and does not move (the mesh is given in FP32-representable coordinates,
+    so the FP32 inputs are exactly the rest shape).  A cell with a NaN coordinate is
+    flagged and returned unchanged without disturbing its tile mates."""
     from paper_1903_06479_amd import CONVERGED, NONFINITE
     m = oracle_model(642)
-    x = np.concatenate([m.X, m.X + 1.0, m.X])
-    x[2 * 642 + 7, 1] = np.nan                       # third cell poisoned
+    X32 = rounded(m.X, "fp32")
+    # cells: exact rest, a translated copy (re-rounded in FP32, so strained at the 1e-7
+    # level), exact rest, poisoned
+    x = np.concatenate([X32, rounded(X32 + 1.0, "fp32"), X32, X32])
+    x[3 * 642 + 7, 1] = np.nan
     v = np.zeros_like(x)
     f = np.zeros_like(x)
-    plan = make([(m.X, m.tris)], "fp32", cells_per_tile=5)
-    xo, vo, st, _ = run_step(plan, np.zeros(3, np.int32), rounded(x, "fp32"), v, f)
-    assert st["status"][0] == CONVERGED and st["iterations"][0] == 0
-    np.testing.assert_array_equal(xo[:642], rounded(m.X, "fp32"))
-    assert np.abs(vo[:1284]).max() == 0.0
-    assert st["status"][2] == NONFINITE
-    np.testing.assert_array_equal(np.isnan(xo[1284:]), np.isnan(x[1284:]))
+    plan = make([(X32, m.tris)], "fp32", cells_per_tile=5)
+    xo, vo, st, _ = run_step(plan, np.zeros(4, np.int32), x, v, f)
+    for c in (0, 2):
+        s = slice(642 * c, 642 * (c + 1))
+        assert st["status"][c] == CONVERGED and st["iterations"][c] == 0
+        np.testing.assert_array_equal(xo[s], x[s])
+        assert np.abs(vo[s]).max() == 0.0
+    assert st["status"][1] == CONVERGED
+    assert np.abs(xo[642:1284] - x[642:1284]).max() <= 1e-6 * np.ptp(X32[:, 0])
+    assert st["status"][3] == NONFINITE
+    np.testing.assert_array_equal(np.isnan(xo[1926:]), np.isnan(x[1926:]))
+    np.testing.assert_array_equal(xo[1926:][~np.isnan(x[1926:])], x[1926:][~np.isnan(x[1926:])])
 
 
 def test_user_guess_does_not_change_the_solution():
