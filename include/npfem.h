@@ -90,6 +90,10 @@ typedef struct {
   double noise_factor;      /* line search accepts increases below noise_factor*eps*sum|terms| */
   int32_t cells_per_tile;   /* cells sharing one H~^-1 product (1..21); 0 = automatic */
   int32_t grid_blocks;      /* persistent workgroups; 0 = automatic */
+  int32_t inverse_bf16;     /* FP32 plans: 1 = apply H~^-1 and h^2 M~^-1 as an exact FP32
+                               diagonal plus a BF16 off-diagonal part on the matrix cores
+                               (they only precondition and start the iteration, so the
+                               solution is unchanged); 0 = FP32 matrix cores */
 } npfem_solver_params;
 
 /* Per-cell result of a step (device array filled by npfem_step). */
@@ -142,7 +146,7 @@ npfem_status npfem_mesh_rest_data(const npfem_mesh *mesh, double *vor_area, doub
  * (eq. fullyDeveloped_g), M~ = M + beta h^2 L' (eq. preOptimizationNewton with Rayleigh
  * damping) and H~ = M~/h^2 + L + K_mat (section 2.1.1), Cholesky-factors M~ and H~
  * (NPFEM_E_NOT_SPD on failure), and uploads the dense inverses h^2 M~^-1 and H~^-1
- * in the plan's precision, zero-padded to a multiple of 16.  A new dt needs a new plan.
+ * in the plan's precision, zero-padded to a multiple of 32.  A new dt needs a new plan.
  * meshes: host array of n_meshes handles, which must outlive the plan.
  */
 npfem_status npfem_plan_create(int32_t hip_device, const npfem_mesh *const *meshes,
@@ -196,7 +200,7 @@ npfem_status npfem_eval(npfem_batch *batch, const void *x, const void *v, const 
  * out[r][:] = A in[r][:] for r < rows, with A = H~^-1 (which = 0) or h^2 M~^-1
  * (which = 1) of mesh type mesh_index: the MFMA product the step applies once per
  * iteration (section 2.1.1).  in, out: device [rows][n_pad] row-major in the plan's
- * precision, n_pad = n_verts rounded up to 16 (padding entries of `in` must be zero).
+ * precision, n_pad = n_verts rounded up to 32 (padding entries of `in` must be zero).
  * n_pad_out (may be NULL) receives n_pad.  Exposed for testing and measurement.
  */
 npfem_status npfem_apply_inverse(npfem_plan *plan, int32_t mesh_index, int32_t which,

@@ -21,7 +21,8 @@ class Material(ctypes.Structure):
 class SolverParams(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("lbfgs_m", c_int32), ("max_iter", c_int32),
                 ("max_halvings", c_int32), ("tol", c_double), ("c1", c_double),
-                ("noise_factor", c_double), ("cells_per_tile", c_int32), ("grid_blocks", c_int32)]
+                ("noise_factor", c_double), ("cells_per_tile", c_int32), ("grid_blocks", c_int32),
+                ("inverse_bf16", c_int32)]
 
 
 CELL_STATS_DTYPE = np.dtype([("iterations", np.int32), ("evaluations", np.int32),

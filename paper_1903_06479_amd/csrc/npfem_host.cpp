@@ -8,6 +8,7 @@
 #include <memory>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -106,6 +107,14 @@ std::vector<double> spd_inverse(const std::vector<double>& L, int n) {
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------
@@ -165,6 +174,7 @@ void npfem_solver_params_default(npfem_solver_params* p) {
   p->noise_factor = 8.0;
   p->cells_per_tile = 0;
   p->grid_blocks = 0;
+  p->inverse_bf16 = 0;
 }
 
 npfem_status npfem_mesh_create(int32_t n, const double* xyz, int32_t nt, const int32_t* tris,
@@ -404,6 +414,29 @@ npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>&
   if ((s = p->buf.upload(m->nb_ptr.data(), m->nb_ptr.size(), &d.nb_ptr))) return s;
   if ((s = p->buf.upload(m->nb_idx.data(), m->nb_idx.size(), &d.nb_idx))) return s;
   if ((s = p->buf.upload(w.data(), w.size(), &d.nb_w))) return s;
+  // padded (ELL) copies of the neighbour and corner lists, column q of vertex i at q*n_pad + i
+  int nbd = 0, vcd = 0;
+  for (int i = 0; i < n; ++i) {
+    nbd = std::max(nbd, m->nb_ptr[i + 1] - m->nb_ptr[i]);
+    vcd = std::max(vcd, m->vc_ptr[i + 1] - m->vc_ptr[i]);
+  }
+  std::vector<int> nbe((size_t)nbd * np), vce((size_t)vcd * np, -1);
+  std::vector<Real> nbwe((size_t)nbd * np, Real(0));
+  for (int i = 0; i < np; ++i)
+    for (int q = 0; q < nbd; ++q) nbe[(size_t)q * np + i] = i < n ? i : 0;
+  for (int i = 0; i < n; ++i) {
+    for (int q = m->nb_ptr[i]; q < m->nb_ptr[i + 1]; ++q) {
+      const size_t o = (size_t)(q - m->nb_ptr[i]) * np + i;
+      nbe[o] = m->nb_idx[q];
+      nbwe[o] = Real(m->nb_w[q]);
+    }
+    for (int q = m->vc_ptr[i]; q < m->vc_ptr[i + 1]; ++q) vce[(size_t)(q - m->vc_ptr[i]) * np + i] = m->vc_idx[q];
+  }
+  d.nb_deg = nbd;
+  d.vc_deg = vcd;
+  if ((s = p->buf.upload(nbe.data(), nbe.size(), &d.nb_ell))) return s;
+  if ((s = p->buf.upload(nbwe.data(), nbwe.size(), &d.nbw_ell))) return s;
+  if ((s = p->buf.upload(vce.data(), vce.size(), &d.vc_ell))) return s;
   if ((s = p->buf.upload(va.data(), va.size(), &d.vor_area))) return s;
   if ((s = p->buf.upload(e0.data(), e0.size(), &d.ell0))) return s;
   if ((s = p->buf.upload(ms.data(), ms.size(), &d.mass))) return s;
@@ -411,6 +444,25 @@ npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>&
   auto Mi = pad_matrix<Real>(minv_h2, n, np, 1.0);
   if ((s = p->buf.upload(H.data(), H.size(), &d.hinv))) return s;
   if ((s = p->buf.upload(Mi.data(), Mi.size(), &d.minv))) return s;
+  d.hinv_bf = d.minv_bf = nullptr;
+  d.hinv_diag = d.minv_diag = nullptr;
+  if (p->prm.inverse_bf16 && p->precision == NPFEM_FP32) {
+    // exact FP32 diagonal + BF16 off-diagonal part (zero diagonal, zero padding)
+    for (int which = 0; which < 2; ++which) {
+      const std::vector<double>& A = which == 0 ? hinv : minv_h2;
+      std::vector<uint16_t> off((size_t)np * np, 0);
+      std::vector<float> dg(np, 0.0f);
+      for (int i = 0; i < n; ++i) {
+        dg[i] = (float)A[(size_t)i * n + i];
+        for (int j = 0; j < n; ++j)
+          if (j != i) off[(size_t)i * np + j] = to_bf16((float)A[(size_t)i * n + j]);
+      }
+      const uint16_t** po = which == 0 ? &d.hinv_bf : &d.minv_bf;
+      const float** pd = which == 0 ? &d.hinv_diag : &d.minv_diag;
+      if ((s = p->buf.upload(off.data(), off.size(), po))) return s;
+      if ((s = p->buf.upload(dg.data(), dg.size(), pd))) return s;
+    }
+  }
   d.V0 = m->V0;
   d.floor_force = mp.floor_force;
   return NPFEM_OK;
@@ -419,10 +471,10 @@ npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>&
 // Largest triangle chunk for which the step's LDS fits the budget.
 template <typename Real>
 int choose_chunk(int np, int nt, size_t budget) {
-  if (lds_bytes<Real>(np, nt) <= budget) return nt;
+  if (lds_bytes<Real>(np, nt, 0) <= budget) return nt;
   int lo = 0;
   for (int ch = nt; ch >= 64; ch -= 64)
-    if (lds_bytes<Real>(np, ch) <= budget) { lo = ch; break; }
+    if (lds_bytes<Real>(np, ch, 0) <= budget) { lo = ch; break; }
   return lo;
 }
 
@@ -475,7 +527,7 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
     MeshPlan& mp = p->meshes[mi];
     mp.mesh = m;
     const int n = m->n;
-    mp.n_pad = round_up(n, 16);
+    mp.n_pad = round_up(n, 32);
     // two workgroups per CU when the whole triangle list fits in half the LDS
     const size_t half = 80 * 1024 - 512;
     mp.chunk = fp64 ? choose_chunk<double>(mp.n_pad, m->nt, half) : choose_chunk<float>(mp.n_pad, m->nt, half);
@@ -598,7 +650,7 @@ StepArgs<Real> make_args(npfem_batch* b) {
   a.mat = {p->mat.B, p->mat.C, p->mat.D, p->mat.k_bend, p->mat.k_volume, p->mat.beta, p->mat.kappa};
   const double eps = std::is_same<Real, float>::value ? 1.1920928955078125e-07 : 2.220446049250313e-16;
   a.sol = {p->dt, p->prm.tol, p->prm.c1, p->prm.noise_factor * eps, p->prm.lbfgs_m, p->prm.max_iter,
-           p->prm.max_halvings};
+           p->prm.max_halvings, (p->prm.inverse_bf16 && std::is_same<Real, float>::value) ? 1 : 0};
   a.tiles = b->tiles;
   a.tile_cells = b->tile_cells;
   a.cell_voff = b->cell_voff;
@@ -618,7 +670,8 @@ template <typename Real>
 npfem_status batch_setup(npfem_batch* b) {
   npfem_plan* p = b->plan;
   size_t lds = 0;
-  for (auto& mp : p->meshes) lds = std::max(lds, lds_bytes<Real>(mp.n_pad, mp.chunk));
+  const int stage_rows = (p->prm.inverse_bf16 && std::is_same<Real, float>::value) ? 16 * ((3 * b->T + 15) / 16) : 0;
+  for (auto& mp : p->meshes) lds = std::max(lds, lds_bytes<Real>(mp.n_pad, mp.chunk, stage_rows));
   b->lds = lds;
   HIP_TRY(set_lds_limit<Real>(lds));
   int per_cu = 0;
@@ -795,6 +848,11 @@ npfem_status npfem_apply_inverse(npfem_plan* p, int32_t mi, int32_t which, const
     const double* A = which == 0 ? mp.dev64.hinv : mp.dev64.minv;
     HIP_TRY(launch_apply_inverse<double>(A, mp.n_pad, static_cast<const double*>(in), static_cast<double*>(out),
                                          rows, s));
+  } else if (p->prm.inverse_bf16) {
+    const uint16_t* A = which == 0 ? mp.dev32.hinv_bf : mp.dev32.minv_bf;
+    const float* dg = which == 0 ? mp.dev32.hinv_diag : mp.dev32.minv_diag;
+    HIP_TRY(launch_apply_inverse_bf16(A, dg, mp.n_pad, static_cast<const float*>(in), static_cast<float*>(out),
+                                      rows, s));
   } else {
     const float* A = which == 0 ? mp.dev32.hinv : mp.dev32.minv;
     HIP_TRY(launch_apply_inverse<float>(A, mp.n_pad, static_cast<const float*>(in), static_cast<float*>(out),

@@ -15,7 +15,7 @@ constexpr int kTerms = 8;          // objective terms reported by npfem_eval
 // Rest data of one mesh type on the device (precision Real).
 template <typename Real>
 struct MeshDev {
-  int n, nt, n_pad;            // vertices, triangles, n rounded up to 16
+  int n, nt, n_pad;            // vertices, triangles, n rounded up to 32
   int chunk;                   // triangles per LDS corner chunk
   const int* tri;              // [nt][3]
   const double* dminv;         // [nt][4] D_m^-1 row-major (FP64 in every precision: the
@@ -26,11 +26,19 @@ struct MeshDev {
   const int* nb_ptr;           // [n+1] vertex -> neighbours
   const int* nb_idx;
   const Real* nb_w;            // cotangent weight (cot a + cot b)/2 of each neighbour edge
+  int nb_deg, vc_deg;          // padded widths of the ELL lists below (max degree / valence)
+  const int* nb_ell;           // [nb_deg][n_pad] neighbour of vertex i (i itself as padding)
+  const Real* nbw_ell;         // [nb_deg][n_pad] its cotangent weight (0 as padding)
+  const int* vc_ell;           // [vc_deg][n_pad] incident corner 3t + k (-1 as padding)
   const Real* vor_area;        // [n] mixed Voronoi area A_i
   const Real* ell0;            // [n] |l0_i|
   const Real* mass;            // [n]
   const Real* hinv;            // [n_pad][n_pad] H~^-1
   const Real* minv;            // [n_pad][n_pad] h^2 M~^-1
+  const uint16_t* hinv_bf;     // [n_pad][n_pad] off-diagonal part of H~^-1, BF16 bits (or null)
+  const uint16_t* minv_bf;     // [n_pad][n_pad] off-diagonal part of h^2 M~^-1, BF16 bits
+  const float* hinv_diag;      // [n_pad] diagonal of H~^-1
+  const float* minv_diag;      // [n_pad] diagonal of h^2 M~^-1
   double V0;                   // rest volume
   double floor_force;          // B sqrt(A0): force floor of the residual
 };
@@ -42,6 +50,7 @@ struct MaterialDev {
 struct SolverDev {
   double h, tol, c1, noise;    // noise = noise_factor * machine epsilon
   int m, max_iter, max_halvings;
+  int bf16;                    // products with the inverses on the BF16 matrix cores
 };
 
 // Per-cell scalar state of the step, kept in the workspace between kernel phases.
@@ -52,6 +61,7 @@ struct CellState {
   double resid;
   double rho[kMaxHistory];
   double alpha[kMaxHistory];
+  double SY[kMaxHistory][kMaxHistory];   // s_i . y_j over the history slots
   int hist_n, hist_head, iter, evals, status, active, retry, halvings;
 };
 
@@ -96,13 +106,16 @@ hipError_t launch_eval(const StepArgs<Real>& a, int n_cells, const Real* u, Real
 template <typename Real>
 hipError_t launch_apply_inverse(const Real* A, int n_pad, const Real* in, Real* out, int rows,
                                 hipStream_t s);
+hipError_t launch_apply_inverse_bf16(const uint16_t* A, const float* diag, int n_pad, const float* in,
+                                     float* out, int rows, hipStream_t s);
 template <typename Real>
 hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, const int* cell_mesh,
                        const int* mesh_n, int n_cells, const double* zeta, const double* rate,
                        const double* origin, double umax, double radius, double ay, double az,
                        Real* f, hipStream_t s);
+// LDS of the step kernel; stage_rows > 0: rows of the BF16 tile product staged in LDS.
 template <typename Real>
-size_t lds_bytes(int n_pad, int chunk);
+size_t lds_bytes(int n_pad, int chunk, int stage_rows);
 template <typename Real>
 hipError_t set_lds_limit(size_t bytes);
 template <typename Real>

@@ -16,6 +16,7 @@
 
 #include <cfloat>
 #include <cmath>
+#include <type_traits>
 
 #include "npfem_internal.h"
 
@@ -25,20 +26,44 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <typename Real> struct Eps;
 template <> struct Eps<float> { static constexpr double v = 1.1920928955078125e-07; };
 template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
 
-// LDS: [red: 4 waves x 16 doubles][ints: 32][xn 3*np][ut 3*np][work max(3*np, 9*chunk)]
-constexpr int kRedDoubles = 64;
-constexpr int kLdsHeader = kRedDoubles * 8 + 32 * 4;
+// LDS: [red: 4 waves x 32 doubles][32 doubles][ints: 32][xn 3*np][ut 3*np][work max(3*np, 12*chunk)];
+// during the BF16 tile product the region from xn on holds the tile's rows in BF16.
+constexpr int kRedStride = 32;
+constexpr int kRedDoubles = 4 * kRedStride;
+constexpr int kLdsHeader = kRedDoubles * 8 + 32 * 8 + 32 * 4;   // reduction, picked sums, ints
 
 __device__ inline int tid() { return threadIdx.x; }
 
-// Sum N doubles over the workgroup; fixed order, so deterministic.
+// 16-byte vectors of the plan's precision for the per-cell vector passes (the SoA
+// vectors have 3 n_pad elements, a multiple of 96, so every pass is whole vectors).
+template <typename Real> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); static constexpr int W = 4; };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); static constexpr int W = 2; };
+template <typename Real>
+__device__ inline typename Vec16<Real>::type vload(const Real* p, int e) {
+  return *reinterpret_cast<const typename Vec16<Real>::type*>(p + e);
+}
+template <typename Real>
+__device__ inline void vstore(Real* p, int e, typename Vec16<Real>::type v) {
+  *reinterpret_cast<typename Vec16<Real>::type*>(p + e) = v;
+}
+template <typename Real>
+__device__ inline void vcopy(Real* dst, const Real* src, int len) {
+  constexpr int W = Vec16<Real>::W;
+#pragma unroll 2
+  for (int e = W * tid(); e < len; e += W * kBlock) vstore(dst, e, vload(src, e));
+}
+
+// Sum N (<= 32) doubles over the workgroup; fixed order, so deterministic.
 template <int N>
 __device__ inline void block_sum(double (&v)[N], double* red) {
+  static_assert(N <= kRedStride, "block_sum: too many values");
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     double x = v[i];
@@ -50,11 +75,12 @@ __device__ inline void block_sum(double (&v)[N], double* red) {
   __syncthreads();
   if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) red[wave * 16 + i] = v[i];
+    for (int i = 0; i < N; ++i) red[wave * kRedStride + i] = v[i];
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = (red[i] + red[16 + i]) + (red[32 + i] + red[48 + i]);
+  for (int i = 0; i < N; ++i)
+    v[i] = (red[i] + red[kRedStride + i]) + (red[2 * kRedStride + i] + red[3 * kRedStride + i]);
 }
 
 template <typename Real>
@@ -166,22 +192,30 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
   const Real beta = Real(mat.beta), kb = Real(mat.k_bend);
   const Real Cst = Real(mat.C), Bsk = Real(mat.B), Dsk = Real(mat.D);
 
-  // ---- pass A: enclosed volume (FP64) and bending residuals R_i -> work -----------
+  // The corner buffer holds, per triangle, the in-plane gradient of its three corners
+  // (9 values) and its volume-gradient vector (e1 x e2)/6 (3 values).  When all
+  // triangles fit one chunk the enclosed volume is summed in the triangle pass itself;
+  // otherwise it is summed first, in a pass of its own.
+  const bool single = nt <= ch;
+  // ---- pass A: (volume when chunked) and bending residuals R_i -> work -------------
   double accA[3] = {0.0, 0.0, 0.0};   // volume, bending energy, bending Rayleigh energy
-  for (int t = tid(); t < nt; t += kBlock) {
-    const int a = M.tri[3 * t], b = M.tri[3 * t + 1], c = M.tri[3 * t + 2];
-    const double ax = (double)xn[a] + ut[a], ay = (double)xn[np + a] + ut[np + a], az = (double)xn[2 * np + a] + ut[2 * np + a];
-    const double bx = (double)xn[b] + ut[b], by = (double)xn[np + b] + ut[np + b], bz = (double)xn[2 * np + b] + ut[2 * np + b];
-    const double cx = (double)xn[c] + ut[c], cy = (double)xn[np + c] + ut[np + c], cz = (double)xn[2 * np + c] + ut[2 * np + c];
-    accA[0] += ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
+  if (!single) {
+    for (int t = tid(); t < nt; t += kBlock) {
+      const int a = M.tri[3 * t], b = M.tri[3 * t + 1], c = M.tri[3 * t + 2];
+      const double ax = (double)xn[a] + ut[a], ay = (double)xn[np + a] + ut[np + a], az = (double)xn[2 * np + a] + ut[2 * np + a];
+      const double bx = (double)xn[b] + ut[b], by = (double)xn[np + b] + ut[np + b], bz = (double)xn[2 * np + b] + ut[2 * np + b];
+      const double cx = (double)xn[c] + ut[c], cy = (double)xn[np + c] + ut[np + c], cz = (double)xn[2 * np + c] + ut[2 * np + c];
+      accA[0] += ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
+    }
   }
   for (int i = tid(); i < n; i += kBlock) {
     Real lx = 0, ly = 0, lz = 0, ux = 0, uy = 0, uz = 0;
     const Real xix = xn[i], xiy = xn[np + i], xiz = xn[2 * np + i];
     const Real uix = ut[i], uiy = ut[np + i], uiz = ut[2 * np + i];
-    for (int q = M.nb_ptr[i]; q < M.nb_ptr[i + 1]; ++q) {
-      const int j = M.nb_idx[q];
-      const Real w = M.nb_w[q];
+#pragma unroll 6
+    for (int q = 0; q < M.nb_deg; ++q) {
+      const int j = M.nb_ell[q * np + i];
+      const Real w = M.nbw_ell[q * np + i];
       const Real dux = ut[j] - uix, duy = ut[np + j] - uiy, duz = ut[2 * np + j] - uiz;
       lx += w * ((xn[j] - xix) + dux);
       ly += w * ((xn[np + j] - xiy) + duy);
@@ -202,20 +236,27 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     work[np + i] = ry + beta * uy;
     work[2 * np + i] = rz + beta * uz;
   }
-  block_sum<3>(accA, red);
-  const double vol = accA[0] / 6.0;
-  const double Cv = vol - M.V0;
-  const Real coef = Real(mat.k_volume * Cv / Gn);          // k C / G_n
-  const double e_vol = 0.5 * mat.k_volume * Cv * Cv / Gn;
+  double coefd = 0.0, vol = 0.0;
+  if (!single) {
+    block_sum<3>(accA, red);
+    vol = accA[0] / 6.0;
+    coefd = mat.k_volume * (vol - M.V0) / Gn;               // k C / G_n
+  } else {
+    double ab[2] = {accA[1], accA[2]};
+    block_sum<2>(ab, red);                                   // also the barrier before pass B
+    accA[1] = ab[0];
+    accA[2] = ab[1];
+  }
 
   // ---- pass B: bending gradient + inertia - b -> gout ----------------------------
   double accB[1] = {0.0};
   for (int i = tid(); i < n; i += kBlock) {
     Real gx = 0, gy = 0, gz = 0;
     const Real rix = work[i], riy = work[np + i], riz = work[2 * np + i];
-    for (int q = M.nb_ptr[i]; q < M.nb_ptr[i + 1]; ++q) {
-      const int j = M.nb_idx[q];
-      const Real w = M.nb_w[q];
+#pragma unroll 6
+    for (int q = 0; q < M.nb_deg; ++q) {
+      const int j = M.nb_ell[q * np + i];
+      const Real w = M.nbw_ell[q * np + i];
       gx += w * (work[j] - rix);
       gy += w * (work[np + j] - riy);
       gz += w * (work[2 * np + j] - riz);
@@ -233,7 +274,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
   __syncthreads();   // work (R) is reused for the corner chunks below
 
   // ---- passes C/D: triangle in-plane terms + volume, per chunk --------------------
-  double accC[4] = {0.0, 0.0, 0.0, 0.0};   // area PD, Skalak, triangle Rayleigh, |u.b|
+  double accC[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // area PD, Skalak, triangle Rayleigh, |u.b|, 6 volume
   double accD[4] = {0.0, 0.0, 0.0, 0.0};   // |grad|^2, |M u/h^2|^2, |b|^2, |F_int|^2
   for (int t0 = 0; t0 < nt; t0 += ch) {
     const int tn = min(ch, nt - t0);
@@ -308,38 +349,61 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       const Real G1z = w1 * u1z * vy + w2 * u2z * vx + wr * g1z;
       // corner gradients [g_a g_b] = dE/dF D_m^-T, g_c = -g_a - g_b, plus the volume
       // gradient k C / G_n * (e1 x e2) / 6 on each corner
-      const Real vvx = coef * nx / Real(6), vvy = coef * ny / Real(6), vvz = coef * nz / Real(6);
       const Real gax = G0x * d00 + G1x * d01, gay = G0y * d00 + G1y * d01, gaz = G0z * d00 + G1z * d01;
       const Real gbx = G0x * d10 + G1x * d11, gby = G0y * d10 + G1y * d11, gbz = G0z * d10 + G1z * d11;
-      work[0 * ch + tt] = gax + vvx;
-      work[1 * ch + tt] = gay + vvy;
-      work[2 * ch + tt] = gaz + vvz;
-      work[3 * ch + tt] = gbx + vvx;
-      work[4 * ch + tt] = gby + vvy;
-      work[5 * ch + tt] = gbz + vvz;
-      work[6 * ch + tt] = -(gax + gbx) + vvx;
-      work[7 * ch + tt] = -(gay + gby) + vvy;
-      work[8 * ch + tt] = -(gaz + gbz) + vvz;
+      work[0 * ch + tt] = gax;
+      work[1 * ch + tt] = gay;
+      work[2 * ch + tt] = gaz;
+      work[3 * ch + tt] = gbx;
+      work[4 * ch + tt] = gby;
+      work[5 * ch + tt] = gbz;
+      work[6 * ch + tt] = -(gax + gbx);
+      work[7 * ch + tt] = -(gay + gby);
+      work[8 * ch + tt] = -(gaz + gbz);
+      work[9 * ch + tt] = nx / Real(6);      // volume gradient of each corner: (e1 x e2) / 6
+      work[10 * ch + tt] = ny / Real(6);
+      work[11 * ch + tt] = nz / Real(6);
+      if (single) {
+        // x_a . (x_b x x_c) = E1 . (E2 x x_c) with E1 = x_a - x_c, E2 = x_b - x_c (FP64)
+        const double cx = (double)xn[c] + (double)ut[c], cy = (double)xn[np + c] + (double)ut[np + c],
+                     cz = (double)xn[2 * np + c] + (double)ut[2 * np + c];
+        accC[4] += E1x * (E2y * cz - E2z * cy) + E1y * (E2z * cx - E2x * cz) + E1z * (E2x * cy - E2y * cx);
+      }
       accC[0] += 0.5 * (double)(Cst * A0) * ((double)dA1 * dA1 + (double)dA2 * dA2);
       accC[1] += (double)A0 * (0.125 * (double)Bsk * ((double)s1m * s1m + (double)s2m * s2m)
                                + 0.25 * (double)Dsk * ((double)a1 * a1 * a1 * a1 + (double)a2 * a2 * a2 * a2));
       accC[2] += 0.5 * (double)wr * ((double)g0x * g0x + (double)g0y * g0y + (double)g0z * g0z
                                      + (double)g1x * g1x + (double)g1y * g1y + (double)g1z * g1z);
     }
-    __syncthreads();
+    if (single) {
+      double vv[1] = {accC[4]};
+      block_sum<1>(vv, red);                  // also the barrier before the gather
+      vol = vv[0] / 6.0;
+      coefd = mat.k_volume * (vol - M.V0) / Gn;
+    } else {
+      __syncthreads();
+    }
+    const Real coef = Real(coefd);
     const bool last = t0 + ch >= nt;
     for (int i = tid(); i < n; i += kBlock) {
-      Real gx = 0, gy = 0, gz = 0;
-      for (int q = M.vc_ptr[i]; q < M.vc_ptr[i + 1]; ++q) {
-        const int cid = M.vc_idx[q];
+      Real gx = 0, gy = 0, gz = 0, vx = 0, vy = 0, vz = 0;
+#pragma unroll 6
+      for (int q = 0; q < M.vc_deg; ++q) {
+        const int cid = M.vc_ell[q * np + i];
         const int t = cid / 3 - t0;
-        if (t >= 0 && t < tn) {
+        if (cid >= 0 && t >= 0 && t < tn) {
           const int k = cid - 3 * (cid / 3);
           gx += work[(3 * k) * ch + t];
           gy += work[(3 * k + 1) * ch + t];
           gz += work[(3 * k + 2) * ch + t];
+          vx += work[9 * ch + t];
+          vy += work[10 * ch + t];
+          vz += work[11 * ch + t];
         }
       }
+      gx += coef * vx;
+      gy += coef * vy;
+      gz += coef * vz;
       gx += gout[i];
       gy += gout[np + i];
       gz += gout[2 * np + i];
@@ -361,6 +425,8 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     }
     __syncthreads();
   }
+  const double Cv = vol - M.V0;
+  const double e_vol = 0.5 * mat.k_volume * Cv * Cv / Gn;
   double acc[9] = {accB[0], accC[0], accC[1], accC[2], accC[3], accD[0], accD[1], accD[2], accD[3]};
   block_sum<9>(acc, red);
   const double inertial = acc[0];
@@ -467,6 +533,157 @@ __device__ inline void tile_gemm(const double* __restrict__ A, int np, const dou
   }
 }
 
+// BF16 variant for FP32 plans: Out^T = In^T (diag(a) + A_off) with the off-diagonal part
+// A_off in BF16 on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation) and
+// the diagonal applied exactly in FP32 in the epilogue.  In is rounded to BF16 on the
+// fly (8 consecutive k per lane, the same k order for both operands).
+__device__ inline void tile_gemm_bf16(const uint16_t* __restrict__ Abits, const float* __restrict__ diag,
+                                      int np, const float* __restrict__ In, float* __restrict__ Out,
+                                      int rows) {
+  const __bf16* A = reinterpret_cast<const __bf16*>(Abits);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int mb_n = (rows + 15) >> 4;
+  for (int nb = wave; nb < (np >> 4); nb += 4) {
+    const int n0 = nb << 4;
+    floatx4 acc[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) acc[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const __bf16* arow = A + (size_t)(n0 + l16) * np + 8 * kq;
+    for (int k0 = 0; k0 < np; k0 += 32) {
+      const bf16x8 bq = *reinterpret_cast<const bf16x8*>(arow + k0);
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        if (mb < mb_n) {
+          const int r = mb * 16 + l16;
+          bf16x8 aq;
+          if (r < rows) {
+            const floatx4 lo = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + k0 + 8 * kq);
+            const floatx4 hi = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + k0 + 8 * kq + 4);
+            aq = bf16x8{(__bf16)lo.x, (__bf16)lo.y, (__bf16)lo.z, (__bf16)lo.w,
+                        (__bf16)hi.x, (__bf16)hi.y, (__bf16)hi.z, (__bf16)hi.w};
+          } else {
+            aq = bf16x8{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f,
+                        (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+          }
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, bq, acc[mb], 0, 0, 0);
+        }
+      }
+    }
+    const float dn = diag[n0 + l16];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      if (mb < mb_n) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = mb * 16 + 4 * kq + i;
+          if (r < rows) {
+            const size_t o = (size_t)r * np + n0 + l16;
+            Out[o] = acc[mb][i] + dn * In[o];
+          }
+        }
+      }
+    }
+  }
+}
+
+// Same product with the tile's rows staged once in LDS as BF16 (rows padded to 16),
+// and each wave carrying four column blocks at a time, so that four independent
+// B fragments are in flight per k step and every A fragment read from LDS feeds four
+// matrix instructions.  Needs 16 ceil(rows/16) (n_pad + 8) BF16 of LDS at `stage`.
+constexpr int kStageMaxPad = 1024;
+__device__ inline void tile_gemm_bf16_lds(const uint16_t* __restrict__ Abits, const float* __restrict__ diag,
+                                          int np, const float* __restrict__ In, float* __restrict__ Out,
+                                          int rows, __bf16* stage) {
+  const __bf16* A = reinterpret_cast<const __bf16*>(Abits);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int mb_n = (rows + 15) >> 4;
+  const int ldk = np + 8;
+  const int k8n = np >> 3;
+  __syncthreads();
+  for (int e = tid(); e < mb_n * 16 * k8n; e += kBlock) {
+    const int r = e / k8n, k8 = (e - r * k8n) << 3;
+    bf16x8 v;
+    if (r < rows) {
+      const floatx4 lo = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + k8);
+      const floatx4 hi = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + k8 + 4);
+      v = bf16x8{(__bf16)lo.x, (__bf16)lo.y, (__bf16)lo.z, (__bf16)lo.w,
+                 (__bf16)hi.x, (__bf16)hi.y, (__bf16)hi.z, (__bf16)hi.w};
+    } else {
+      v = bf16x8{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f,
+                 (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+    }
+    *reinterpret_cast<bf16x8*>(stage + r * ldk + k8) = v;
+  }
+  __syncthreads();
+  constexpr int NB = 4;
+  const int ncb = np >> 4;
+  for (int g0 = wave; g0 < ncb; g0 += 4 * NB) {
+    floatx4 acc[4][NB];
+    const __bf16* arow[NB];
+    bool valid[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int cb = g0 + 4 * q;
+      valid[q] = cb < ncb;
+      arow[q] = A + (size_t)((valid[q] ? cb : 0) * 16 + l16) * np + 8 * kq;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) acc[mb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int k0 = 0; k0 < np; k0 += 32) {
+      bf16x8 bq[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) bq[q] = *reinterpret_cast<const bf16x8*>(arow[q] + k0);
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        if (mb < mb_n) {
+          const bf16x8 aq = *reinterpret_cast<const bf16x8*>(stage + (mb * 16 + l16) * ldk + k0 + 8 * kq);
+#pragma unroll
+          for (int q = 0; q < NB; ++q) acc[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, bq[q], acc[mb][q], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (!valid[q]) continue;
+      const int n = (g0 + 4 * q) * 16 + l16;
+      const float dn = diag[n];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        if (mb < mb_n) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = mb * 16 + 4 * kq + i;
+            if (r < rows) {
+              const size_t o = (size_t)r * np + n;
+              Out[o] = acc[mb][q][i] + dn * In[o];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// The tile's product with H~^-1 (which 0) or h^2 M~^-1 (which 1) in the plan's format.
+template <typename Real>
+__device__ inline void tile_product(const MeshDev<Real>& M, const SolverDev& sol, int which, const Real* In,
+                                    Real* Out, int rows, unsigned char* stage) {
+  if constexpr (std::is_same<Real, float>::value) {
+    if (sol.bf16) {
+      const uint16_t* Ab = which == 0 ? M.hinv_bf : M.minv_bf;
+      const float* dg = which == 0 ? M.hinv_diag : M.minv_diag;
+      if (M.n_pad <= kStageMaxPad)
+        tile_gemm_bf16_lds(Ab, dg, M.n_pad, In, Out, rows, reinterpret_cast<__bf16*>(stage));
+      else
+        tile_gemm_bf16(Ab, dg, M.n_pad, In, Out, rows);
+      return;
+    }
+  }
+  tile_gemm(which == 0 ? M.hinv : M.minv, M.n_pad, In, Out, rows);
+}
+
 // ---------------------------------------------------------------------------------
 // The step
 // ---------------------------------------------------------------------------------
@@ -570,7 +787,7 @@ __device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, c
   }
 }
 
-template <typename Real>
+template <typename Real, int H>
 __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* CS, double* red,
                          int* sint, unsigned char* lds) {
   const TileDesc td = A.tiles[tile];
@@ -608,7 +825,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
     __syncthreads();
   }
   if (!A.u_guess) {
-    tile_gemm(M.minv, np, tl.mat(VB), tl.mat(VU), 3 * cnt);     // u = h^2 M~^-1 b
+    tile_product(M, A.sol, 1, tl.mat(VB), tl.mat(VU), 3 * cnt, reinterpret_cast<unsigned char*>(xn));  // u = h^2 M~^-1 b
     __syncthreads();
   }
 
@@ -616,18 +833,13 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
   for (int j = 0; j < cnt; ++j) {
     const int cell = A.tile_cells[td.first + j];
     stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
-    const Real* U = tl.vec(VU, j);
-    for (int e = tid(); e < len; e += kBlock) ut[e] = U[e];
+    vcopy(ut, tl.vec(VU, j), len);
     __syncthreads();
     EvalResult r;
     evaluate(M, A.mat, h, CS[j].Gn, xn, ut, work, tl.vec(VB, j), tl.vec(VG, j), red, r);
     const bool bad = !isfinite(r.E) || !isfinite(r.resid);
     const bool done = bad || r.resid <= A.sol.tol;
-    if (!done) {
-      const Real* G = tl.vec(VG, j);
-      Real* Q = tl.vec(VQ, j);
-      for (int e = tid(); e < len; e += kBlock) Q[e] = G[e];
-    }
+    if (!done) vcopy(tl.vec(VQ, j), tl.vec(VG, j), len);
     if (tid() == 0) {
       CellState& cs = CS[j];
       cs.E = r.E;
@@ -642,8 +854,17 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
   }
 
   // ---- quasi-Newton iterations (Algorithm 1, while loop) --------------------------
-  // every round an active cell accepts a step (iter + 1, bounded by max_iter) or
-  // clears its history for one retry, so 2 max_iter + 2 rounds always suffice
+  // L-BFGS two-loop recursion (Nocedal & Wright Alg. 7.4) written with the matrix
+  // SY[i][j] = s_i . y_j of the stored pairs: with q_i = g - sum_{j newer} alpha_j y_j,
+  //   alpha_i = rho_i (s_i . g - sum_{j newer} alpha_j SY[i][j]),
+  // and with z_i = r + sum_{j older} (alpha_j - beta_j) s_j, r = H~^-1 q,
+  //   beta_i = rho_i (y_i . r + sum_{j older} (alpha_j - beta_j) SY[j][i]),
+  // so each half of the recursion is one pass of dot products plus one pass that
+  // combines vectors.  The dot products the first half needs are accumulated while
+  // the step is accepted.
+  //
+  // Every round an active cell accepts a step (iter + 1, bounded by max_iter) or clears
+  // its history for one retry, so 2 max_iter + 2 rounds always suffice.
   const int max_rounds = 2 * A.sol.max_iter + 2;
   for (int round = 0;; ++round) {
     if (tid() == 0) {
@@ -659,7 +880,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
     }
     __syncthreads();
     if (sint[1] == 0) break;
-    tile_gemm(M.hinv, np, tl.mat(VQ), tl.mat(VD), 3 * cnt);      // r = H~^-1 q
+    tile_product(M, A.sol, 0, tl.mat(VQ), tl.mat(VD), 3 * cnt, reinterpret_cast<unsigned char*>(xn));  // r = H~^-1 q
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
       CellState& cs = CS[j];
@@ -672,28 +893,84 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
       Real* D = tl.vec(VD, j);
       Real* Q = tl.vec(VQ, j);
       const int hn = cs.hist_n, head = cs.hist_head;
-      // two-loop recursion, second half: z = r + sum_i s_i (alpha_i - beta_i), oldest first
-      for (int p = 0; p < hn; ++p) {
-        const int slot = (head - hn + p + m) % m;       // p = 0 is the oldest pair
-        const Real* S = tl.vec(VS0 + slot, j);
-        const Real* Y = tl.vec(VS0 + m + slot, j);
-        const double bta = cs.rho[slot] * dot_vec(Y, D, len, red);
-        const Real coefs = Real(cs.alpha[slot] - bta);
-        for (int e = tid(); e < len; e += kBlock) D[e] += coefs * S[e];
-        __syncthreads();
+      auto slot = [&](int p) { return (head - hn + p + m) % m; };   // p = 0 oldest .. hn-1 newest
+      // second half: y_p . r for every stored pair (one pass)
+      constexpr int W = Vec16<Real>::W;
+      double yr[H];
+#pragma unroll
+      for (int p = 0; p < H; ++p) yr[p] = 0.0;
+      if (hn > 0) {
+#pragma unroll 2
+        for (int e = W * tid(); e < len; e += W * kBlock) {
+          const auto rv = vload(D, e);
+#pragma unroll
+          for (int p = 0; p < H; ++p) {
+            if (p < hn) {
+              const auto yv = vload(tl.vec(VS0 + m + slot(p), j), e);
+#pragma unroll
+              for (int w = 0; w < W; ++w) yr[p] += (double)yv[w] * rv[w];
+            }
+          }
+        }
+        block_sum<H>(yr, red);
       }
-      for (int e = tid(); e < len; e += kBlock) D[e] = -D[e];
-      __syncthreads();
+      double cf[H];                                    // alpha_p - beta_p
+#pragma unroll
+      for (int p = 0; p < H; ++p) {
+        cf[p] = 0.0;
+        if (p < hn) {
+          double acc = yr[p];
+#pragma unroll
+          for (int q = 0; q < H; ++q)
+            if (q < p) acc += cf[q] * cs.SY[slot(q)][slot(p)];
+          cf[p] = cs.alpha[slot(p)] - cs.rho[slot(p)] * acc;
+        }
+      }
+      // d = -(r + sum_p cf_p s_p), g . d, and the first trial point u + d staged in LDS
+      // (one pass)
+      double gdv[1] = {0.0};
+#pragma unroll 2
+      for (int e = W * tid(); e < len; e += W * kBlock) {
+        const auto rv = vload(D, e);
+        double z[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) z[w] = rv[w];
+#pragma unroll
+        for (int p = 0; p < H; ++p) {
+          if (p < hn) {
+            const auto sv = vload(tl.vec(VS0 + slot(p), j), e);
+#pragma unroll
+            for (int w = 0; w < W; ++w) z[w] += cf[p] * (double)sv[w];
+          }
+        }
+        const auto gv = vload(G, e), uv = vload(U, e);
+        typename Vec16<Real>::type dv, tv;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          dv[w] = Real(-z[w]);
+          tv[w] = uv[w] + dv[w];
+          gdv[0] += (double)gv[w] * dv[w];
+        }
+        vstore(D, e, dv);
+        vstore(ut, e, tv);
+      }
+      block_sum<1>(gdv, red);
+      const double gd = gdv[0];
       // line search: alpha = 1, 1/2, ... until sufficient decrease (Algorithm 1)
-      const double gd = dot_vec(G, D, len, red);
       double alpha = 1.0;
       bool accepted = false;
       EvalResult r;
       int hv = 0;
       for (; hv <= A.sol.max_halvings; ++hv) {
-        const Real al = Real(alpha);
-        for (int e = tid(); e < len; e += kBlock) ut[e] = U[e] + al * D[e];
-        __syncthreads();
+        if (hv > 0) {
+          const Real al = Real(alpha);
+#pragma unroll 2
+          for (int e = W * tid(); e < len; e += W * kBlock) {
+            const auto uv = vload(U, e), dv = vload(D, e);
+            vstore(ut, e, uv + al * dv);
+          }
+          __syncthreads();
+        }
         evaluate(M, A.mat, h, cs.Gn, xn, ut, work, tl.vec(VB, j), GT, red, r);
         const double slack = A.sol.noise * fmax(cs.noise, r.noise);
         accepted = isfinite(r.E) && (r.E <= cs.E + A.sol.c1 * alpha * gd + slack);
@@ -703,7 +980,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
       const int evals_add = accepted ? hv + 1 : hv;
       if (!accepted) {
         if (hn > 0) {
-          for (int e = tid(); e < len; e += kBlock) Q[e] = G[e];
+          vcopy(Q, G, len);
           __syncthreads();
           if (tid() == 0) {
             cs.hist_n = 0;
@@ -719,42 +996,109 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
         __syncthreads();
         continue;
       }
-      // accept: s = alpha d, y = grad_t - grad; u += s; grad = grad_t
+      // accept: s = alpha d, y = grad_t - grad, u += s, grad = grad_t; in the same pass the
+      // dot products of the new pair with itself, with the kept pairs and with the new
+      // gradient.  With a full ring the new pair goes into the oldest pair's slot.
       const Real al = Real(alpha);
-      double dots[3] = {0.0, 0.0, 0.0};
+      const bool full = m > 0 && hn == m;
+      const int ns = head;                                       // slot written
+      // acc: [0] s.y  [1] s.s  [2] y.y  [3] s.g'  [4+p] s_p.g'  [4+H+p] s.y_p  [4+2H+p] y.s_p
+      double acc[4 + 3 * H];
+#pragma unroll
+      for (int k = 0; k < 4 + 3 * H; ++k) acc[k] = 0.0;
       if (m > 0) {
-        Real* S = tl.vec(VS0 + head, j);
-        Real* Y = tl.vec(VS0 + m + head, j);
-        for (int e = tid(); e < len; e += kBlock) {
-          const Real s = al * D[e], y = GT[e] - G[e];
-          S[e] = s;
-          Y[e] = y;
-          U[e] += s;
-          G[e] = GT[e];
-          dots[0] += (double)s * y;
-          dots[1] += (double)s * s;
-          dots[2] += (double)y * y;
+        Real* Sn = tl.vec(VS0 + ns, j);
+        Real* Yn = tl.vec(VS0 + m + ns, j);
+#pragma unroll 2
+        for (int e = W * tid(); e < len; e += W * kBlock) {
+          const auto gt = vload(GT, e), gv = vload(G, e), dv = vload(D, e), uv = vload(U, e);
+          const auto sv = al * dv;
+          const auto yv = gt - gv;
+#pragma unroll
+          for (int p = 0; p < H; ++p) {
+            if (p < hn && !(full && p == 0)) {                   // p = 0 is the slot being replaced when full
+              const auto so = vload(tl.vec(VS0 + slot(p), j), e), yo = vload(tl.vec(VS0 + m + slot(p), j), e);
+#pragma unroll
+              for (int w = 0; w < W; ++w) {
+                acc[4 + p] += (double)so[w] * gt[w];
+                acc[4 + H + p] += (double)sv[w] * yo[w];
+                acc[4 + 2 * H + p] += (double)yv[w] * so[w];
+              }
+            }
+          }
+          vstore(Sn, e, sv);
+          vstore(Yn, e, yv);
+          vstore(U, e, uv + sv);
+          vstore(G, e, gt);
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            acc[0] += (double)sv[w] * yv[w];
+            acc[1] += (double)sv[w] * sv[w];
+            acc[2] += (double)yv[w] * yv[w];
+            acc[3] += (double)sv[w] * gt[w];
+          }
         }
       } else {
-        for (int e = tid(); e < len; e += kBlock) {
-          U[e] += al * D[e];
-          G[e] = GT[e];
+#pragma unroll 2
+        for (int e = W * tid(); e < len; e += W * kBlock) {
+          vstore(U, e, vload(U, e) + al * vload(D, e));
+          vstore(G, e, vload(GT, e));
         }
       }
-      block_sum<3>(dots, red);
-      const bool store = m > 0 && dots[0] > 1e-12 * sqrt(dots[1] * dots[2]);
-      int hn2 = hn, head2 = head;
-      if (store) {
-        hn2 = min(hn + 1, m);
-        head2 = (head + 1) % m;
-      } else if (hn == m) {
-        hn2 = m - 1;          // slot `head` held the oldest pair and was overwritten
+      block_sum<4 + 3 * H>(acc, red);
+      // the reduced dot products go to LDS so they can be picked by pair index below
+      double* s_acc = red + kRedDoubles;                         // 32 doubles after the reduction buffer
+      if (tid() < 4 + 3 * H) {
+#pragma unroll
+        for (int k = 0; k < 4 + 3 * H; ++k)
+          if (k == tid()) s_acc[k] = acc[k];
       }
+      __syncthreads();
+      const bool store = m > 0 && s_acc[0] > 1e-12 * sqrt(s_acc[1] * s_acc[2]);
+      // new history (p = 0 oldest): the kept old pairs (old index p + first_kept), then the
+      // new pair in slot ns if it is stored
+      const int first_kept = full ? 1 : 0;
+      const int n_kept = hn - first_kept;
+      const int hn2 = n_kept + (store ? 1 : 0);
+      const int head2 = store ? (head + 1) % m : head;
+      auto slot2 = [&](int p) { return p < n_kept ? (head - hn + first_kept + p + m) % m : ns; };
       const bool conv = r.resid <= A.sol.tol;
       const bool out_of_iters = cs.iter + 1 >= A.sol.max_iter;
+      // first half of the next recursion: alpha_p, newest first
+      double al_new[H];
+#pragma unroll
+      for (int p = H - 1; p >= 0; --p) {
+        al_new[p] = 0.0;
+        if (p < hn2) {
+          const bool isnew = p >= n_kept;
+          const double rho = isnew ? 1.0 / s_acc[0] : cs.rho[slot2(p)];
+          double sg = isnew ? s_acc[3] : s_acc[4 + p + first_kept];
+#pragma unroll
+          for (int q = H - 1; q >= 0; --q) {
+            if (q > p && q < hn2) {
+              // SY[slot p][slot q] = s_p . y_q; the new pair is the newest, so p is old here
+              const double syq = q >= n_kept ? s_acc[4 + 2 * H + p + first_kept]   // s_p . y_new
+                                             : cs.SY[slot2(p)][slot2(q)];
+              sg -= al_new[q] * syq;
+            }
+          }
+          al_new[p] = rho * sg;
+        }
+      }
       __syncthreads();
       if (tid() == 0) {
-        if (store) cs.rho[head] = 1.0 / dots[0];
+        if (store) {
+          cs.rho[ns] = 1.0 / s_acc[0];
+          cs.SY[ns][ns] = s_acc[0];
+          for (int p = 0; p < n_kept; ++p) {
+            const int sp = slot2(p), o = p + first_kept;
+            cs.SY[ns][sp] = s_acc[4 + H + o];       // s_new . y_p
+            cs.SY[sp][ns] = s_acc[4 + 2 * H + o];   // s_p . y_new
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < H; ++p)
+          if (p < hn2) cs.alpha[slot2(p)] = al_new[p];
         cs.hist_n = hn2;
         cs.hist_head = head2;
         cs.E = r.E;
@@ -768,20 +1112,27 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
         else if (out_of_iters) { cs.status = NPFEM_MAXITER; cs.active = 0; }
       }
       if (conv || out_of_iters) { __syncthreads(); continue; }
-      // two-loop recursion, first half: q = g; alpha_i = rho_i s_i.q; q -= alpha_i y_i
-      for (int e = tid(); e < len; e += kBlock) Q[e] = G[e];
-      __syncthreads();
-      for (int p = hn2 - 1; p >= 0; --p) {
-        const int slot = (head2 - hn2 + p + m) % m;
-        const Real* S = tl.vec(VS0 + slot, j);
-        const Real* Y = tl.vec(VS0 + m + slot, j);
-        const double rho = (p == hn2 - 1 && store) ? 1.0 / dots[0] : CS[j].rho[slot];
-        const double a = rho * dot_vec(S, Q, len, red);
-        const Real ar = Real(a);
-        for (int e = tid(); e < len; e += kBlock) Q[e] -= ar * Y[e];
-        if (tid() == 0) cs.alpha[slot] = a;
-        __syncthreads();
+      // q = g - sum_p alpha_p y_p (one pass)
+#pragma unroll 2
+      for (int e = W * tid(); e < len; e += W * kBlock) {
+        const auto gv = vload(G, e);
+        double qv[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) qv[w] = gv[w];
+#pragma unroll
+        for (int p = 0; p < H; ++p) {
+          if (p < hn2) {
+            const auto yv = vload(tl.vec(VS0 + m + slot2(p), j), e);
+#pragma unroll
+            for (int w = 0; w < W; ++w) qv[w] -= al_new[p] * (double)yv[w];
+          }
+        }
+        typename Vec16<Real>::type o;
+#pragma unroll
+        for (int w = 0; w < W; ++w) o[w] = Real(qv[w]);
+        vstore(Q, e, o);
       }
+      __syncthreads();
     }
     __syncthreads();
   }
@@ -798,11 +1149,15 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
   }
 }
 
-template <typename Real>
-__global__ void __launch_bounds__(kBlock) step_kernel(StepArgs<Real> A) {
+#ifndef NPFEM_STEP_WAVES_PER_SIMD
+#define NPFEM_STEP_WAVES_PER_SIMD 2
+#endif
+// H: compile-time bound on the L-BFGS history (the loops over pairs are unrolled to H)
+template <typename Real, int H>
+__global__ void __launch_bounds__(kBlock, NPFEM_STEP_WAVES_PER_SIMD) step_kernel(StepArgs<Real> A) {
   extern __shared__ __align__(16) unsigned char lds[];
   double* red = reinterpret_cast<double*>(lds);
-  int* sint = reinterpret_cast<int*>(lds + kRedDoubles * 8);
+  int* sint = reinterpret_cast<int*>(lds + kRedDoubles * 8 + 32 * 8);
   Real* W = A.work + (size_t)blockIdx.x * A.slot_stride;
   CellState* CS = A.cstate + (size_t)blockIdx.x * A.tile_cells_max;
   for (;;) {
@@ -811,7 +1166,7 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepArgs<Real> A) {
     const int tile = sint[0];
     __syncthreads();
     if (tile >= A.n_tiles) break;
-    run_tile(A, tile, W, CS, red, sint, lds);
+    run_tile<Real, H>(A, tile, W, CS, red, sint, lds);
     __syncthreads();
   }
 }
@@ -866,6 +1221,12 @@ __global__ void __launch_bounds__(kBlock) apply_inverse_kernel(const Real* A, in
   tile_gemm(A, np, in + (size_t)r0 * np, out + (size_t)r0 * np, min(48, rows - r0));
 }
 
+__global__ void __launch_bounds__(kBlock) apply_inverse_bf16_kernel(const uint16_t* A, const float* diag, int np,
+                                                                    const float* in, float* out, int rows) {
+  const int r0 = blockIdx.x * 48;
+  tile_gemm_bf16(A, diag, np, in + (size_t)r0 * np, out + (size_t)r0 * np, min(48, rows - r0));
+}
+
 template <typename Real>
 __global__ void drag_kernel(const Real* x, const Real* v, const int64_t* cell_voff, const int* cell_mesh,
                             const int* mesh_n, const double* zeta, const double* rate,
@@ -894,30 +1255,44 @@ __global__ void drag_kernel(const Real* x, const Real* v, const int64_t* cell_vo
 }  // namespace
 
 template <typename Real>
-size_t lds_bytes(int n_pad, int chunk) {
-  const size_t work = (size_t)(3 * n_pad > 9 * chunk ? 3 * n_pad : 9 * chunk);
-  return kLdsHeader + sizeof(Real) * (6 * (size_t)n_pad + work);
+size_t lds_bytes(int n_pad, int chunk, int stage_rows) {
+  const size_t work = (size_t)(3 * n_pad > 12 * chunk ? 3 * n_pad : 12 * chunk);
+  size_t region = sizeof(Real) * (6 * (size_t)n_pad + work);
+  if (stage_rows > 0 && n_pad <= kStageMaxPad) {
+    const size_t st = (size_t)stage_rows * (n_pad + 8) * 2;
+    region = region > st ? region : st;
+  }
+  return kLdsHeader + region;
 }
 
 template <typename Real>
 hipError_t set_lds_limit(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&step_kernel<Real>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&eval_kernel<Real>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* fns[] = {reinterpret_cast<const void*>(&step_kernel<Real, 2>),
+                       reinterpret_cast<const void*>(&step_kernel<Real, 5>),
+                       reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory>),
+                       reinterpret_cast<const void*>(&eval_kernel<Real>)};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <typename Real>
 hipError_t occupancy(int* blocks_per_cu, size_t lds) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<Real>, kBlock, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<Real, kMaxHistory>, kBlock, lds);
 }
 
 template <typename Real>
 hipError_t launch_step(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s, int* counter) {
   (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
-  hipLaunchKernelGGL(step_kernel<Real>, dim3(grid), dim3(kBlock), lds, s, a);
+  if (a.sol.m <= 2)
+    hipLaunchKernelGGL((step_kernel<Real, 2>), dim3(grid), dim3(kBlock), lds, s, a);
+  else if (a.sol.m <= 5)
+    hipLaunchKernelGGL((step_kernel<Real, 5>), dim3(grid), dim3(kBlock), lds, s, a);
+  else
+    hipLaunchKernelGGL((step_kernel<Real, kMaxHistory>), dim3(grid), dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
@@ -938,6 +1313,14 @@ hipError_t launch_apply_inverse(const Real* A, int n_pad, const Real* in, Real* 
   return hipGetLastError();
 }
 
+hipError_t launch_apply_inverse_bf16(const uint16_t* A, const float* diag, int n_pad, const float* in,
+                                     float* out, int rows, hipStream_t s) {
+  (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
+  hipLaunchKernelGGL(apply_inverse_bf16_kernel, dim3((rows + 47) / 48), dim3(kBlock), 0, s, A, diag, n_pad, in,
+                     out, rows);
+  return hipGetLastError();
+}
+
 template <typename Real>
 hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, const int* cell_mesh,
                        const int* mesh_n, int n_cells, const double* zeta, const double* rate,
@@ -950,7 +1333,7 @@ hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, c
 }
 
 #define NPFEM_INSTANTIATE(R)                                                                       \
-  template size_t lds_bytes<R>(int, int);                                                          \
+  template size_t lds_bytes<R>(int, int, int);                                                     \
   template hipError_t set_lds_limit<R>(size_t);                                                    \
   template hipError_t occupancy<R>(int*, size_t);                                                  \
   template hipError_t launch_step<R>(const StepArgs<R>&, int, size_t, hipStream_t, int*);          \

@@ -44,10 +44,14 @@ def oracle_step(model, xn, vn, f, tol=1e-12, x_start=None):
 
 # ---- the MFMA product with the dense inverses -------------------------------------
 
-@pytest.mark.parametrize("precision,n", [("fp32", 642), ("fp64", 258), ("fp32", 258), ("fp64", 642)])
-def test_apply_inverse_matches_oracle(precision, n):
+@pytest.mark.parametrize("precision,n,bf16", [("fp32", 642, 0), ("fp64", 258, 0), ("fp32", 258, 0), ("fp64", 642, 0),
+                                              ("fp32", 642, 1), ("fp32", 2562, 1)])
+def test_apply_inverse_matches_oracle(precision, n, bf16):
+    """The matrix-core product with the dense inverses.  BF16 products (exact FP32
+    diagonal + BF16 off-diagonal part) are checked against the bound their rounding
+    allows: 2^-7 of the off-diagonal contribution."""
     m = oracle_model(n)
-    plan = make([(m.X, m.tris)], precision)
+    plan = make([(m.X, m.tris)], precision, inverse_bf16=bf16)
     dt = torch.float64 if precision == "fp64" else torch.float32
     npad = plan.n_pad(0)
     rows = 53                                        # spans several 48-row launches + a ragged tail
@@ -55,11 +59,17 @@ def test_apply_inverse_matches_oracle(precision, n):
     q = np.zeros((rows, npad))
     q[:, :n] = rng.standard_normal((rows, n))
     tol = 2e-6 if precision == "fp32" else 1e-13
-    for which, ref in ((0, np.linalg.solve(m.Ht, q[:, :n].T).T),
-                       (1, DT * DT * np.linalg.solve(m.Mt, q[:, :n].T).T)):
+    for which, Ainv in ((0, np.linalg.inv(m.Ht)), (1, DT * DT * np.linalg.inv(m.Mt))):
+        ref = q[:, :n] @ Ainv
         out = plan.apply_inverse(0, which, T(q, dt)).cpu().numpy().astype(np.float64)
-        scale = np.abs(ref).max()
-        assert np.abs(out[:, :n] - ref).max() <= tol * scale * np.sqrt(n)
+        if bf16:
+            off = Ainv - np.diag(np.diag(Ainv))
+            # both operands are rounded to BF16 (unit roundoff 2^-8 each)
+            bound = 1.01 * 2.0 ** -7 * (np.abs(q[:, :n]) @ np.abs(off)) + 1e-6 * np.abs(ref)
+            assert np.all(np.abs(out[:, :n] - ref) <= bound)
+        else:
+            scale = np.abs(ref).max()
+            assert np.abs(out[:, :n] - ref).max() <= tol * scale * np.sqrt(n)
         assert np.abs(out[:, n:]).max() == 0.0
 
 
@@ -145,6 +155,29 @@ def test_step_fp32_shear_matches_oracle():
         ur = xr - x[s]
         assert np.abs((xo[s] - x[s]) - ur).max() <= 1e-3 * np.abs(ur).max() + 1e-6
         assert np.abs(vo[s] - vr).max() <= 1e-3 * np.abs(vr).max() + 1e-5
+
+
+def test_step_fp32_bf16_products_same_solution():
+    """BF16 products with the inverses only precondition the iteration: the converged
+    positions agree with the FP32-product path and the oracle within tolerance."""
+    from paper_1903_06479_amd import CONVERGED
+    b = workloads.shear(n_cells=12, seed=77)
+    X, Tr = b.meshes[642]
+    m = oracle_model(642)
+    x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
+    f = rounded(workloads.drag_forces(b, x, v), "fp32")
+    res = {}
+    for bf in (0, 1):
+        xo, vo, st, _ = run_step(make([(X, Tr)], "fp32", inverse_bf16=bf), np.zeros(12, np.int32), x, v, f)
+        assert np.all(st["status"] == CONVERGED), st
+        res[bf] = (xo, st["iterations"])
+    D = np.ptp(X[:, 0])
+    assert np.abs(res[0][0] - res[1][0]).max() <= 1e-5 * D
+    assert res[1][1].mean() <= res[0][1].mean() + 1.0
+    for c in (0, 7):
+        s = b.cell_slice(c)
+        xr, _, _ = oracle_step(m, x[s], v[s], f[s])
+        assert np.abs(res[1][0][s] - xr).max() <= 1e-5 * D
 
 
 def test_step_tile_size_and_repeat_bitwise():
