@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--cells", type=int, default=100000)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cells-per-tile", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--fp32-products", action="store_true", help="FP32 instead of BF16 products with the inverses")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=48)
     args = ap.parse_args()
@@ -96,7 +99,8 @@ def main():
     b = make_inputs(args.cells)
     X, T = b.meshes[642]
     dev = torch.device("cuda:0")
-    params = default_params(tol=args.tol, cells_per_tile=args.cells_per_tile)
+    params = default_params(tol=args.tol, cells_per_tile=args.cells_per_tile,
+                            inverse_bf16=0 if args.fp32_products else 1)
     t0 = time.time()
     plan = Plan([Mesh(X, T)], workloads.DT_US, params=params)
     batch = Batch(plan, np.zeros(b.n_cells, np.int32))
@@ -108,6 +112,14 @@ def main():
     origin = torch.tensor(b.origin, dtype=torch.float64, device=dev)
     p = b.poiseuille
     x, v, f = x0.clone(), v0.clone(), torch.empty_like(x0)
+    tuned = None
+    if not args.no_autotune:
+        batch.drag_forces(x, v, zeta, rate, origin, p["umax"], p["radius"], p["axis_y"], p["axis_z"], out=f)
+        t0 = time.time()
+        tuned = batch.autotune(x, v, f, max_lbfgs_m=5)
+        log(f"[bench] autotune {time.time() - t0:.1f}s -> {tuned}")
+    if not args.no_graph:
+        batch.set_graph(True)
     xo, vo = torch.empty_like(x0), torch.empty_like(x0)
     st = torch.empty(b.n_cells * 40, dtype=torch.uint8, device=dev)
 
@@ -160,7 +172,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"throughput: {b.n_cells} RBCs x 642-vertex mesh, shear + Poiseuille drag, "
                                "dt=1e-7 s, FP32 bulk + FP64 reductions", "cells": b.n_cells, "mesh_vertices": n,
-                   "form": "plain", "tol": args.tol, "cells_per_tile": batch_T(batch)},
+                   "form": "plain", "tol": args.tol, "schedule": batch.schedule(),
+                   "inverse_products": "fp32" if args.fp32_products else "bf16 off-diagonal + fp32 diagonal",
+                   "hip_graph": not args.no_graph},
         "roofline": roof,
         "step_kernel_ms": float(np.mean(kernel_ms)),
         "iterations_mean": I, "iterations_max": int(np.max(iters)), "evaluations_mean": float(np.mean(evals)),
@@ -170,10 +184,6 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(b, args.cpu_sample, args.tol)
     print(json.dumps(out), flush=True)
-
-
-def batch_T(batch):
-    return None
 
 
 if __name__ == "__main__":

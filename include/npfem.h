@@ -167,6 +167,37 @@ npfem_status npfem_batch_create(npfem_plan *plan, int64_t n_cells, const int32_t
 void npfem_batch_destroy(npfem_batch *batch);
 
 /*
+ * Schedule of a batch: cells_per_tile (1..21) cells share one product with H~^-1 on the
+ * matrix cores and one workgroup; lbfgs_m (0..8) is the L-BFGS history length used by
+ * this batch (the solution does not depend on either, only the time to reach it).
+ * npfem_batch_schedule rebuilds the tile queue and workspace (synchronously; no step of
+ * this batch may be in flight); npfem_batch_get_schedule reports the current one
+ * (outputs may be NULL).
+ */
+npfem_status npfem_batch_schedule(npfem_batch *batch, int32_t cells_per_tile, int32_t lbfgs_m);
+npfem_status npfem_batch_get_schedule(const npfem_batch *batch, int32_t *cells_per_tile,
+                                      int32_t *lbfgs_m, int32_t *grid_blocks, int32_t *n_tiles);
+
+/*
+ * Autotuner: times one step of the batch on the caller's inputs for each candidate
+ * schedule (cells_per_tile in {5, 10, 16, 21}, lbfgs_m in {2, 3, 5, 8} up to
+ * max_lbfgs_m) and keeps the fastest.  x, v, f_ext: device inputs as for npfem_step;
+ * x_scratch, v_scratch: device [V_total][3] outputs it may overwrite.  Synchronous.
+ * best_ms (may be NULL) receives the best step time in milliseconds.
+ */
+npfem_status npfem_batch_autotune(npfem_batch *batch, const void *x, const void *v, const void *f_ext,
+                                  void *x_scratch, void *v_scratch, int32_t max_lbfgs_m, void *stream,
+                                  double *best_ms);
+
+/*
+ * use_graph = 1: npfem_step captures its launches into a HIP graph on the first call
+ * with a given set of buffers and stream and replays the graph on later calls with the
+ * same arguments (a different argument set is captured anew).  Not used on the NULL
+ * stream.  use_graph = 0 (default): launches directly.
+ */
+npfem_status npfem_batch_set_graph(npfem_batch *batch, int32_t use_graph);
+
+/*
  * One time step of every cell of the batch (Algorithm 1), asynchronous on `stream`
  * (a hipStream_t; NULL = default stream).
  *   x, v, f_ext : device [V_total][3] inputs x_n, v_n, F_ext(x_n)

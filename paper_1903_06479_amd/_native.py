@@ -49,6 +49,10 @@ _SIGNATURES = {
     "npfem_plan_masses": (c_int32, [c_void_p, c_int32, _P]),
     "npfem_batch_create": (c_int32, [c_void_p, c_int64, _P, POINTER(c_void_p), POINTER(c_int64)]),
     "npfem_batch_destroy": (None, [c_void_p]),
+    "npfem_batch_schedule": (c_int32, [c_void_p, c_int32, c_int32]),
+    "npfem_batch_get_schedule": (c_int32, [c_void_p, _P, _P, _P, _P]),
+    "npfem_batch_autotune": (c_int32, [c_void_p, _P, _P, _P, _P, _P, c_int32, _P, _P]),
+    "npfem_batch_set_graph": (c_int32, [c_void_p, c_int32]),
     "npfem_step": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P, _P]),
     "npfem_eval": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P]),
     "npfem_apply_inverse": (c_int32, [c_void_p, c_int32, c_int32, _P, _P, c_int32, _P, _P]),

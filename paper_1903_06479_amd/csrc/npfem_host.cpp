@@ -339,8 +339,10 @@ namespace {
 
 struct DeviceBuffers {
   std::vector<void*> ptrs;
-  ~DeviceBuffers() {
+  ~DeviceBuffers() { release(); }
+  void release() {
     for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
   }
   template <typename T>
   npfem_status upload(const T* src, size_t count, const T** out) {
@@ -625,19 +627,35 @@ npfem_status npfem_plan_masses(const npfem_plan* p, int32_t mi, double* out) {
 struct npfem_batch {
   npfem_plan* plan = nullptr;
   int64_t n_cells = 0, n_vert = 0;
-  int T = 0, n_tiles = 0, grid = 0, n_pad_max = 0, n_vec = 0;
-  size_t lds = 0;
-  int64_t slot_stride = 0;
-  DeviceBuffers buf;
-  const TileDesc* tiles = nullptr;
-  const int* tile_cells = nullptr;
+  int n_pad_max = 0;
+  std::vector<std::vector<int>> by_mesh;   // cells of each mesh type, in batch order
+  DeviceBuffers buf;                       // cell layout (fixed)
   const int64_t* cell_voff = nullptr;
   const int* cell_mesh = nullptr;
   const int* mesh_n = nullptr;
+  void* eval_scratch = nullptr;
+  // schedule: tiling, history length and workspace (rebuilt by the autotuner)
+  int T = 0, m = 0, n_tiles = 0, grid = 0, n_vec = 0;
+  size_t lds = 0;
+  int64_t slot_stride = 0;
+  DeviceBuffers sched;
+  const TileDesc* tiles = nullptr;
+  const int* tile_cells = nullptr;
   int* counter = nullptr;
   void* work = nullptr;
   CellState* cstate = nullptr;
-  void* eval_scratch = nullptr;
+  // captured step (hipGraph), keyed by the buffers it was captured with
+  int use_graph = 0;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  const void* graph_key[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+  }
+  ~npfem_batch() { drop_graph(); }
 };
 
 namespace {
@@ -649,7 +667,7 @@ StepArgs<Real> make_args(npfem_batch* b) {
   a.meshes = static_cast<const MeshDev<Real>*>(p->d_meshdev);
   a.mat = {p->mat.B, p->mat.C, p->mat.D, p->mat.k_bend, p->mat.k_volume, p->mat.beta, p->mat.kappa};
   const double eps = std::is_same<Real, float>::value ? 1.1920928955078125e-07 : 2.220446049250313e-16;
-  a.sol = {p->dt, p->prm.tol, p->prm.c1, p->prm.noise_factor * eps, p->prm.lbfgs_m, p->prm.max_iter,
+  a.sol = {p->dt, p->prm.tol, p->prm.c1, p->prm.noise_factor * eps, b->m, p->prm.max_iter,
            p->prm.max_halvings, (p->prm.inverse_bf16 && std::is_same<Real, float>::value) ? 1 : 0};
   a.tiles = b->tiles;
   a.tile_cells = b->tile_cells;
@@ -666,33 +684,74 @@ StepArgs<Real> make_args(npfem_batch* b) {
   return a;
 }
 
+// (Re)build the schedule for T cells per tile and history length m: the tile list
+// (cells of one mesh type, largest meshes first since the cost grows like n^2), the
+// LDS size, the persistent grid and the workspace.
 template <typename Real>
-npfem_status batch_setup(npfem_batch* b) {
+npfem_status batch_schedule(npfem_batch* b, int T, int m) {
   npfem_plan* p = b->plan;
+  b->drop_graph();
+  b->sched.release();
+  b->T = T;
+  b->m = m;
+  const int nm = (int)p->meshes.size();
+  std::vector<int> order(nm);
+  for (int i = 0; i < nm; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int c) { return p->meshes[a].mesh->n > p->meshes[c].mesh->n; });
+  std::vector<TileDesc> tiles;
+  std::vector<int> tcells;
+  for (int mi : order) {
+    const auto& cl = b->by_mesh[mi];
+    for (size_t s0 = 0; s0 < cl.size(); s0 += T) {
+      TileDesc td;
+      td.mesh = mi;
+      td.count = (int)std::min<size_t>(T, cl.size() - s0);
+      td.first = (int)tcells.size();
+      td.pad = 0;
+      tcells.insert(tcells.end(), cl.begin() + s0, cl.begin() + s0 + td.count);
+      tiles.push_back(td);
+    }
+  }
+  b->n_tiles = (int)tiles.size();
+  npfem_status s;
+  if ((s = b->sched.upload(tiles.data(), tiles.size(), &b->tiles))) return s;
+  if ((s = b->sched.upload(tcells.data(), tcells.size(), &b->tile_cells))) return s;
   size_t lds = 0;
-  const int stage_rows = (p->prm.inverse_bf16 && std::is_same<Real, float>::value) ? 16 * ((3 * b->T + 15) / 16) : 0;
-  for (auto& mp : p->meshes) lds = std::max(lds, lds_bytes<Real>(mp.n_pad, mp.chunk, stage_rows));
+  const int stage_rows = (p->prm.inverse_bf16 && std::is_same<Real, float>::value) ? 16 * ((3 * T + 15) / 16) : 0;
+  for (int mi = 0; mi < nm; ++mi)
+    if (!b->by_mesh[mi].empty())
+      lds = std::max(lds, lds_bytes<Real>(p->meshes[mi].n_pad, p->meshes[mi].chunk, stage_rows));
   b->lds = lds;
   HIP_TRY(set_lds_limit<Real>(lds));
   int per_cu = 0;
   HIP_TRY(occupancy<Real>(&per_cu, lds));
-  if (per_cu < 1) return fail(NPFEM_E_UNSUPPORTED, "batch_create: step kernel does not fit on a compute unit");
+  if (per_cu < 1) return fail(NPFEM_E_UNSUPPORTED, "batch: step kernel does not fit on a compute unit");
   const int slots = p->cu_count * per_cu;
   b->grid = p->prm.grid_blocks > 0 ? p->prm.grid_blocks : slots;
   b->grid = std::max(1, std::min(b->grid, b->n_tiles));
-  b->n_vec = 6 + 2 * p->prm.lbfgs_m;
-  b->slot_stride = (int64_t)b->n_vec * b->T * 3 * b->n_pad_max;
-  npfem_status s;
+  b->n_vec = 6 + 2 * m;
+  b->slot_stride = (int64_t)b->n_vec * T * 3 * b->n_pad_max;
   const size_t wbytes = (size_t)b->grid * b->slot_stride * sizeof(Real);
-  if ((s = b->buf.alloc(wbytes, &b->work))) return s;
+  if ((s = b->sched.alloc(wbytes, &b->work))) return s;
   HIP_TRY(hipMemset(b->work, 0, wbytes));
   void* cs;
-  if ((s = b->buf.alloc((size_t)b->grid * b->T * sizeof(CellState), &cs))) return s;
+  if ((s = b->sched.alloc((size_t)b->grid * T * sizeof(CellState), &cs))) return s;
   b->cstate = static_cast<CellState*>(cs);
   void* c;
-  if ((s = b->buf.alloc(sizeof(int), &c))) return s;
+  if ((s = b->sched.alloc(sizeof(int), &c))) return s;
   b->counter = static_cast<int*>(c);
   return NPFEM_OK;
+}
+
+npfem_status schedule(npfem_batch* b, int T, int m) {
+  return b->plan->precision == NPFEM_FP64 ? batch_schedule<double>(b, T, m) : batch_schedule<float>(b, T, m);
+}
+
+int default_tile(const npfem_batch* b) {
+  // as many cells per tile as keep every compute unit busy (the matrix product runs 3T
+  // rows; T = 5, 10, 16 fill 16, 32, 48 rows)
+  const int64_t want = 2 * (int64_t)b->plan->cu_count;
+  return b->n_cells / 16 >= want ? 16 : (b->n_cells / 10 >= want ? 10 : 5);
 }
 
 }  // namespace
@@ -720,33 +779,7 @@ npfem_status npfem_batch_create(npfem_plan* p, int64_t n_cells, const int32_t* c
     by_mesh[mi].push_back((int)c);
   }
   b->n_vert = v;
-  // cells per tile: as many as keep every compute unit busy (the matrix product runs
-  // 3T rows; T = 5, 10, 16 fill 16, 32, 48 rows)
-  int T = p->prm.cells_per_tile;
-  if (T == 0) {
-    const int64_t want = 2 * (int64_t)p->cu_count;
-    T = n_cells / 16 >= want ? 16 : (n_cells / 10 >= want ? 10 : 5);
-  }
-  b->T = T;
-  // tiles of one mesh type, largest meshes first (cost grows like n^2)
-  std::vector<int> order(nm);
-  for (int i = 0; i < nm; ++i) order[i] = i;
-  std::sort(order.begin(), order.end(), [&](int a, int c) { return p->meshes[a].mesh->n > p->meshes[c].mesh->n; });
-  std::vector<TileDesc> tiles;
-  std::vector<int> tcells;
-  for (int mi : order) {
-    const auto& cl = by_mesh[mi];
-    for (size_t s0 = 0; s0 < cl.size(); s0 += T) {
-      TileDesc td;
-      td.mesh = mi;
-      td.count = (int)std::min<size_t>(T, cl.size() - s0);
-      td.first = (int)tcells.size();
-      td.pad = 0;
-      tcells.insert(tcells.end(), cl.begin() + s0, cl.begin() + s0 + td.count);
-      tiles.push_back(td);
-    }
-  }
-  b->n_tiles = (int)tiles.size();
+  b->by_mesh = by_mesh;
   b->n_pad_max = 0;
   std::vector<int> mesh_n(nm);
   for (int i = 0; i < nm; ++i) {
@@ -755,13 +788,11 @@ npfem_status npfem_batch_create(npfem_plan* p, int64_t n_cells, const int32_t* c
   }
   npfem_status s;
   std::vector<int> cm(cell_mesh, cell_mesh + n_cells);
-  if ((s = b->buf.upload(tiles.data(), tiles.size(), &b->tiles))) return s;
-  if ((s = b->buf.upload(tcells.data(), tcells.size(), &b->tile_cells))) return s;
   if ((s = b->buf.upload(voff.data(), voff.size(), &b->cell_voff))) return s;
   if ((s = b->buf.upload(cm.data(), cm.size(), &b->cell_mesh))) return s;
   if ((s = b->buf.upload(mesh_n.data(), mesh_n.size(), &b->mesh_n))) return s;
-  s = p->precision == NPFEM_FP64 ? batch_setup<double>(b.get()) : batch_setup<float>(b.get());
-  if (s) return s;
+  const int T = p->prm.cells_per_tile > 0 ? p->prm.cells_per_tile : default_tile(b.get());
+  if ((s = schedule(b.get(), T, p->prm.lbfgs_m))) return s;
   if (n_vert_out) *n_vert_out = v;
   *out = b.release();
   return NPFEM_OK;
@@ -773,11 +804,12 @@ void npfem_batch_destroy(npfem_batch* b) {
   delete b;
 }
 
-npfem_status npfem_step(npfem_batch* b, const void* x, const void* v, const void* f, void* x_out,
-                        void* v_out, const void* u_guess, npfem_cell_stats* stats, void* stream) {
-  if (!b || !x || !v || !f || !x_out || !v_out) return fail(NPFEM_E_INVALID, "step: NULL pointer");
-  HIP_TRY(hipSetDevice(b->plan->device));
-  hipStream_t s = static_cast<hipStream_t>(stream);
+}  // extern "C"
+
+namespace {
+
+npfem_status launch_step_now(npfem_batch* b, const void* x, const void* v, const void* f, void* x_out,
+                             void* v_out, const void* u_guess, npfem_cell_stats* stats, hipStream_t s) {
   if (b->plan->precision == NPFEM_FP64) {
     auto a = make_args<double>(b);
     a.x = static_cast<const double*>(x);
@@ -800,6 +832,111 @@ npfem_status npfem_step(npfem_batch* b, const void* x, const void* v, const void
     HIP_TRY(launch_step<float>(a, b->grid, b->lds, s, b->counter));
   }
   return NPFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+npfem_status npfem_step(npfem_batch* b, const void* x, const void* v, const void* f, void* x_out,
+                        void* v_out, const void* u_guess, npfem_cell_stats* stats, void* stream) {
+  if (!b || !x || !v || !f || !x_out || !v_out) return fail(NPFEM_E_INVALID, "step: NULL pointer");
+  HIP_TRY(hipSetDevice(b->plan->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!b->use_graph || s == nullptr) return launch_step_now(b, x, v, f, x_out, v_out, u_guess, stats, s);
+  // replay the captured launch sequence when the buffers and stream are the ones captured
+  const void* key[8] = {x, v, f, x_out, v_out, u_guess, stats, stream};
+  bool same = b->graph_exec != nullptr;
+  for (int k = 0; k < 8; ++k) same = same && key[k] == b->graph_key[k];
+  if (!same) {
+    b->drop_graph();
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    npfem_status st = launch_step_now(b, x, v, f, x_out, v_out, u_guess, stats, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    HIP_TRY(e);
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
+    for (int k = 0; k < 8; ++k) b->graph_key[k] = key[k];
+  }
+  HIP_TRY(hipGraphLaunch(b->graph_exec, s));
+  return NPFEM_OK;
+}
+
+npfem_status npfem_batch_set_graph(npfem_batch* b, int32_t use_graph) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch_set_graph: NULL batch");
+  b->use_graph = use_graph ? 1 : 0;
+  if (!b->use_graph) b->drop_graph();
+  return NPFEM_OK;
+}
+
+npfem_status npfem_batch_schedule(npfem_batch* b, int32_t cells_per_tile, int32_t lbfgs_m) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch_schedule: NULL batch");
+  if (cells_per_tile < 1 || cells_per_tile > kMaxTile) return fail(NPFEM_E_INVALID, "batch_schedule: cells_per_tile must be in [1, 21]");
+  if (lbfgs_m < 0 || lbfgs_m > kMaxHistory) return fail(NPFEM_E_INVALID, "batch_schedule: lbfgs_m must be in [0, 8]");
+  HIP_TRY(hipSetDevice(b->plan->device));
+  return schedule(b, cells_per_tile, lbfgs_m);
+}
+
+npfem_status npfem_batch_get_schedule(const npfem_batch* b, int32_t* cells_per_tile, int32_t* lbfgs_m,
+                                      int32_t* grid_blocks, int32_t* n_tiles) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch_get_schedule: NULL batch");
+  if (cells_per_tile) *cells_per_tile = b->T;
+  if (lbfgs_m) *lbfgs_m = b->m;
+  if (grid_blocks) *grid_blocks = b->grid;
+  if (n_tiles) *n_tiles = b->n_tiles;
+  return NPFEM_OK;
+}
+
+npfem_status npfem_batch_autotune(npfem_batch* b, const void* x, const void* v, const void* f, void* x_scratch,
+                                  void* v_scratch, int32_t max_lbfgs_m, void* stream, double* best_ms) {
+  if (!b || !x || !v || !f || !x_scratch || !v_scratch) return fail(NPFEM_E_INVALID, "batch_autotune: NULL pointer");
+  if (max_lbfgs_m < 0 || max_lbfgs_m > kMaxHistory) return fail(NPFEM_E_INVALID, "batch_autotune: bad max_lbfgs_m");
+  HIP_TRY(hipSetDevice(b->plan->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int use_graph = b->use_graph;
+  b->use_graph = 0;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best = 1e300;
+  int bT = b->T, bm = b->m;
+  const int Ts[] = {5, 10, 16, 21};
+  const int ms[] = {2, 3, 5, 8};
+  npfem_status st = NPFEM_OK;
+  for (int T : Ts) {
+    if ((int64_t)T > b->n_cells && T != 5) continue;
+    for (int m : ms) {
+      if (m > max_lbfgs_m && !(m == 2 && max_lbfgs_m < 2)) continue;
+      const int mm = std::min(m, max_lbfgs_m);
+      if ((st = schedule(b, T, mm))) break;
+      // one step to warm up, one timed
+      if ((st = launch_step_now(b, x, v, f, x_scratch, v_scratch, nullptr, nullptr, s))) break;
+      (void)hipEventRecord(e0, s);
+      if ((st = launch_step_now(b, x, v, f, x_scratch, v_scratch, nullptr, nullptr, s))) break;
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) { st = fail(NPFEM_E_HIP, "batch_autotune: event sync failed"); break; }
+      float ms_ = 0.f;
+      (void)hipEventElapsedTime(&ms_, e0, e1);
+      if (ms_ < best) {
+        best = ms_;
+        bT = T;
+        bm = mm;
+      }
+      if (mm != m) break;
+    }
+    if (st) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->use_graph = use_graph;
+  if (st) return st;
+  if (best_ms) *best_ms = best;
+  return schedule(b, bT, bm);
 }
 
 npfem_status npfem_eval(npfem_batch* b, const void* x, const void* v, const void* f, const void* u,

@@ -146,6 +146,33 @@ class Batch:
         sizes = np.array([m.n for m in plan.meshes])[self.cell_mesh]
         self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
 
+    def schedule(self, cells_per_tile: int | None = None, lbfgs_m: int | None = None) -> dict:
+        """Set (when given) and report the schedule: cells per tile, history length,
+        persistent workgroups, tiles."""
+        if cells_per_tile is not None or lbfgs_m is not None:
+            cur = self.schedule()
+            N.check(N.lib().npfem_batch_schedule(self._h, cells_per_tile or cur["cells_per_tile"],
+                                                 cur["lbfgs_m"] if lbfgs_m is None else lbfgs_m),
+                    "npfem_batch_schedule")
+        T, m, g, nt = c_int32(), c_int32(), c_int32(), c_int32()
+        N.check(N.lib().npfem_batch_get_schedule(self._h, byref(T), byref(m), byref(g), byref(nt)),
+                "npfem_batch_get_schedule")
+        return {"cells_per_tile": T.value, "lbfgs_m": m.value, "grid_blocks": g.value, "n_tiles": nt.value}
+
+    def autotune(self, x, v, f, max_lbfgs_m: int = 5, stream=None) -> dict:
+        """Time the candidate schedules on these inputs and keep the fastest."""
+        import torch
+        xs, vs = torch.empty_like(x), torch.empty_like(v)
+        best = c_double()
+        N.check(N.lib().npfem_batch_autotune(self._h, _dptr(x), _dptr(v), _dptr(f), _dptr(xs), _dptr(vs),
+                                             max_lbfgs_m, _stream(stream), byref(best)), "npfem_batch_autotune")
+        out = self.schedule()
+        out["best_ms"] = best.value
+        return out
+
+    def set_graph(self, use_graph: bool) -> None:
+        N.check(N.lib().npfem_batch_set_graph(self._h, 1 if use_graph else 0), "npfem_batch_set_graph")
+
     def _vec(self, t, name):
         if t.shape != (self.n_vertices, 3):
             raise ValueError(f"{name} must have shape ({self.n_vertices}, 3)")

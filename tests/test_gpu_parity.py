@@ -343,3 +343,52 @@ def test_drag_forces_kernel_matches_inputs_module():
                           T(b.shear_rate, torch.float64), T(b.origin, torch.float64),
                           p["umax"], p["radius"], p["axis_y"], p["axis_z"])
     np.testing.assert_allclose(f.cpu().numpy(), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_graph_replay_matches_eager_launch():
+    """The step captured in a HIP graph and replayed gives the eager result bit for bit,
+    on every replay, with unrelated eager work and synchronisations in between."""
+    from paper_1903_06479_amd import Batch
+    b = workloads.shear(n_cells=12, seed=21)
+    X, Tr = b.meshes[642]
+    x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
+    f = rounded(workloads.drag_forces(b, x, v), "fp32")
+    plan = make([(X, Tr)], "fp32", inverse_bf16=1)
+    ref = Batch(plan, np.zeros(12, np.int32))
+    xe, ve, _ = ref.step(T(x, torch.float32), T(v, torch.float32), T(f, torch.float32))
+    torch.cuda.synchronize()
+    g = Batch(plan, np.zeros(12, np.int32))
+    g.set_graph(True)
+    xi, vi, fi = T(x, torch.float32), T(v, torch.float32), T(f, torch.float32)
+    xo, vo = torch.empty_like(xi), torch.empty_like(vi)
+    st = torch.empty(12 * 40, dtype=torch.uint8, device=dev())
+    for rep in range(4):
+        xo.fill_(0.0)
+        g.step(xi, vi, fi, x_out=xo, v_out=vo, stats=st)
+        junk = (xi * 2.0).sum()                       # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(xo, xe) and torch.equal(vo, ve), rep
+        assert float(junk) == float(junk)
+
+
+def test_autotuner_keeps_the_solution():
+    from paper_1903_06479_amd import Batch, CONVERGED
+    b = workloads.shear(n_cells=40, seed=23)
+    X, Tr = b.meshes[642]
+    x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
+    f = rounded(workloads.drag_forces(b, x, v), "fp32")
+    plan = make([(X, Tr)], "fp32", inverse_bf16=1)
+    batch = Batch(plan, np.zeros(40, np.int32))
+    xi, vi, fi = T(x, torch.float32), T(v, torch.float32), T(f, torch.float32)
+    x0, _, _ = batch.step(xi, vi, fi)
+    best = batch.autotune(xi, vi, fi)
+    assert best["cells_per_tile"] in (5, 10, 16, 21) and best["lbfgs_m"] in (2, 3, 5) and best["best_ms"] > 0
+    x1, _, st = batch.step(xi, vi, fi)
+    torch.cuda.synchronize()
+    assert np.all(batch.stats_to_numpy(st)["status"] == CONVERGED)
+    assert (x1 - x0).abs().max().item() <= 1e-5 * np.ptp(X[:, 0])
+    batch.schedule(cells_per_tile=7, lbfgs_m=1)
+    assert batch.schedule()["cells_per_tile"] == 7
+    x2, _, st = batch.step(xi, vi, fi)
+    torch.cuda.synchronize()
+    assert (x2 - x0).abs().max().item() <= 1e-5 * np.ptp(X[:, 0])
