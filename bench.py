@@ -30,8 +30,57 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-MFMA_FP32_PEAK_TFLOPS = 157.3  # dense FP32 matrix
+VALU_FP32_PEAK_TFLOPS = 157.3  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
 N_CU = 256
+
+# Algorithmic arithmetic of one objective + gradient evaluation, counted operation by
+# operation from its formulas (add, mul, div, sqrt = 1 flop, fused multiply-add = 2):
+# per directed edge 21 (curvature vectors) + 9 (bending gradient), per triangle corner
+# 6 (gather), per triangle 237 single + 116 double (strain, SL(2) projection with three
+# Newton steps, Skalak, corner gradients, energies, volume), per vertex 120 (of which 60
+# in double: inertia, norms, residual sums).
+EVAL_FP32_PER = {"dir_edge": 30, "corner": 6, "tri": 237, "vert": 60}
+EVAL_FP64_PER = {"tri": 116, "vert": 60}
+
+
+def eval_flops(n, nt, ne):
+    f32 = EVAL_FP32_PER["dir_edge"] * 2 * ne + EVAL_FP32_PER["corner"] * 3 * nt + \
+        EVAL_FP32_PER["tri"] * nt + EVAL_FP32_PER["vert"] * n
+    f64 = EVAL_FP64_PER["tri"] * nt + EVAL_FP64_PER["vert"] * n
+    return f32, f64
+
+
+def measured_traffic():
+    """HBM bytes per step launch from the committed counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "step_kernel_throughput_100k_642.md")
+    if not os.path.exists(prof):
+        return None
+    kv = {}
+    for line in open(prof):
+        if ":" in line and not line.startswith(" "):
+            k, _, v = line.partition(":")
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("npfem_kernels.hip", "npfem_internal.h"):
+        with open(os.path.join(ROOT, "paper_1903_06479_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if kv.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def cell_step_flops(n, nt, ne, iters, evals, m):
+    """(VALU FP32, VALU FP64, matrix-core) flops of one cell-step with the given mean
+    iteration and evaluation counts: evaluations, the two-loop recursion and the
+    iterate/history updates (8m + 10 flops per unknown per iteration), the dissipation
+    (about 50 double flops per vertex), and (I + 1) products with the n x n inverses."""
+    e32, e64 = eval_flops(n, nt, ne)
+    f32 = evals * e32 + iters * (8 * m + 10) * 3 * n
+    f64 = evals * e64 + 50 * n
+    mfma = (iters + 1) * 2.0 * n * n * 3
+    return f32, f64, mfma
 
 
 def log(*a):
@@ -81,11 +130,14 @@ def main():
     ap.add_argument("--cells", type=int, default=100000)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cells-per-tile", type=int, default=0)
+    ap.add_argument("--lbfgs-m", type=int, default=0, help="history length when not autotuned (0: plan default)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-check", type=int, default=0,
+                    help="only copy a buffer of this many bytes 5 times (calibrates the HBM byte counters)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--fp32-products", action="store_true", help="FP32 instead of BF16 products with the inverses")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--cpu-sample", type=int, default=320)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the cells are independent, "
@@ -93,6 +145,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_check:
+        a = torch.ones(args.copy_check // 4, dtype=torch.float32, device="cuda:0")
+        c = torch.empty_like(a)
+        for _ in range(5):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": c.numel() * 4}), flush=True)
+        return
     from rbc_inputs import workloads
     from paper_1903_06479_amd import Batch, Mesh, Plan, default_params, CONVERGED
 
@@ -102,7 +162,8 @@ def main():
     params = default_params(tol=args.tol, cells_per_tile=args.cells_per_tile,
                             inverse_bf16=0 if args.fp32_products else 1)
     t0 = time.time()
-    plan = Plan([Mesh(X, T)], workloads.DT_US, params=params)
+    mesh = Mesh(X, T)
+    plan = Plan([mesh], workloads.DT_US, params=params)
     batch = Batch(plan, np.zeros(b.n_cells, np.int32))
     log(f"[bench] plan + batch in {time.time() - t0:.1f}s")
     x0 = torch.tensor(b.x, dtype=torch.float32, device=dev)
@@ -118,6 +179,8 @@ def main():
         t0 = time.time()
         tuned = batch.autotune(x, v, f, max_lbfgs_m=5)
         log(f"[bench] autotune {time.time() - t0:.1f}s -> {tuned}")
+    elif args.cells_per_tile or args.lbfgs_m:
+        batch.schedule(cells_per_tile=args.cells_per_tile or None, lbfgs_m=args.lbfgs_m or None)
     if not args.no_graph:
         batch.set_graph(True)
     xo, vo = torch.empty_like(x0), torch.empty_like(x0)
@@ -158,12 +221,17 @@ def main():
     cell_steps = b.n_cells * args.steps
     value = cell_steps / elapsed
     mean_kernel_s = float(np.mean(kernel_ms)) / 1e3
-    # algorithmic work of one step launch
-    I = float(np.mean(iters))
-    gemm_flops = b.n_cells * (I + 1.0) * 2.0 * n * n * 3.0          # (I + 1) products with n x n inverses
+    # algorithmic work of one step launch (the step kernel dominates the step)
+    I, E = float(np.mean(iters)), float(np.mean(evals))
+    sched = batch.schedule()
+    f32, f64, mfma = cell_step_flops(n, mesh.nt, mesh.ne, I, E, sched["lbfgs_m"])
+    # vector arithmetic in FP32-equivalent flops: a double flop costs two single ones
+    alu_flops = b.n_cells * (f32 + 2.0 * f64)
     io_bytes = b.n_cells * 60.0 * n                                  # x, v, f in; x, v out (FP32)
-    roof = {"bound": "mfma", "achieved": gemm_flops / mean_kernel_s / 1e12, "peak": MFMA_FP32_PEAK_TFLOPS,
+    roof = {"bound": "alu", "achieved": alu_flops / mean_kernel_s / 1e12, "peak": VALU_FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": None, "traffic": None}
+    if b.n_cells == 100000 and sched["cells_per_tile"] == 5 and sched["lbfgs_m"] == 2:
+        roof["traffic"] = measured_traffic()
     roof["frac"] = roof["achieved"] / roof["peak"]
     out = {
         "metric": "RBC cell-steps/sec at residual <=1e-6 (plain quasi-Newton)",
@@ -176,6 +244,9 @@ def main():
                    "inverse_products": "fp32" if args.fp32_products else "bf16 off-diagonal + fp32 diagonal",
                    "hip_graph": not args.no_graph},
         "roofline": roof,
+        "work_per_cell_step": {"valu_fp32_flops": f32, "valu_fp64_flops": f64, "mfma_flops": mfma,
+                               "state_bytes": 60.0 * n},
+        "mfma_TFLOPs": b.n_cells * mfma / mean_kernel_s / 1e12,
         "step_kernel_ms": float(np.mean(kernel_ms)),
         "iterations_mean": I, "iterations_max": int(np.max(iters)), "evaluations_mean": float(np.mean(evals)),
         "converged_fraction": conv,
