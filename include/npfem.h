@@ -239,6 +239,83 @@ npfem_status npfem_apply_inverse(npfem_plan *plan, int32_t mesh_index, int32_t w
                                  void *stream);
 
 /*
+ * First guess of the step (Algorithm 1, first line): u_out = y_n - x_n = h^2 M~^-1 b
+ * with b = M v_n / h + f_ext, for every cell.  x, v, f_ext, u_out: device [V_total][3]
+ * in the plan's precision.  Used to form the training targets of the learned warm start.
+ */
+npfem_status npfem_first_guess(npfem_batch *batch, const void *x, const void *v, const void *f_ext,
+                               void *u_out, void *stream);
+
+/*
+ * Learned warm start.  The paper starts every step from y_n; this network predicts the
+ * correction delta = x_{n+1} - y_n per vertex so that the iteration starts closer to its
+ * fixed point (the fixed point itself does not depend on the start).  Per cell, the
+ * inputs are expressed in the cell's best-fit rest frame R (mass-weighted Kabsch fit of
+ * the rest mesh to x_n), as 12 features per vertex: shape deviation
+ * (R^T (x_i - x_c) - (X_i - X_c)) / shape_scale, velocity R^T (v_i - v_c) h / s, force
+ * R^T (f_i - m_i a_c) h^2 / (m_i s) and rest position (X_i - X_c) / max|X - X_c|, with the
+ * displacement scale s = h^2 (rms_i |f_i - m_i a_c| + force_floor) / mean(m).  The network
+ * is a residual GraphSAGE: h = relu(W_e feat + b_e), then `layers` times
+ * h <- h + relu(W_s h + W_n mean_{mesh neighbours}(h) + b), then o = W_d h + b_d and
+ * delta_i = s R o_i.  Hidden width 64.  Weights are applied as BF16 on the matrix cores
+ * with FP32 accumulation; activations are stored in BF16; frame and sums in FP64.
+ *
+ * Parameters: one FP32 vector, row-major blocks in this order: W_e [64][12], b_e [64],
+ * per layer W_s [64][64], W_n [64][64], b [64], then W_d [3][64], b_d [3].
+ * A network belongs to one plan (its mesh types) and one device.
+ */
+typedef struct npfem_net npfem_net;
+typedef struct {
+  int32_t hidden;        /* must be 64 */
+  int32_t layers;        /* message-passing layers, 1..8 */
+  double force_floor;    /* force floor of the displacement scale (force units) */
+  double shape_scale;    /* length scale of the shape-deviation features */
+} npfem_net_config;
+
+void npfem_net_config_default(npfem_net_config *cfg);  /* 64, 4, 1.0, 0.1 */
+int64_t npfem_net_param_count(const npfem_net_config *cfg);   /* -1 for an invalid config */
+/* theta: host FP32 [param_count] initial parameters (copied). */
+npfem_status npfem_net_create(npfem_plan *plan, const npfem_net_config *cfg, const float *theta,
+                              npfem_net **out);
+void npfem_net_destroy(npfem_net *net);
+npfem_status npfem_net_set_params(npfem_net *net, const float *theta);   /* host FP32; resets Adam */
+npfem_status npfem_net_get_params(const npfem_net *net, float *theta);   /* host FP32 */
+
+/*
+ * Inference: delta_out (device [V_total][3], plan precision) = predicted correction of
+ * every cell of the batch, world frame.
+ */
+npfem_status npfem_net_infer(npfem_net *net, npfem_batch *batch, const void *x, const void *v,
+                             const void *f_ext, void *delta_out, void *stream);
+
+/*
+ * One step that starts from y_n + delta (delta from the network) instead of y_n; otherwise
+ * identical to npfem_step (same outputs, statistics and convergence test).  Honours the
+ * batch's graph setting (the network and the step are captured together).
+ */
+npfem_status npfem_step_learned(npfem_batch *batch, npfem_net *net, const void *x, const void *v,
+                                const void *f_ext, void *x_out, void *v_out,
+                                npfem_cell_stats *stats, void *stream);
+
+/*
+ * Training.  For the cells listed in `cells` (device int32 [n_cells] batch cell indices,
+ * or NULL for cells 0..n_cells-1), with inputs x, v, f_ext, the converged x_next and the
+ * first guess u0 (all device [V_total][3], plan precision), the loss is the mean over
+ * the listed cells, their vertices and the 3 components of (o_i - t_i)^2 with target
+ * t_i = R^T (x_next_i - x_i - u0_i) / s.  loss_out (host, may be NULL) receives the loss
+ * (the call then synchronises the stream); grad_out (device FP32 [param_count]) the
+ * gradient with respect to the parameters, summed in a fixed order (deterministic).
+ */
+npfem_status npfem_net_loss_grad(npfem_net *net, npfem_batch *batch, const int32_t *cells,
+                                 int32_t n_cells, const void *x, const void *v, const void *f_ext,
+                                 const void *x_next, const void *u0, double *loss_out,
+                                 float *grad_out, void *stream);
+/* Adam (Kingma & Ba) on the FP32 parameters with a device FP32 gradient; t counts
+ * the updates since creation or the last set_params, from 1. */
+npfem_status npfem_net_adam_step(npfem_net *net, const float *grad, double lr, double beta1,
+                                 double beta2, double eps, void *stream);
+
+/*
  * Stand-in for the fluid (not part of the method): per-vertex Stokes drag towards an
  * analytic flow, f = zeta_c (u(x) - v) with u = [rate_c * z + u_P] e_x, where
  * u_P = umax (1 - rho^2/R^2) for rho < R, rho^2 = (oy_c + y - axis_y)^2 + (oz_c + z - axis_z)^2.

@@ -25,6 +25,10 @@ class SolverParams(ctypes.Structure):
                 ("inverse_bf16", c_int32)]
 
 
+class NetConfig(ctypes.Structure):
+    _fields_ = [("hidden", c_int32), ("layers", c_int32), ("force_floor", c_double), ("shape_scale", c_double)]
+
+
 CELL_STATS_DTYPE = np.dtype([("iterations", np.int32), ("evaluations", np.int32),
                              ("status", np.uint32), ("halvings", np.int32), ("residual", np.float64),
                              ("objective", np.float64), ("volume", np.float64)])
@@ -58,6 +62,18 @@ _SIGNATURES = {
     "npfem_apply_inverse": (c_int32, [c_void_p, c_int32, c_int32, _P, _P, c_int32, _P, _P]),
     "npfem_drag_forces": (c_int32, [c_void_p, _P, _P, _P, _P, _P, c_double, c_double, c_double,
                                     c_double, _P, _P]),
+    "npfem_first_guess": (c_int32, [c_void_p, _P, _P, _P, _P, _P]),
+    "npfem_net_config_default": (None, [POINTER(NetConfig)]),
+    "npfem_net_param_count": (c_int64, [POINTER(NetConfig)]),
+    "npfem_net_create": (c_int32, [c_void_p, POINTER(NetConfig), _P, POINTER(c_void_p)]),
+    "npfem_net_destroy": (None, [c_void_p]),
+    "npfem_net_set_params": (c_int32, [c_void_p, _P]),
+    "npfem_net_get_params": (c_int32, [c_void_p, _P]),
+    "npfem_net_infer": (c_int32, [c_void_p, c_void_p, _P, _P, _P, _P, _P]),
+    "npfem_step_learned": (c_int32, [c_void_p, c_void_p, _P, _P, _P, _P, _P, _P, _P]),
+    "npfem_net_loss_grad": (c_int32, [c_void_p, c_void_p, _P, c_int32, _P, _P, _P, _P, _P, POINTER(c_double),
+                                      _P, _P]),
+    "npfem_net_adam_step": (c_int32, [c_void_p, _P, c_double, c_double, c_double, c_double, _P]),
 }
 
 _lib = None

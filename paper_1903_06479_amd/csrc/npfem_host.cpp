@@ -14,6 +14,7 @@
 
 #include "npfem.h"
 #include "npfem_internal.h"
+#include "npfem_net_internal.h"
 
 using namespace npfem;
 
@@ -648,7 +649,10 @@ struct npfem_batch {
   int use_graph = 0;
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
-  const void* graph_key[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void* graph_key[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // learned warm start: the predicted correction of every vertex (allocated on first use)
+  DeviceBuffers dbuf;
+  void* delta = nullptr;
   void drop_graph() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -809,13 +813,16 @@ void npfem_batch_destroy(npfem_batch* b) {
 namespace {
 
 npfem_status launch_step_now(npfem_batch* b, const void* x, const void* v, const void* f, void* x_out,
-                             void* v_out, const void* u_guess, npfem_cell_stats* stats, hipStream_t s) {
+                             void* v_out, const void* u_guess, npfem_cell_stats* stats, hipStream_t s,
+                             const void* u_delta = nullptr, int guess_only = 0) {
   if (b->plan->precision == NPFEM_FP64) {
     auto a = make_args<double>(b);
     a.x = static_cast<const double*>(x);
     a.v = static_cast<const double*>(v);
     a.f = static_cast<const double*>(f);
     a.u_guess = static_cast<const double*>(u_guess);
+    a.u_delta = static_cast<const double*>(u_delta);
+    a.guess_only = guess_only;
     a.x_out = static_cast<double*>(x_out);
     a.v_out = static_cast<double*>(v_out);
     a.stats = stats;
@@ -826,11 +833,39 @@ npfem_status launch_step_now(npfem_batch* b, const void* x, const void* v, const
     a.v = static_cast<const float*>(v);
     a.f = static_cast<const float*>(f);
     a.u_guess = static_cast<const float*>(u_guess);
+    a.u_delta = static_cast<const float*>(u_delta);
+    a.guess_only = guess_only;
     a.x_out = static_cast<float*>(x_out);
     a.v_out = static_cast<float*>(v_out);
     a.stats = stats;
     HIP_TRY(launch_step<float>(a, b->grid, b->lds, s, b->counter));
   }
+  return NPFEM_OK;
+}
+
+// Run `launch` on stream s, directly or through the batch's captured graph: the graph
+// is (re)captured when the key (buffers, stream, network) differs from the captured one.
+template <typename F>
+npfem_status run_maybe_graph(npfem_batch* b, const void* const (&key)[9], hipStream_t s, F launch) {
+  if (!b->use_graph || s == nullptr) return launch();
+  bool same = b->graph_exec != nullptr;
+  for (int k = 0; k < 9; ++k) same = same && key[k] == b->graph_key[k];
+  if (!same) {
+    b->drop_graph();
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    npfem_status st = launch();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    HIP_TRY(e);
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
+    for (int k = 0; k < 9; ++k) b->graph_key[k] = key[k];
+  }
+  HIP_TRY(hipGraphLaunch(b->graph_exec, s));
   return NPFEM_OK;
 }
 
@@ -843,28 +878,15 @@ npfem_status npfem_step(npfem_batch* b, const void* x, const void* v, const void
   if (!b || !x || !v || !f || !x_out || !v_out) return fail(NPFEM_E_INVALID, "step: NULL pointer");
   HIP_TRY(hipSetDevice(b->plan->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (!b->use_graph || s == nullptr) return launch_step_now(b, x, v, f, x_out, v_out, u_guess, stats, s);
-  // replay the captured launch sequence when the buffers and stream are the ones captured
-  const void* key[8] = {x, v, f, x_out, v_out, u_guess, stats, stream};
-  bool same = b->graph_exec != nullptr;
-  for (int k = 0; k < 8; ++k) same = same && key[k] == b->graph_key[k];
-  if (!same) {
-    b->drop_graph();
-    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    npfem_status st = launch_step_now(b, x, v, f, x_out, v_out, u_guess, stats, s);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(s, &g);
-    if (st) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
-    }
-    HIP_TRY(e);
-    b->graph = g;
-    HIP_TRY(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
-    for (int k = 0; k < 8; ++k) b->graph_key[k] = key[k];
-  }
-  HIP_TRY(hipGraphLaunch(b->graph_exec, s));
-  return NPFEM_OK;
+  const void* const key[9] = {x, v, f, x_out, v_out, u_guess, stats, stream, nullptr};
+  return run_maybe_graph(b, key, s, [&] { return launch_step_now(b, x, v, f, x_out, v_out, u_guess, stats, s); });
+}
+
+npfem_status npfem_first_guess(npfem_batch* b, const void* x, const void* v, const void* f, void* u_out,
+                               void* stream) {
+  if (!b || !x || !v || !f || !u_out) return fail(NPFEM_E_INVALID, "first_guess: NULL pointer");
+  HIP_TRY(hipSetDevice(b->plan->device));
+  return launch_step_now(b, x, v, f, u_out, u_out, nullptr, nullptr, static_cast<hipStream_t>(stream), nullptr, 1);
 }
 
 npfem_status npfem_batch_set_graph(npfem_batch* b, int32_t use_graph) {
@@ -1012,6 +1034,396 @@ npfem_status npfem_drag_forces(npfem_batch* b, const void* x, const void* v, con
     HIP_TRY(launch_drag<float>(static_cast<const float*>(x), static_cast<const float*>(v), b->cell_voff,
                                b->cell_mesh, b->mesh_n, (int)b->n_cells, zeta, rate, origin, umax, radius, ay,
                                az, static_cast<float*>(f), s));
+  return NPFEM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Learned warm start
+// ---------------------------------------------------------------------------------
+
+struct npfem_net {
+  npfem_plan* plan = nullptr;
+  NetLayout lay{};
+  double force_floor = 1.0, shape_scale = 0.1;
+  DeviceBuffers buf;                        // parameters, optimiser state, BF16 weights, meshes
+  float* theta = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  uint16_t *We = nullptr, *Wl = nullptr, *WsT = nullptr, *WnT = nullptr, *Wd = nullptr;
+  const NetMeshDev* d_meshes = nullptr;
+  int n_pad_max = 0;
+  int adam_t = 0;
+  // inference scratch: per workgroup, features and two activation planes
+  DeviceBuffers ibuf;
+  int igrid = 0;
+  uint16_t *ifeat = nullptr, *iH = nullptr;
+  // training scratch, sized for the largest minibatch seen
+  DeviceBuffers tbuf;
+  int tcap = 0, bgrid = 0;
+  uint16_t *tfeat = nullptr, *tH = nullptr, *tZ = nullptr, *dZ = nullptr;
+  double *tframe = nullptr, *tloss = nullptr;
+  float *tout = nullptr, *tdout = nullptr, *dH = nullptr, *Q = nullptr, *partial = nullptr;
+
+  NetWeights weights() const {
+    NetWeights w;
+    w.lay = lay;
+    w.force_floor = force_floor;
+    w.shape_scale = shape_scale;
+    w.theta = theta;
+    w.We = We;
+    w.Wl = Wl;
+    w.WsT = WsT;
+    w.WnT = WnT;
+    w.Wd = Wd;
+    return w;
+  }
+};
+
+namespace {
+
+bool net_config_ok(const npfem_net_config* c) {
+  return c && c->hidden == kNetH && c->layers >= 1 && c->layers <= kNetMaxLayers && c->force_floor > 0.0 &&
+         c->shape_scale > 0.0 && std::isfinite(c->force_floor) && std::isfinite(c->shape_scale);
+}
+
+npfem_status net_upload_params(npfem_net* net, const float* theta, hipStream_t s) {
+  for (int64_t i = 0; i < net->lay.count; ++i)
+    if (!std::isfinite(theta[i])) return fail(NPFEM_E_INVALID, "net: non-finite parameter");
+  HIP_TRY(hipMemcpy(net->theta, theta, net->lay.count * sizeof(float), hipMemcpyHostToDevice));
+  HIP_TRY(launch_fill_zero(net->adam_m, net->lay.count, s));
+  HIP_TRY(launch_fill_zero(net->adam_v, net->lay.count, s));
+  HIP_TRY(launch_net_pack(net->weights(), net->We, net->Wl, net->WsT, net->WnT, net->Wd, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  net->adam_t = 0;
+  return NPFEM_OK;
+}
+
+npfem_status net_check_batch(const npfem_net* net, const npfem_batch* b) {
+  if (net->plan != b->plan) return fail(NPFEM_E_INVALID, "net: batch belongs to another plan");
+  return NPFEM_OK;
+}
+
+npfem_status net_inference_scratch(npfem_net* net) {
+  if (net->ibuf.ptrs.size()) return NPFEM_OK;
+  net->igrid = 4 * net->plan->cu_count;
+  const size_t np = (size_t)net->n_pad_max;
+  void* p;
+  npfem_status s;
+  if ((s = net->ibuf.alloc((size_t)net->igrid * np * kNetFeatPad * 2, &p))) return s;
+  net->ifeat = static_cast<uint16_t*>(p);
+  if ((s = net->ibuf.alloc((size_t)net->igrid * 2 * np * kNetH * 2, &p))) return s;
+  net->iH = static_cast<uint16_t*>(p);
+  return NPFEM_OK;
+}
+
+npfem_status net_training_scratch(npfem_net* net, int cells) {
+  if (cells <= net->tcap) return NPFEM_OK;
+  net->tbuf.release();
+  net->tcap = 0;
+  const size_t np = (size_t)net->n_pad_max, L1 = (size_t)net->lay.layers + 1, C = (size_t)cells;
+  net->bgrid = std::max(1, std::min(cells, net->plan->cu_count));
+  const size_t G = (size_t)net->bgrid;
+  void* p;
+  npfem_status s;
+  if ((s = net->tbuf.alloc(C * np * kNetFeatPad * 2, &p))) return s;
+  net->tfeat = static_cast<uint16_t*>(p);
+  if ((s = net->tbuf.alloc(C * L1 * np * kNetH * 2, &p))) return s;
+  net->tH = static_cast<uint16_t*>(p);
+  if ((s = net->tbuf.alloc(C * L1 * np * kNetH * 2, &p))) return s;
+  net->tZ = static_cast<uint16_t*>(p);
+  if ((s = net->tbuf.alloc(C * 12 * sizeof(double), &p))) return s;
+  net->tframe = static_cast<double*>(p);
+  if ((s = net->tbuf.alloc(C * sizeof(double), &p))) return s;
+  net->tloss = static_cast<double*>(p);
+  if ((s = net->tbuf.alloc(C * np * 3 * sizeof(float), &p))) return s;
+  net->tout = static_cast<float*>(p);
+  if ((s = net->tbuf.alloc(C * np * 3 * sizeof(float), &p))) return s;
+  net->tdout = static_cast<float*>(p);
+  if ((s = net->tbuf.alloc(G * 2 * np * kNetH * sizeof(float), &p))) return s;
+  net->dH = static_cast<float*>(p);
+  if ((s = net->tbuf.alloc(G * np * kNetH * sizeof(float), &p))) return s;
+  net->Q = static_cast<float*>(p);
+  if ((s = net->tbuf.alloc(G * np * kNetH * 2, &p))) return s;
+  net->dZ = static_cast<uint16_t*>(p);
+  if ((s = net->tbuf.alloc(G * (size_t)net->lay.count * sizeof(float), &p))) return s;
+  net->partial = static_cast<float*>(p);
+  net->tcap = cells;
+  return NPFEM_OK;
+}
+
+template <typename Real>
+NetFwdArgs<Real> net_fwd_args(const npfem_net* net, const npfem_batch* b, const void* x, const void* v,
+                              const void* f) {
+  NetFwdArgs<Real> a{};
+  a.W = net->weights();
+  a.meshes = net->d_meshes;
+  a.cell_voff = b->cell_voff;
+  a.cell_mesh = b->cell_mesh;
+  a.h = b->plan->dt;
+  a.x = static_cast<const Real*>(x);
+  a.v = static_cast<const Real*>(v);
+  a.f = static_cast<const Real*>(f);
+  a.S.n_pad_max = net->n_pad_max;
+  return a;
+}
+
+template <typename Real>
+npfem_status net_infer_now(npfem_net* net, npfem_batch* b, const void* x, const void* v, const void* f,
+                           void* delta, hipStream_t s) {
+  auto a = net_fwd_args<Real>(net, b, x, v, f);
+  a.S.feat = net->ifeat;
+  a.S.H = net->iH;
+  a.S.train = 0;
+  a.n_cells = (int)b->n_cells;
+  a.delta = static_cast<Real*>(delta);
+  HIP_TRY(launch_net_forward<Real>(a, std::max(1, std::min(net->igrid, (int)b->n_cells)), s));
+  return NPFEM_OK;
+}
+
+npfem_status net_infer_any(npfem_net* net, npfem_batch* b, const void* x, const void* v, const void* f,
+                           void* delta, hipStream_t s) {
+  return b->plan->precision == NPFEM_FP64 ? net_infer_now<double>(net, b, x, v, f, delta, s)
+                                          : net_infer_now<float>(net, b, x, v, f, delta, s);
+}
+
+template <typename Real>
+npfem_status net_loss_grad_now(npfem_net* net, npfem_batch* b, const int32_t* cells, int n_cells,
+                               const void* x, const void* v, const void* f, const void* x_next, const void* u0,
+                               double* loss_out, float* grad_out, hipStream_t s) {
+  auto a = net_fwd_args<Real>(net, b, x, v, f);
+  a.S.feat = net->tfeat;
+  a.S.H = net->tH;
+  a.S.Z = net->tZ;
+  a.S.frame = net->tframe;
+  a.S.out = net->tout;
+  a.S.train = 1;
+  a.cells = cells;
+  a.n_cells = n_cells;
+  HIP_TRY(launch_net_forward<Real>(a, std::max(1, std::min(4 * net->plan->cu_count, n_cells)), s));
+  // nodes of the listed cells (for the mean)
+  int64_t nodes = 0;
+  if (cells) {
+    std::vector<int32_t> hc(n_cells);
+    HIP_TRY(hipMemcpyAsync(hc.data(), cells, n_cells * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int> cm(b->n_cells);
+    for (int k = 0; k < n_cells; ++k) {
+      if (hc[k] < 0 || hc[k] >= b->n_cells) return fail(NPFEM_E_INVALID, "net_loss_grad: cell index out of range");
+    }
+    for (size_t mi = 0; mi < b->by_mesh.size(); ++mi)
+      for (int c : b->by_mesh[mi]) cm[c] = (int)mi;
+    for (int k = 0; k < n_cells; ++k) nodes += b->plan->meshes[cm[hc[k]]].mesh->n;
+  } else {
+    for (size_t mi = 0; mi < b->by_mesh.size(); ++mi)
+      for (int c : b->by_mesh[mi])
+        if (c < n_cells) nodes += b->plan->meshes[mi].mesh->n;
+  }
+  NetLossArgs<Real> la{};
+  la.S = a.S;
+  la.meshes = net->d_meshes;
+  la.cell_voff = b->cell_voff;
+  la.cell_mesh = b->cell_mesh;
+  la.cells = cells;
+  la.n_cells = n_cells;
+  la.inv_count = 1.0 / (3.0 * (double)nodes);
+  la.x = static_cast<const Real*>(x);
+  la.x_next = static_cast<const Real*>(x_next);
+  la.u0 = static_cast<const Real*>(u0);
+  la.dout = net->tdout;
+  la.cell_loss = net->tloss;
+  HIP_TRY(launch_net_loss<Real>(la, s));
+  NetBwdArgs ba{};
+  ba.W = net->weights();
+  ba.S = a.S;
+  ba.meshes = net->d_meshes;
+  ba.cell_mesh = b->cell_mesh;
+  ba.cells = cells;
+  ba.n_cells = n_cells;
+  ba.dout = net->tdout;
+  ba.dH = net->dH;
+  ba.Q = net->Q;
+  ba.dZ = net->dZ;
+  ba.partial = net->partial;
+  const int g = std::max(1, std::min(net->bgrid, n_cells));
+  HIP_TRY(launch_fill_zero(net->partial, (int64_t)g * net->lay.count, s));
+  HIP_TRY(launch_net_backward(ba, g, s));
+  HIP_TRY(launch_net_reduce(net->partial, g, net->lay.count, grad_out, s));
+  if (loss_out) {
+    std::vector<double> cl(n_cells);
+    HIP_TRY(hipMemcpyAsync(cl.data(), net->tloss, n_cells * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (double c : cl) t += c;
+    *loss_out = t * la.inv_count;
+  }
+  return NPFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void npfem_net_config_default(npfem_net_config* c) {
+  if (!c) return;
+  c->hidden = kNetH;
+  c->layers = 4;
+  c->force_floor = 1.0;
+  c->shape_scale = 0.1;
+}
+
+int64_t npfem_net_param_count(const npfem_net_config* c) {
+  if (!net_config_ok(c)) return -1;
+  return net_layout(c->layers).count;
+}
+
+npfem_status npfem_net_create(npfem_plan* p, const npfem_net_config* cfg, const float* theta, npfem_net** out) {
+  if (!p || !cfg || !theta || !out) return fail(NPFEM_E_INVALID, "net_create: NULL pointer");
+  *out = nullptr;
+  if (!net_config_ok(cfg)) return fail(NPFEM_E_INVALID, "net_create: hidden must be 64, layers 1..8, scales > 0");
+  HIP_TRY(hipSetDevice(p->device));
+  auto net = std::make_unique<npfem_net>();
+  net->plan = p;
+  net->lay = net_layout(cfg->layers);
+  net->force_floor = cfg->force_floor;
+  net->shape_scale = cfg->shape_scale;
+  const int64_t P = net->lay.count;
+  void* q;
+  npfem_status s;
+  for (float** dst : {&net->theta, &net->adam_m, &net->adam_v}) {
+    if ((s = net->buf.alloc(P * sizeof(float), &q))) return s;
+    *dst = static_cast<float*>(q);
+  }
+  const size_t nL = (size_t)cfg->layers * kNetH * kNetH;
+  if ((s = net->buf.alloc((size_t)kNetH * kNetFeatPad * 2, &q))) return s;
+  net->We = static_cast<uint16_t*>(q);
+  if ((s = net->buf.alloc(2 * nL * 2, &q))) return s;
+  net->Wl = static_cast<uint16_t*>(q);
+  if ((s = net->buf.alloc(nL * 2, &q))) return s;
+  net->WsT = static_cast<uint16_t*>(q);
+  if ((s = net->buf.alloc(nL * 2, &q))) return s;
+  net->WnT = static_cast<uint16_t*>(q);
+  if ((s = net->buf.alloc(3 * kNetH * 2, &q))) return s;
+  net->Wd = static_cast<uint16_t*>(q);
+  // per mesh type: rest positions about the mass-weighted centroid, masses, neighbours
+  std::vector<NetMeshDev> md(p->meshes.size());
+  for (size_t mi = 0; mi < p->meshes.size(); ++mi) {
+    const MeshPlan& mp = p->meshes[mi];
+    const npfem_mesh* m = mp.mesh;
+    NetMeshDev& d = md[mi];
+    d.n = m->n;
+    d.n_pad = mp.n_pad;
+    net->n_pad_max = std::max(net->n_pad_max, mp.n_pad);
+    double ms = 0.0, c[3] = {0, 0, 0};
+    for (int i = 0; i < m->n; ++i) {
+      ms += mp.mass[i];
+      for (int k = 0; k < 3; ++k) c[k] += mp.mass[i] * m->X[3 * i + k];
+    }
+    std::vector<double> Xc(3 * (size_t)m->n);
+    double rho = 0.0;
+    for (int i = 0; i < m->n; ++i) {
+      double r2 = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        Xc[3 * i + k] = m->X[3 * i + k] - c[k] / ms;
+        r2 += Xc[3 * i + k] * Xc[3 * i + k];
+      }
+      rho = std::max(rho, std::sqrt(r2));
+    }
+    for (int i = 0; i < m->n; ++i)
+      if (m->nb_ptr[i + 1] == m->nb_ptr[i]) return fail(NPFEM_E_MESH, "net_create: vertex without neighbours");
+    d.inv_rho = 1.0 / rho;
+    d.mass_sum = ms;
+    d.mass_mean = ms / m->n;
+    d.nb_ptr = p->precision == NPFEM_FP64 ? mp.dev64.nb_ptr : mp.dev32.nb_ptr;
+    d.nb_idx = p->precision == NPFEM_FP64 ? mp.dev64.nb_idx : mp.dev32.nb_idx;
+    if ((s = net->buf.upload(Xc.data(), Xc.size(), &d.Xc))) return s;
+    if ((s = net->buf.upload(mp.mass.data(), mp.mass.size(), &d.mass))) return s;
+  }
+  if ((s = net->buf.upload(md.data(), md.size(), &net->d_meshes))) return s;
+  if ((s = net_upload_params(net.get(), theta, nullptr))) return s;
+  *out = net.release();
+  return NPFEM_OK;
+}
+
+void npfem_net_destroy(npfem_net* net) {
+  if (!net) return;
+  (void)hipSetDevice(net->plan->device);
+  delete net;
+}
+
+npfem_status npfem_net_set_params(npfem_net* net, const float* theta) {
+  if (!net || !theta) return fail(NPFEM_E_INVALID, "net_set_params: NULL pointer");
+  HIP_TRY(hipSetDevice(net->plan->device));
+  HIP_TRY(hipDeviceSynchronize());
+  return net_upload_params(net, theta, nullptr);
+}
+
+npfem_status npfem_net_get_params(const npfem_net* net, float* theta) {
+  if (!net || !theta) return fail(NPFEM_E_INVALID, "net_get_params: NULL pointer");
+  HIP_TRY(hipSetDevice(net->plan->device));
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(theta, net->theta, net->lay.count * sizeof(float), hipMemcpyDeviceToHost));
+  return NPFEM_OK;
+}
+
+npfem_status npfem_net_infer(npfem_net* net, npfem_batch* b, const void* x, const void* v, const void* f,
+                             void* delta, void* stream) {
+  if (!net || !b || !x || !v || !f || !delta) return fail(NPFEM_E_INVALID, "net_infer: NULL pointer");
+  npfem_status s;
+  if ((s = net_check_batch(net, b))) return s;
+  HIP_TRY(hipSetDevice(b->plan->device));
+  if ((s = net_inference_scratch(net))) return s;
+  return net_infer_any(net, b, x, v, f, delta, static_cast<hipStream_t>(stream));
+}
+
+npfem_status npfem_step_learned(npfem_batch* b, npfem_net* net, const void* x, const void* v, const void* f,
+                                void* x_out, void* v_out, npfem_cell_stats* stats, void* stream) {
+  if (!net || !b || !x || !v || !f || !x_out || !v_out) return fail(NPFEM_E_INVALID, "step_learned: NULL pointer");
+  npfem_status s;
+  if ((s = net_check_batch(net, b))) return s;
+  HIP_TRY(hipSetDevice(b->plan->device));
+  if ((s = net_inference_scratch(net))) return s;
+  if (!b->delta) {
+    const size_t bytes = (size_t)b->n_vert * 3 * (b->plan->precision == NPFEM_FP64 ? 8 : 4);
+    if ((s = b->dbuf.alloc(bytes, &b->delta))) return s;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const void* const key[9] = {x, v, f, x_out, v_out, b->delta, stats, stream, net};
+  return run_maybe_graph(b, key, st, [&]() -> npfem_status {
+    npfem_status r;
+    if ((r = net_infer_any(net, b, x, v, f, b->delta, st))) return r;
+    return launch_step_now(b, x, v, f, x_out, v_out, nullptr, stats, st, b->delta, 0);
+  });
+}
+
+npfem_status npfem_net_loss_grad(npfem_net* net, npfem_batch* b, const int32_t* cells, int32_t n_cells,
+                                 const void* x, const void* v, const void* f, const void* x_next, const void* u0,
+                                 double* loss_out, float* grad_out, void* stream) {
+  if (!net || !b || !x || !v || !f || !x_next || !u0 || !grad_out)
+    return fail(NPFEM_E_INVALID, "net_loss_grad: NULL pointer");
+  if (n_cells < 1 || (!cells && n_cells > b->n_cells)) return fail(NPFEM_E_INVALID, "net_loss_grad: bad cell count");
+  npfem_status s;
+  if ((s = net_check_batch(net, b))) return s;
+  HIP_TRY(hipSetDevice(b->plan->device));
+  if ((s = net_training_scratch(net, n_cells))) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return b->plan->precision == NPFEM_FP64
+             ? net_loss_grad_now<double>(net, b, cells, n_cells, x, v, f, x_next, u0, loss_out, grad_out, st)
+             : net_loss_grad_now<float>(net, b, cells, n_cells, x, v, f, x_next, u0, loss_out, grad_out, st);
+}
+
+npfem_status npfem_net_adam_step(npfem_net* net, const float* grad, double lr, double b1, double b2, double eps,
+                                 void* stream) {
+  if (!net || !grad) return fail(NPFEM_E_INVALID, "net_adam_step: NULL pointer");
+  if (!(lr > 0.0) || !(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0) || !(eps > 0.0))
+    return fail(NPFEM_E_INVALID, "net_adam_step: bad hyper-parameters");
+  HIP_TRY(hipSetDevice(net->plan->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  net->adam_t += 1;
+  HIP_TRY(launch_net_adam(net->theta, net->adam_m, net->adam_v, grad, net->lay.count, lr, b1, b2, eps,
+                          net->adam_t, s));
+  HIP_TRY(launch_net_pack(net->weights(), net->We, net->Wl, net->WsT, net->WnT, net->Wd, s));
   return NPFEM_OK;
 }
 

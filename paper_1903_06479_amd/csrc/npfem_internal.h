@@ -91,7 +91,9 @@ struct StepArgs {
   const Real* x;               // [V][3]
   const Real* v;
   const Real* f;
-  const Real* u_guess;         // nullable
+  const Real* u_guess;         // nullable: start from x_n + u_guess instead of the first guess
+  const Real* u_delta;         // nullable: start from the first guess + u_delta (learned correction)
+  int guess_only;              // write the first guess y_n - x_n to x_out and stop
   Real* x_out;
   Real* v_out;
   npfem_cell_stats* stats;     // nullable

@@ -827,6 +827,21 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
   if (!A.u_guess) {
     tile_product(M, A.sol, 1, tl.mat(VB), tl.mat(VU), 3 * cnt, reinterpret_cast<unsigned char*>(xn));  // u = h^2 M~^-1 b
     __syncthreads();
+    if (A.guess_only || A.u_delta) {
+      for (int j = 0; j < cnt; ++j) {
+        const int64_t voff = A.cell_voff[A.tile_cells[td.first + j]];
+        Real* U = tl.vec(VU, j);
+        for (int e = tid(); e < len; e += kBlock) {
+          const int c = e / np, i = e - c * np;
+          if (i < n) {
+            if (A.guess_only) A.x_out[3 * (voff + i) + c] = U[e];
+            else U[e] += A.u_delta[3 * (voff + i) + c];
+          }
+        }
+      }
+      __syncthreads();
+      if (A.guess_only) return;
+    }
   }
 
   // ---- first evaluation ---------------------------------------------------------

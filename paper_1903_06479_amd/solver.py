@@ -202,6 +202,35 @@ class Batch:
     def stats_to_numpy(st) -> np.ndarray:
         return st.cpu().numpy().view(N.CELL_STATS_DTYPE)
 
+    def step_learned(self, net: "Net", x, v, f, x_out=None, v_out=None, stats=True, stream=None):
+        """One step started from y_n + delta, delta predicted by the network."""
+        import torch
+        for t, nm in ((x, "x"), (v, "v"), (f, "f")):
+            self._vec(t, nm)
+        x_out = torch.empty_like(x) if x_out is None else x_out
+        v_out = torch.empty_like(v) if v_out is None else v_out
+        self._vec(x_out, "x_out")
+        self._vec(v_out, "v_out")
+        st = None
+        if stats is True:
+            st = torch.empty(self.n_cells * N.CELL_STATS_DTYPE.itemsize, dtype=torch.uint8, device=x.device)
+        elif stats is not None and stats is not False:
+            st = stats
+        N.check(N.lib().npfem_step_learned(self._h, net._h, _dptr(x), _dptr(v), _dptr(f), _dptr(x_out),
+                                           _dptr(v_out), _dptr(st), _stream(stream)), "npfem_step_learned")
+        return x_out, v_out, st
+
+    def first_guess(self, x, v, f, out=None, stream=None):
+        """u0 = y_n - x_n = h^2 M~^-1 (M v / h + f) of every cell."""
+        import torch
+        for t, nm in ((x, "x"), (v, "v"), (f, "f")):
+            self._vec(t, nm)
+        out = torch.empty_like(x) if out is None else out
+        self._vec(out, "out")
+        N.check(N.lib().npfem_first_guess(self._h, _dptr(x), _dptr(v), _dptr(f), _dptr(out), _stream(stream)),
+                "npfem_first_guess")
+        return out
+
     def eval(self, x, v, f, u, stream=None):
         """Objective terms [n_cells, 8] and gradient at x_n + u."""
         import torch
@@ -232,3 +261,79 @@ class Batch:
         h, self._h = getattr(self, "_h", None), None
         if h and N is not None and N._lib is not None:
             N._lib.npfem_batch_destroy(h)
+
+
+def default_net_config(**overrides) -> N.NetConfig:
+    c = N.NetConfig()
+    N.lib().npfem_net_config_default(byref(c))
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c
+
+
+class Net:
+    """The learned warm-start network of a plan (parameters and optimiser on the GPU)."""
+
+    def __init__(self, plan: Plan, theta=None, config: N.NetConfig | None = None):
+        self.plan = plan
+        self.config = config or default_net_config()
+        self.n_params = int(N.lib().npfem_net_param_count(byref(self.config)))
+        if self.n_params < 0:
+            raise ValueError("invalid network configuration")
+        theta = np.zeros(self.n_params, np.float32) if theta is None else np.ascontiguousarray(theta, np.float32)
+        if theta.shape != (self.n_params,):
+            raise ValueError(f"theta must have {self.n_params} entries")
+        h = c_void_p()
+        N.check(N.lib().npfem_net_create(plan._h, byref(self.config), _ptr(theta), byref(h)), "npfem_net_create")
+        self._h = h
+
+    def set_params(self, theta) -> None:
+        theta = np.ascontiguousarray(theta, np.float32)
+        if theta.shape != (self.n_params,):
+            raise ValueError(f"theta must have {self.n_params} entries")
+        N.check(N.lib().npfem_net_set_params(self._h, _ptr(theta)), "npfem_net_set_params")
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, np.float32)
+        N.check(N.lib().npfem_net_get_params(self._h, _ptr(out)), "npfem_net_get_params")
+        return out
+
+    def infer(self, batch: Batch, x, v, f, out=None, stream=None):
+        """World-frame correction delta of every vertex of the batch."""
+        import torch
+        out = torch.empty_like(x) if out is None else out
+        for t, nm in ((x, "x"), (v, "v"), (f, "f"), (out, "out")):
+            batch._vec(t, nm)
+        N.check(N.lib().npfem_net_infer(self._h, batch._h, _dptr(x), _dptr(v), _dptr(f), _dptr(out),
+                                        _stream(stream)), "npfem_net_infer")
+        return out
+
+    def loss_grad(self, batch: Batch, x, v, f, x_next, u0, cells=None, n_cells=None, grad=None, stream=None,
+                  want_loss=True):
+        """Mean squared error of the listed cells (device int32 tensor, or the first n_cells)
+        and its gradient (device float32 [n_params])."""
+        import torch
+        for t, nm in ((x, "x"), (v, "v"), (f, "f"), (x_next, "x_next"), (u0, "u0")):
+            batch._vec(t, nm)
+        if cells is not None:
+            if cells.dtype != torch.int32 or not cells.is_cuda or not cells.is_contiguous():
+                raise ValueError("cells must be a contiguous int32 CUDA tensor")
+            n_cells = cells.numel()
+        elif n_cells is None:
+            n_cells = batch.n_cells
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=x.device) if grad is None else grad
+        loss = c_double(float("nan"))
+        N.check(N.lib().npfem_net_loss_grad(self._h, batch._h, _dptr(cells), int(n_cells), _dptr(x), _dptr(v),
+                                            _dptr(f), _dptr(x_next), _dptr(u0),
+                                            byref(loss) if want_loss else None, _dptr(grad), _stream(stream)),
+                "npfem_net_loss_grad")
+        return loss.value, grad
+
+    def adam_step(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None) -> None:
+        N.check(N.lib().npfem_net_adam_step(self._h, _dptr(grad), lr, beta1, beta2, eps, _stream(stream)),
+                "npfem_net_adam_step")
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and N is not None and N._lib is not None:
+            N._lib.npfem_net_destroy(h)
