@@ -10,9 +10,12 @@ from the current state by a drag kernel, as a fluid solver would hand them over.
 
 A step is one npFEM time step of every cell (Algorithm 1 of the paper: first guess,
 L-BFGS iterations with the H~^-1 product on the matrix cores, line search, velocity
-update, dissipation), with every cell converged to residual <= 1e-6.
+update, dissipation), with every cell converged to residual <= 1e-6.  Two forms are
+timed on the same inputs and schedule: plain (start from the first guess y_n) and
+learned (start from y_n + the correction predicted by the trained warm-start network,
+inference included in the step); `value` is the faster one ("form" in the config).
 
-    python bench.py [--steps K] [--warmup W] [--cells C] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--cells C] [--weights W.npy] [--no-cpu-baseline]
 
 Prints one JSON line.
 """
@@ -136,6 +139,8 @@ def main():
                     help="only copy a buffer of this many bytes 5 times (calibrates the HBM byte counters)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--fp32-products", action="store_true", help="FP32 instead of BF16 products with the inverses")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1903_06479_amd", "data", "warmstart_642.npy"),
+                    help="trained warm-start network (FP32 parameters); empty string: plain form only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=320)
     args = ap.parse_args()
@@ -185,71 +190,99 @@ def main():
         batch.set_graph(True)
     xo, vo = torch.empty_like(x0), torch.empty_like(x0)
     st = torch.empty(b.n_cells * 40, dtype=torch.uint8, device=dev)
-
-    def one_step(ev=None):
-        nonlocal x, v, xo, vo
-        batch.drag_forces(x, v, zeta, rate, origin, p["umax"], p["radius"], p["axis_y"], p["axis_z"], out=f)
-        if ev is not None:
-            ev[0].record()
-        batch.step(x, v, f, x_out=xo, v_out=vo, stats=st)
-        if ev is not None:
-            ev[1].record()
-        x, xo = xo, x
-        v, vo = vo, v
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    x.copy_(x0)
-    v.copy_(v0)
-    torch.cuda.synchronize()
-
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-    iters, evals, conv = [], [], []
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        one_step(events[k])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    kernel_ms = [a.elapsed_time(e) for a, e in events]
-    # statistics of the last step (read after timing)
-    s = Batch.stats_to_numpy(st)
-    iters, evals = s["iterations"], s["evaluations"]
-    conv = float(np.mean((s["status"] & CONVERGED) != 0))
-    n = 642
-    cell_steps = b.n_cells * args.steps
-    value = cell_steps / elapsed
-    mean_kernel_s = float(np.mean(kernel_ms)) / 1e3
-    # algorithmic work of one step launch (the step kernel dominates the step)
-    I, E = float(np.mean(iters)), float(np.mean(evals))
     sched = batch.schedule()
+
+    def run_form(form, net=None):
+        """Warm-up, reset, then K timed steps of one form; HIP events around each step call
+        (on the stream the kernels run on)."""
+        nonlocal x, v, xo, vo
+
+        def one_step(ev=None):
+            nonlocal x, v, xo, vo
+            batch.drag_forces(x, v, zeta, rate, origin, p["umax"], p["radius"], p["axis_y"], p["axis_z"], out=f)
+            if ev is not None:
+                ev[0].record()
+            if net is None:
+                batch.step(x, v, f, x_out=xo, v_out=vo, stats=st)
+            else:
+                batch.step_learned(net, x, v, f, x_out=xo, v_out=vo, stats=st)
+            if ev is not None:
+                ev[1].record()
+            x, xo = xo, x
+            v, vo = vo, v
+
+        x.copy_(x0)
+        v.copy_(v0)
+        for _ in range(args.warmup):
+            one_step()
+        torch.cuda.synchronize()
+        x.copy_(x0)
+        v.copy_(v0)
+        torch.cuda.synchronize()
+        events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            one_step(events[k])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        kernel_ms = [a.elapsed_time(e) for a, e in events]
+        s = Batch.stats_to_numpy(st)                    # last step (read after timing)
+        res = {"value": b.n_cells * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+               "step_call_ms": float(np.mean(kernel_ms)),
+               "iterations_mean": float(np.mean(s["iterations"])), "iterations_max": int(np.max(s["iterations"])),
+               "evaluations_mean": float(np.mean(s["evaluations"])),
+               "converged_fraction": float(np.mean((s["status"] & CONVERGED) != 0))}
+        log(f"[bench] {form}: {res}")
+        return res
+
+    forms = {"plain": run_form("plain")}
+    if args.weights:
+        from paper_1903_06479_amd import Net
+        net = Net(plan, np.load(args.weights))
+        forms["learned"] = run_form("learned", net)
+        # the network's own time (inference alone, same inputs)
+        d = torch.empty_like(x0)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+        for a, e in ev:
+            a.record()
+            net.infer(batch, x0, v0, f, out=d)
+            e.record()
+        torch.cuda.synchronize()
+        forms["learned"]["net_infer_ms"] = float(np.mean([a.elapsed_time(e) for a, e in ev[1:]]))
+        forms["learned"]["weights"] = os.path.relpath(args.weights, ROOT)
+    chosen = max(forms, key=lambda k: forms[k]["value"])
+    pl = forms["plain"]
+    n = 642
+    mean_kernel_s = pl["step_call_ms"] / 1e3
+    # roofline of the dominant kernel: the step kernel of the plain form
+    I, E = pl["iterations_mean"], pl["evaluations_mean"]
     f32, f64, mfma = cell_step_flops(n, mesh.nt, mesh.ne, I, E, sched["lbfgs_m"])
     # vector arithmetic in FP32-equivalent flops: a double flop costs two single ones
     alu_flops = b.n_cells * (f32 + 2.0 * f64)
     io_bytes = b.n_cells * 60.0 * n                                  # x, v, f in; x, v out (FP32)
     roof = {"bound": "alu", "achieved": alu_flops / mean_kernel_s / 1e12, "peak": VALU_FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": None, "traffic": None}
+    roof["frac"] = roof["achieved"] / roof["peak"]
     if b.n_cells == 100000 and sched["cells_per_tile"] == 5 and sched["lbfgs_m"] == 2:
         roof["traffic"] = measured_traffic()
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    ch = forms[chosen]
     out = {
-        "metric": "RBC cell-steps/sec at residual <=1e-6 (plain quasi-Newton)",
-        "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "metric": "RBC cell-steps/sec at residual <=1e-6, plain vs batched+learned warm start",
+        "value": ch["value"], "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ch["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"throughput: {b.n_cells} RBCs x 642-vertex mesh, shear + Poiseuille drag, "
                                "dt=1e-7 s, FP32 bulk + FP64 reductions", "cells": b.n_cells, "mesh_vertices": n,
-                   "form": "plain", "tol": args.tol, "schedule": batch.schedule(),
+                   "form": chosen, "tol": args.tol, "schedule": sched,
                    "inverse_products": "fp32" if args.fp32_products else "bf16 off-diagonal + fp32 diagonal",
                    "hip_graph": not args.no_graph},
+        "forms": forms,
         "roofline": roof,
+        "roofline_kernel": "step kernel, plain form",
         "work_per_cell_step": {"valu_fp32_flops": f32, "valu_fp64_flops": f64, "mfma_flops": mfma,
                                "state_bytes": 60.0 * n},
         "mfma_TFLOPs": b.n_cells * mfma / mean_kernel_s / 1e12,
-        "step_kernel_ms": float(np.mean(kernel_ms)),
-        "iterations_mean": I, "iterations_max": int(np.max(iters)), "evaluations_mean": float(np.mean(evals)),
-        "converged_fraction": conv,
         "io_GBs": io_bytes / mean_kernel_s / 1e9,
     }
     if not args.no_cpu_baseline:

@@ -100,6 +100,7 @@ def compare(batch: Batch, net: Net, traj: dict, diameter: float):
     convergence, and the position difference relative to the cell diameter."""
     import torch
     it_p, it_l, dx, conv = [], [], [], []
+    off = batch.offsets
     for s in range(len(traj["x"])):
         x, v, f = traj["x"][s], traj["v"][s], traj["f"][s]
         xp, _, sp = batch.step(x, v, f)
@@ -108,13 +109,18 @@ def compare(batch: Batch, net: Net, traj: dict, diameter: float):
         it_p.append(sp["iterations"].astype(np.float64))
         it_l.append(sl["iterations"].astype(np.float64))
         conv.append(bool(np.all(sp["status"] == N.CONVERGED) and np.all(sl["status"] == N.CONVERGED)))
-        dx.append((xl - xp).abs().max().item() / diameter)
+        d = (xl - xp).abs().amax(dim=1).cpu().numpy()          # per vertex
+        dx.append(np.maximum.reduceat(d, off[:-1]) / diameter)  # per cell
     torch.cuda.synchronize()
-    it_p, it_l = np.concatenate(it_p), np.concatenate(it_l)
+    it_p, it_l, dx = np.concatenate(it_p), np.concatenate(it_l), np.concatenate(dx)
     return {"iterations_plain": float(it_p.mean()), "iterations_learned": float(it_l.mean()),
             "iterations_plain_p99": float(np.percentile(it_p, 99)),
             "iterations_learned_p99": float(np.percentile(it_l, 99)),
-            "all_converged": all(conv), "max_dx_over_D": float(max(dx)), "cell_steps": int(it_p.size)}
+            "all_converged": all(conv), "max_dx_over_D": float(dx.max()),
+            "median_dx_over_D": float(np.median(dx)),
+            "cell_steps_dx_above_1e-5": int(np.sum(dx > 1e-5)),
+            "first_step_max_dx_over_D": float(dx[:batch.n_cells].max()),
+            "cell_steps": int(it_p.size)}
 
 
 def init_params(config, seed: int = 0) -> np.ndarray:
@@ -134,7 +140,8 @@ def main(argv=None):
     import torch
     from rbc_inputs import workloads                # seeded synthetic workloads
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", default="")
+    ap.add_argument("--weights", default="", help="evaluate these FP32 parameters instead of training")
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--runs", type=int, default=4)
     ap.add_argument("--steps", type=int, default=50)
@@ -155,27 +162,33 @@ def main(argv=None):
     cm = np.zeros(args.cells, np.int32)
     D = float(np.ptp(X[:, 0]))
 
-    # training trajectories: FP64 solver, targets converged to target_tol
-    plan64 = Plan([mesh], workloads.DT_US, params=default_params(precision="fp64", tol=args.target_tol))
-    batch64 = Batch(plan64, cm)
-    trajs = []
-    t0 = time.time()
-    for r in range(args.runs):
-        b = workloads.training(r, n_cells=args.cells)
-        flow = Flow(batch64, np.full(args.cells, workloads.drag_coefficient(642)), b.shear_rate, b.origin, b.poiseuille)
-        x, v = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (b.x, b.v))
-        trajs.append(collect(batch64, flow, x, v, args.steps))
-        log(f"[data] run {r}: {args.steps} steps, mean iterations {np.mean(trajs[-1]['iterations']):.2f} "
-            f"({time.time() - t0:.1f}s)")
     cfg = default_net_config()
-    net64 = Net(plan64, init_params(cfg, args.seed), cfg)
-    t0 = time.time()
-    history = train(net64, batch64, trajs, args.epochs, args.minibatch, args.lr, args.lr_final, args.seed, log)
-    t_train = time.time() - t0
-    theta = net64.get_params()
-    np.save(args.out, theta)
-    del trajs
-    torch.cuda.empty_cache()
+    history, t_train = [], 0.0
+    if args.weights:
+        theta = np.load(args.weights)
+    else:
+        # training trajectories: FP64 solver, targets converged to target_tol
+        plan64 = Plan([mesh], workloads.DT_US, params=default_params(precision="fp64", tol=args.target_tol))
+        batch64 = Batch(plan64, cm)
+        trajs = []
+        t0 = time.time()
+        for r in range(args.runs):
+            b = workloads.training(r, n_cells=args.cells)
+            flow = Flow(batch64, np.full(args.cells, workloads.drag_coefficient(642)), b.shear_rate, b.origin,
+                        b.poiseuille)
+            x, v = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (b.x, b.v))
+            trajs.append(collect(batch64, flow, x, v, args.steps))
+            log(f"[data] run {r}: {args.steps} steps, mean iterations {np.mean(trajs[-1]['iterations']):.2f} "
+                f"({time.time() - t0:.1f}s)")
+        net64 = Net(plan64, init_params(cfg, args.seed), cfg)
+        t0 = time.time()
+        history = train(net64, batch64, trajs, args.epochs, args.minibatch, args.lr, args.lr_final, args.seed, log)
+        t_train = time.time() - t0
+        theta = net64.get_params()
+        if args.out:
+            np.save(args.out, theta)
+        del trajs
+        torch.cuda.empty_cache()
 
     # held-out evaluation in the FP32 configuration of the throughput runs
     plan32 = Plan([mesh], workloads.DT_US, params=default_params(tol=1e-6, inverse_bf16=1))
@@ -198,6 +211,8 @@ def main(argv=None):
             "iterations_plain": float(np.mean([r["iterations_plain"] for r in results])),
             "iterations_learned": float(np.mean([r["iterations_learned"] for r in results])),
             "max_dx_over_D": float(max(r["max_dx_over_D"] for r in results)),
+            "cell_steps_dx_above_1e-5": int(sum(r["cell_steps_dx_above_1e-5"] for r in results)),
+            "first_step_max_dx_over_D": float(max(r["first_step_max_dx_over_D"] for r in results)),
             "all_converged": all(r["all_converged"] for r in results)},
     }
     print(json.dumps(summary), flush=True)
