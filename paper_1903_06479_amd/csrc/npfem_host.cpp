@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -1053,7 +1054,8 @@ struct npfem_net {
   float* adam_v = nullptr;
   uint16_t *We = nullptr, *Wl = nullptr, *WsT = nullptr, *WnT = nullptr, *Wd = nullptr;
   const NetMeshDev* d_meshes = nullptr;
-  int n_pad_max = 0;
+  int n_pad_max = 0, nb_deg_max = 0;
+  size_t fwd_lds = 0;                       // LDS of the resident forward variant (0: not used)
   int adam_t = 0;
   // inference scratch: per workgroup, features and two activation planes
   DeviceBuffers ibuf;
@@ -1166,7 +1168,14 @@ NetFwdArgs<Real> net_fwd_args(const npfem_net* net, const npfem_batch* b, const 
   a.v = static_cast<const Real*>(v);
   a.f = static_cast<const Real*>(f);
   a.S.n_pad_max = net->n_pad_max;
+  a.nb_deg_max = net->nb_deg_max;
   return a;
+}
+
+// persistent workgroups of the forward launch: the LDS-resident variant runs one per CU
+int net_fwd_grid(const npfem_net* net, int n_cells) {
+  const int g = net->fwd_lds ? net->plan->cu_count : 4 * net->plan->cu_count;
+  return std::max(1, std::min(g, n_cells));
 }
 
 template <typename Real>
@@ -1178,7 +1187,7 @@ npfem_status net_infer_now(npfem_net* net, npfem_batch* b, const void* x, const 
   a.S.train = 0;
   a.n_cells = (int)b->n_cells;
   a.delta = static_cast<Real*>(delta);
-  HIP_TRY(launch_net_forward<Real>(a, std::max(1, std::min(net->igrid, (int)b->n_cells)), s));
+  HIP_TRY(launch_net_forward<Real>(a, std::min(net->igrid, net_fwd_grid(net, (int)b->n_cells)), net->fwd_lds, s));
   return NPFEM_OK;
 }
 
@@ -1201,7 +1210,7 @@ npfem_status net_loss_grad_now(npfem_net* net, npfem_batch* b, const int32_t* ce
   a.S.train = 1;
   a.cells = cells;
   a.n_cells = n_cells;
-  HIP_TRY(launch_net_forward<Real>(a, std::max(1, std::min(4 * net->plan->cu_count, n_cells)), s));
+  HIP_TRY(launch_net_forward<Real>(a, net_fwd_grid(net, n_cells), net->fwd_lds, s));
   // nodes of the listed cells (for the mean)
   int64_t nodes = 0;
   if (cells) {
@@ -1337,10 +1346,14 @@ npfem_status npfem_net_create(npfem_plan* p, const npfem_net_config* cfg, const 
     d.mass_mean = ms / m->n;
     d.nb_ptr = p->precision == NPFEM_FP64 ? mp.dev64.nb_ptr : mp.dev32.nb_ptr;
     d.nb_idx = p->precision == NPFEM_FP64 ? mp.dev64.nb_idx : mp.dev32.nb_idx;
+    d.nb_ell = p->precision == NPFEM_FP64 ? mp.dev64.nb_ell : mp.dev32.nb_ell;
+    d.nb_deg = p->precision == NPFEM_FP64 ? mp.dev64.nb_deg : mp.dev32.nb_deg;
+    net->nb_deg_max = std::max(net->nb_deg_max, d.nb_deg);
     if ((s = net->buf.upload(Xc.data(), Xc.size(), &d.Xc))) return s;
     if ((s = net->buf.upload(mp.mass.data(), mp.mass.size(), &d.mass))) return s;
   }
   if ((s = net->buf.upload(md.data(), md.size(), &net->d_meshes))) return s;
+  net->fwd_lds = std::getenv("NPFEM_NET_NO_LDS") ? 0 : net_forward_lds_bytes(net->n_pad_max, net->nb_deg_max);
   if ((s = net_upload_params(net.get(), theta, nullptr))) return s;
   *out = net.release();
   return NPFEM_OK;

@@ -28,6 +28,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kRS = 16;     // reduction stride (values per wave)
 constexpr int kTP = 40;     // LDS row pitch (BF16) of the transposed 32-node chunks
+constexpr int kNetUnrollDeg = 6;   // neighbour gathers issued together (the icosphere degree)
 
 __device__ inline int tid() { return threadIdx.x; }
 
@@ -39,7 +40,7 @@ __device__ inline bf16x8 zero8() {
   return bf16x8{z, z, z, z, z, z, z, z};
 }
 
-template <int N>
+template <int N, int NW = 4>
 __device__ inline void wg_sum(double (&v)[N], double* red) {
   static_assert(N <= kRS, "wg_sum: too many values");
 #pragma unroll
@@ -57,7 +58,12 @@ __device__ inline void wg_sum(double (&v)[N], double* red) {
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = (red[i] + red[kRS + i]) + (red[2 * kRS + i] + red[3 * kRS + i]);
+  for (int i = 0; i < N; ++i) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += red[w * kRS + i];
+    v[i] = t;
+  }
 }
 
 // Orthogonal polar factor of a 3x3 matrix with positive determinant (scaled Newton
@@ -86,17 +92,19 @@ __device__ void polar3(const double* C, double* R) {
     cof[7] = X[2] * X[3] - X[0] * X[5];
     cof[8] = X[0] * X[4] - X[1] * X[3];
     const double d = X[0] * cof[0] + X[1] * cof[1] + X[2] * cof[2];
-    double nx = 0.0, ni = 0.0;
+    const double id = 1.0 / d;
+    double nx = 0.0, nc = 0.0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       nx += X[k] * X[k];
-      ni += (cof[k] / d) * (cof[k] / d);
+      nc += cof[k] * cof[k];
     }
-    const double g = sqrt(sqrt(ni / nx));
+    const double g = sqrt(sqrt(nc * id * id / nx));          // (|X^-1|_F / |X|_F)^(1/2)
+    const double cg = 0.5 * id / g, xg = 0.5 * g;
     double diff = 0.0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const double xn = 0.5 * (g * X[k] + cof[k] / (d * g));
+      const double xn = xg * X[k] + cg * cof[k];
       diff += (xn - X[k]) * (xn - X[k]);
       X[k] = xn;
     }
@@ -109,247 +117,368 @@ __device__ void polar3(const double* C, double* R) {
 // ---------------------------------------------------------------------------------
 // Forward: frame, features, encoder, message-passing layers, decoder.
 // ---------------------------------------------------------------------------------
-template <typename Real>
-__global__ void __launch_bounds__(kBlock) net_forward_kernel(NetFwdArgs<Real> A) {
-  __shared__ double red[4 * kRS];
-  __shared__ double fr[10];
-  __shared__ float wd[3 * kNetH + 3];
-  const NetLayout L = A.W.lay;
-  for (int e = tid(); e < 3 * kNetH; e += kBlock) wd[e] = bf2f(A.W.Wd[e]);
-  if (tid() < 3) wd[3 * kNetH + tid()] = A.W.theta[L.off_bd + tid()];
-  const int lane = tid() & 63, wave = tid() >> 6, l16 = lane & 15, kq = lane >> 4;
-  const bool train = A.S.train != 0;
-  const size_t plane = (size_t)A.S.n_pad_max * kNetH;
-  const int nh = train ? L.layers + 1 : 2;
 
-  for (int k = blockIdx.x; k < A.n_cells; k += gridDim.x) {
-    const int cell = A.cells ? A.cells[k] : k;
-    const NetMeshDev& M = A.meshes[A.cell_mesh[cell]];
-    const int n = M.n, np = M.n_pad;
-    const int64_t voff = A.cell_voff[cell];
-    const Real* x = A.x + 3 * voff;
-    const Real* v = A.v + 3 * voff;
-    const Real* f = A.f + 3 * voff;
-    const size_t slot = train ? (size_t)k : (size_t)blockIdx.x;
-    uint16_t* feat = A.S.feat + slot * A.S.n_pad_max * kNetFeatPad;
-    uint16_t* Hs = A.S.H + slot * nh * plane;
-    uint16_t* Zs = train ? A.S.Z + slot * (L.layers + 1) * plane : nullptr;
-
-    // ---- frame: mass-weighted centroids, covariance with the rest shape, Kabsch ----
-    double s1[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = tid(); i < n; i += kBlock) {
-      const double m = M.mass[i];
+// Frame (mass-weighted centroids, covariance with the rest shape, Kabsch) and the node
+// features of cell k, written as BF16 rows of 32 (zero padded) to feat.  Leaves R and
+// s in fr[0..9] (LDS) and ends with a barrier.
+template <typename Real, int NT>
+__device__ void cell_features(const NetFwdArgs<Real>& A, const NetMeshDev& M, int k, const Real* x, const Real* v,
+                              const Real* f, uint16_t* feat, uint16_t* feat2, double* red, double* fr) {
+  const int n = M.n, np = M.n_pad;
+  double s1[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = tid(); i < n; i += NT) {
+    const double m = M.mass[i];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        s1[c] += m * (double)x[3 * i + c];
-        s1[3 + c] += m * (double)v[3 * i + c];
-        s1[6 + c] += (double)f[3 * i + c];
-      }
+    for (int c = 0; c < 3; ++c) {
+      s1[c] += m * (double)x[3 * i + c];
+      s1[3 + c] += m * (double)v[3 * i + c];
+      s1[6 + c] += (double)f[3 * i + c];
     }
-    wg_sum<9>(s1, red);
-    const double ims = 1.0 / M.mass_sum;
-    const double xc[3] = {s1[0] * ims, s1[1] * ims, s1[2] * ims};
-    const double vc[3] = {s1[3] * ims, s1[4] * ims, s1[5] * ims};
-    const double ac[3] = {s1[6] * ims, s1[7] * ims, s1[8] * ims};
-    double s2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = tid(); i < n; i += kBlock) {
+  }
+  wg_sum<9, NT / 64>(s1, red);
+  const double ims = 1.0 / M.mass_sum;
+  const double xc[3] = {s1[0] * ims, s1[1] * ims, s1[2] * ims};
+  const double vc[3] = {s1[3] * ims, s1[4] * ims, s1[5] * ims};
+  const double ac[3] = {s1[6] * ims, s1[7] * ims, s1[8] * ims};
+  double s2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = tid(); i < n; i += NT) {
+    const double m = M.mass[i];
+    double d[3], fd[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      d[c] = (double)x[3 * i + c] - xc[c];
+      fd[c] = (double)f[3 * i + c] - m * ac[c];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) s2[3 * a + b] += m * d[a] * M.Xc[3 * i + b];
+    s2[9] += fd[0] * fd[0] + fd[1] * fd[1] + fd[2] * fd[2];
+  }
+  wg_sum<10, NT / 64>(s2, red);
+  if (tid() == 0) {
+    double R[9];
+    polar3(s2, R);
+    const double s = A.h * A.h * (sqrt(s2[9] / n) + A.W.force_floor) / M.mass_mean;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fr[q] = R[q];
+    fr[9] = s;
+    if (A.S.frame) {
+#pragma unroll
+      for (int q = 0; q < 10; ++q) A.S.frame[(size_t)k * 12 + q] = fr[q];
+    }
+  }
+  __syncthreads();
+  double R[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) R[q] = fr[q];
+  const double s = fr[9];
+  const double hs = A.h / s, h2s = A.h * A.h / s, iq = 1.0 / A.W.shape_scale;
+  for (int i = tid(); i < np; i += NT) {
+    float fv[kNetFeat];
+#pragma unroll
+    for (int q = 0; q < kNetFeat; ++q) fv[q] = 0.f;
+    if (i < n) {
       const double m = M.mass[i];
-      double d[3], fd[3];
+      double d[3], dv[3], df[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         d[c] = (double)x[3 * i + c] - xc[c];
-        fd[c] = (double)f[3 * i + c] - m * ac[c];
+        dv[c] = (double)v[3 * i + c] - vc[c];
+        df[c] = (double)f[3 * i + c] - m * ac[c];
       }
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 3; ++a) {
+        double rd = 0.0, rv = 0.0, rf = 0.0;                 // (R^T w)_a = sum_b R[b][a] w_b
 #pragma unroll
-        for (int b = 0; b < 3; ++b) s2[3 * a + b] += m * d[a] * M.Xc[3 * i + b];
-      s2[9] += fd[0] * fd[0] + fd[1] * fd[1] + fd[2] * fd[2];
-    }
-    wg_sum<10>(s2, red);
-    if (tid() == 0) {
-      double R[9];
-      polar3(s2, R);
-      const double s = A.h * A.h * (sqrt(s2[9] / n) + A.W.force_floor) / M.mass_mean;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) fr[q] = R[q];
-      fr[9] = s;
-      if (A.S.frame) {
-#pragma unroll
-        for (int q = 0; q < 10; ++q) A.S.frame[(size_t)k * 12 + q] = fr[q];
+        for (int b = 0; b < 3; ++b) {
+          rd += R[3 * b + a] * d[b];
+          rv += R[3 * b + a] * dv[b];
+          rf += R[3 * b + a] * df[b];
+        }
+        const double Xa = M.Xc[3 * i + a];
+        fv[a] = (float)((rd - Xa) * iq);
+        fv[3 + a] = (float)(rv * hs);
+        fv[6 + a] = (float)(rf * h2s / m);
+        fv[9 + a] = (float)(Xa * M.inv_rho);
       }
     }
-    __syncthreads();
-    double R[9];
+    bf16x8 w0, w1;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) R[q] = fr[q];
-    const double s = fr[9];
-
-    // ---- node features (BF16, padded to 32) ------------------------------------------
-    const double hs = A.h / s, h2s = A.h * A.h / s, iq = 1.0 / A.W.shape_scale;
-    for (int i = tid(); i < np; i += kBlock) {
-      float fv[kNetFeat];
+    for (int e = 0; e < 8; ++e) w0[e] = (__bf16)fv[e];
 #pragma unroll
-      for (int q = 0; q < kNetFeat; ++q) fv[q] = 0.f;
-      if (i < n) {
-        const double m = M.mass[i];
-        double d[3], dv[3], df[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          d[c] = (double)x[3 * i + c] - xc[c];
-          dv[c] = (double)v[3 * i + c] - vc[c];
-          df[c] = (double)f[3 * i + c] - m * ac[c];
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          double rd = 0.0, rv = 0.0, rf = 0.0;                 // (R^T w)_a = sum_b R[b][a] w_b
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            rd += R[3 * b + a] * d[b];
-            rv += R[3 * b + a] * dv[b];
-            rf += R[3 * b + a] * df[b];
-          }
-          const double Xa = M.Xc[3 * i + a];
-          fv[a] = (float)((rd - Xa) * iq);
-          fv[3 + a] = (float)(rv * hs);
-          fv[6 + a] = (float)(rf * h2s / m);
-          fv[9 + a] = (float)(Xa * M.inv_rho);
-        }
-      }
-      bf16x8 w0, w1;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) w0[e] = (__bf16)fv[e];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) w1[e] = (__bf16)(e < 4 ? fv[8 + e] : 0.f);
-      uint16_t* fp = feat + (size_t)i * kNetFeatPad;
+    for (int e = 0; e < 8; ++e) w1[e] = (__bf16)(e < 4 ? fv[8 + e] : 0.f);
+    for (uint16_t* base : {feat, feat2}) {
+      if (!base) continue;
+      uint16_t* fp = base + (size_t)i * kNetFeatPad;
       *reinterpret_cast<bf16x8*>(fp) = w0;
       *reinterpret_cast<bf16x8*>(fp + 8) = w1;
       *reinterpret_cast<bf16x8*>(fp + 16) = zero8();
       *reinterpret_cast<bf16x8*>(fp + 24) = zero8();
     }
-    __syncthreads();
+  }
+  __syncthreads();
+}
 
-    // ---- encoder: h0 = relu(W_e f + b_e) ---------------------------------------------
-    {
-      uint16_t* H0 = Hs;
-      uint16_t* Z0 = Zs;
-      bf16x8 bq[4];
-      float bias[4];
+// Encoder rows of the waves w = wave, wave + NWV, ...: h0 = relu(W_e f + b_e) into
+// H (row pitch hp); training also stores h0 and z0 (pitch kNetH) to Hg / Zg.
+template <int NWV>
+__device__ void encoder_rows(const NetWeights& W, const uint16_t* feat, int n, int np, uint16_t* H, int hp,
+                             uint16_t* Hg, uint16_t* Zg) {
+  const int lane = tid() & 63, wave = tid() >> 6, l16 = lane & 15, kq = lane >> 4;
+  bf16x8 bq[4];
+  float bias[4];
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-        bq[cb] = ld8(A.W.We + (size_t)(cb * 16 + l16) * kNetFeatPad + 8 * kq);
-        bias[cb] = A.W.theta[L.off_be + cb * 16 + l16];
-      }
-      for (int rb = wave; rb < (np >> 4); rb += 4) {
-        const bf16x8 aq = ld8(feat + (size_t)(rb * 16 + l16) * kNetFeatPad + 8 * kq);
+  for (int cb = 0; cb < 4; ++cb) {
+    bq[cb] = ld8(W.We + (size_t)(cb * 16 + l16) * kNetFeatPad + 8 * kq);
+    bias[cb] = W.theta[W.lay.off_be + cb * 16 + l16];
+  }
+  for (int rb = wave; rb < (np >> 4); rb += NWV) {
+    const bf16x8 aq = ld8(feat + (size_t)(rb * 16 + l16) * kNetFeatPad + 8 * kq);
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-          const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, bq[cb], floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    for (int cb = 0; cb < 4; ++cb) {
+      const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, bq[cb], floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int row = rb * 16 + 4 * kq + i, col = cb * 16 + l16;
-            const float z = row < n ? acc[i] + bias[cb] : 0.f;
-            H0[(size_t)row * kNetH + col] = f2bf(fmaxf(z, 0.f));
-            if (train) Z0[(size_t)row * kNetH + col] = f2bf(z);
-          }
+      for (int i = 0; i < 4; ++i) {
+        const int row = rb * 16 + 4 * kq + i, col = cb * 16 + l16;
+        const float z = row < n ? acc[i] + bias[cb] : 0.f;
+        const uint16_t hb = f2bf(fmaxf(z, 0.f));
+        H[(size_t)row * hp + col] = hb;
+        if (Hg) {
+          Hg[(size_t)row * kNetH + col] = hb;
+          Zg[(size_t)row * kNetH + col] = f2bf(z);
         }
       }
     }
-    __syncthreads();
+  }
+}
 
-    // ---- message-passing layers: h <- h + relu(W_s h + W_n mean_N(h) + b) -----------
+// Decoder on the matrix cores: o = W_d h + b_d (3 outputs padded to one 16-column
+// block); lanes l16 = 0, 1, 2 of each 16-lane group hold the components of a row and
+// exchange them to form the correction s R o (world frame) and/or store o.
+template <typename Real, int NWV>
+__device__ void decoder_rows(const NetFwdArgs<Real>& A, int k, int64_t voff, int n, int np, const uint16_t* H,
+                             int hp, const double* fr) {
+  const int lane = tid() & 63, wave = tid() >> 6, l16 = lane & 15, kq = lane >> 4;
+  double R[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) R[q] = fr[q];
+  const double s = fr[9];
+  bf16x8 bq[2];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2) bq[s2] = l16 < 3 ? ld8(A.W.Wd + (size_t)l16 * kNetH + 32 * s2 + 8 * kq) : zero8();
+  const float bias = l16 < 3 ? A.W.theta[A.W.lay.off_bd + l16] : 0.f;
+  for (int rb = wave; rb < (np >> 4); rb += NWV) {
+    const int row = rb * 16 + l16;
+    floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(H + (size_t)row * hp + 8 * kq), bq[0],
+                                                          floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ld8(H + (size_t)row * hp + 32 + 8 * kq), bq[1], acc, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float o = acc[i] + bias;                    // o[4kq + i][l16]
+      const float o0 = __shfl(o, kq * 16, 64), o1 = __shfl(o, kq * 16 + 1, 64), o2 = __shfl(o, kq * 16 + 2, 64);
+      const int r2 = rb * 16 + 4 * kq + i;
+      if (r2 < n && l16 < 3) {
+        if (A.delta) {
+          const double da = s * (R[3 * l16] * o0 + R[3 * l16 + 1] * o1 + R[3 * l16 + 2] * o2);
+          A.delta[3 * (voff + r2) + l16] = (Real)da;
+        }
+        if (A.S.out) A.S.out[((size_t)k * A.S.n_pad_max + r2) * 3 + l16] = o;
+      }
+    }
+  }
+}
+
+// One message-passing layer over the row blocks of this wave: reads h (row pitch hp)
+// and its neighbour means, writes h + relu(z) to Hout (pitch kNetH) and z to Zout.
+// Neighbour j of row i: nbr(q, i) for q < deg(i).
+template <int NWV, typename NbrF, typename DegF>
+__device__ void layer_rows(const NetWeights& W, int l, int n, int np, int width, const uint16_t* Hin, int hp,
+                           uint16_t* Hout, uint16_t* Zout, NbrF nbr, DegF deg) {
+  const int lane = tid() & 63, wave = tid() >> 6, l16 = lane & 15, kq = lane >> 4;
+  const uint16_t* Wl = W.Wl + (size_t)l * kNetH * 2 * kNetH;
+  bf16x8 bq[4][4];
+  float bias[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) bq[s4][cb] = ld8(Wl + (size_t)(cb * 16 + l16) * 2 * kNetH + 32 * s4 + 8 * kq);
+    bias[cb] = W.theta[W.lay.b(l) + cb * 16 + l16];
+  }
+  for (int rb = wave; rb < (np >> 4); rb += NWV) {
+    const int row = rb * 16 + l16;
+    bf16x8 aq[4];
+    if (row < n) {
+      aq[0] = ld8(Hin + (size_t)row * hp + 8 * kq);
+      aq[1] = ld8(Hin + (size_t)row * hp + 32 + 8 * kq);
+      float g0[8], g1[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) g0[e] = g1[e] = 0.f;
+      const int dg = deg(row);
+      // the first kNetUnrollDeg ELL columns are loaded unconditionally (ELL padding points
+      // at the row itself, so every address is valid) and masked by the degree; wider
+      // meshes continue in a rolled loop
+#pragma unroll
+      for (int q = 0; q < kNetUnrollDeg; ++q) {
+        const int j = q < width ? nbr(q, row) : row;
+        const float w = q < dg ? 1.f : 0.f;
+        const bf16x8 h0 = ld8(Hin + (size_t)j * hp + 8 * kq);
+        const bf16x8 h1 = ld8(Hin + (size_t)j * hp + 32 + 8 * kq);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          g0[e] += w * (float)h0[e];
+          g1[e] += w * (float)h1[e];
+        }
+      }
+      for (int q = kNetUnrollDeg; q < dg; ++q) {
+        const int j = nbr(q, row);
+        const bf16x8 h0 = ld8(Hin + (size_t)j * hp + 8 * kq);
+        const bf16x8 h1 = ld8(Hin + (size_t)j * hp + 32 + 8 * kq);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          g0[e] += (float)h0[e];
+          g1[e] += (float)h1[e];
+        }
+      }
+      const float inv = 1.0f / (float)dg;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        aq[2][e] = (__bf16)(g0[e] * inv);
+        aq[3][e] = (__bf16)(g1[e] * inv);
+      }
+    } else {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) aq[s4] = zero8();
+    }
+    floatx4 acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[s4], bq[s4][cb], acc[cb], 0, 0, 0);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r2 = rb * 16 + 4 * kq + i, col = cb * 16 + l16;
+        const float z = r2 < n ? acc[cb][i] + bias[cb] : 0.f;
+        const float hn = r2 < n ? bf2f(Hin[(size_t)r2 * hp + col]) + fmaxf(z, 0.f) : 0.f;
+        Hout[(size_t)r2 * kNetH + col] = f2bf(hn);
+        if (Zout) Zout[(size_t)r2 * kNetH + col] = f2bf(z);
+      }
+    }
+  }
+}
+
+// Variant for any mesh size: activations ping-pong in memory, neighbours from CSR.
+template <typename Real>
+__global__ void __launch_bounds__(kBlock) net_forward_kernel(NetFwdArgs<Real> A) {
+  __shared__ double red[4 * kRS];
+  __shared__ double fr[10];
+  const NetLayout L = A.W.lay;
+  const bool train = A.S.train != 0;
+  const size_t plane = (size_t)A.S.n_pad_max * kNetH;
+  const int nh = train ? L.layers + 1 : 2;
+  for (int k = blockIdx.x; k < A.n_cells; k += gridDim.x) {
+    const int cell = A.cells ? A.cells[k] : k;
+    const NetMeshDev& M = A.meshes[A.cell_mesh[cell]];
+    const int n = M.n, np = M.n_pad;
+    const int64_t voff = A.cell_voff[cell];
+    const size_t slot = train ? (size_t)k : (size_t)blockIdx.x;
+    uint16_t* feat = A.S.feat + slot * A.S.n_pad_max * kNetFeatPad;
+    uint16_t* Hs = A.S.H + slot * nh * plane;
+    uint16_t* Zs = train ? A.S.Z + slot * (L.layers + 1) * plane : nullptr;
+    cell_features<Real, kBlock>(A, M, k, A.x + 3 * voff, A.v + 3 * voff, A.f + 3 * voff, feat, nullptr, red, fr);
+    encoder_rows<kBlock / 64>(A.W, feat, n, np, Hs, kNetH, nullptr, nullptr);
+    if (train) {                              // z0 for the backward pass
+      __syncthreads();
+      encoder_rows<kBlock / 64>(A.W, feat, n, np, Hs, kNetH, Hs, Zs);
+    }
+    __syncthreads();
+    auto nbr = [&](int q, int i) { return M.nb_ell[q * np + i]; };
+    auto deg = [&](int i) { return M.nb_ptr[i + 1] - M.nb_ptr[i]; };
     for (int l = 0; l < L.layers; ++l) {
       const uint16_t* Hin = Hs + (size_t)(train ? l : (l & 1)) * plane;
       uint16_t* Hout = Hs + (size_t)(train ? l + 1 : ((l + 1) & 1)) * plane;
-      uint16_t* Zl = train ? Zs + (size_t)(l + 1) * plane : nullptr;
-      const uint16_t* Wl = A.W.Wl + (size_t)l * kNetH * 2 * kNetH;
-      bf16x8 bq[4][4];
-      float bias[4];
+      layer_rows<kBlock / 64>(A.W, l, n, np, M.nb_deg, Hin, kNetH, Hout, train ? Zs + (size_t)(l + 1) * plane : nullptr,
+                              nbr, deg);
+      __syncthreads();
+    }
+    const uint16_t* HL = Hs + (size_t)(train ? L.layers : (L.layers & 1)) * plane;
+    decoder_rows<Real, kBlock / 64>(A, k, voff, n, np, HL, kNetH, fr);
+    __syncthreads();
+  }
+}
+
+// LDS-resident variant (meshes whose activations fit a compute unit): 512 threads; the
+// cell's activations live in LDS (row pitch kHP, so 16-byte operand reads of 8
+// consecutive rows fall in distinct banks) together with the mesh's neighbour lists;
+// each layer's output goes to memory (L2) and is copied back after a barrier.
+constexpr int kNetLdsBlock = 512;
+constexpr int kHP = 72;
+constexpr int kNetLdsHeader = 8 * kRS * 8 + 16 * 8;   // reduction, frame
+
+template <typename Real>
+__global__ void __launch_bounds__(kNetLdsBlock) net_forward_lds_kernel(NetFwdArgs<Real> A) {
+  const int np_max = A.S.n_pad_max, deg_max = A.nb_deg_max;
+  extern __shared__ __align__(16) unsigned char lds[];
+  double* red = reinterpret_cast<double*>(lds);
+  double* fr = red + 8 * kRS;
+  uint16_t* Hl = reinterpret_cast<uint16_t*>(lds + kNetLdsHeader);
+  uint16_t* Fl = Hl + (size_t)np_max * kHP;                    // features [np_max][32]
+  uint16_t* nbl = Fl + (size_t)np_max * kNetFeatPad;
+  uint8_t* degl = reinterpret_cast<uint8_t*>(nbl + (size_t)deg_max * np_max);
+  constexpr int NT = kNetLdsBlock, NWV = kNetLdsBlock / 64;
+  const NetLayout L = A.W.lay;
+  const bool train = A.S.train != 0;
+  const size_t plane = (size_t)A.S.n_pad_max * kNetH;
+  const int nh = train ? L.layers + 1 : 2;
+  int staged = -1;
+  for (int k = blockIdx.x; k < A.n_cells; k += gridDim.x) {
+    const int cell = A.cells ? A.cells[k] : k;
+    const int mi = A.cell_mesh[cell];
+    const NetMeshDev& M = A.meshes[mi];
+    const int n = M.n, np = M.n_pad;
+    const int64_t voff = A.cell_voff[cell];
+    if (mi != staged) {                       // neighbour lists of this mesh type into LDS
+      __syncthreads();
+      for (int e = tid(); e < M.nb_deg * np; e += NT) nbl[e] = (uint16_t)M.nb_ell[e];
+      for (int i = tid(); i < np; i += NT) degl[i] = (uint8_t)(i < n ? M.nb_ptr[i + 1] - M.nb_ptr[i] : 0);
+      staged = mi;
+    }
+    const size_t slot = train ? (size_t)k : (size_t)blockIdx.x;
+    uint16_t* feat = A.S.feat + slot * A.S.n_pad_max * kNetFeatPad;
+    uint16_t* Hs = A.S.H + slot * nh * plane;
+    uint16_t* Zs = train ? A.S.Z + slot * (L.layers + 1) * plane : nullptr;
+    cell_features<Real, NT>(A, M, k, A.x + 3 * voff, A.v + 3 * voff, A.f + 3 * voff, Fl, train ? feat : nullptr,
+                            red, fr);
+    encoder_rows<NWV>(A.W, Fl, n, np, Hl, kHP, train ? Hs : nullptr, Zs);
+    __syncthreads();
+    auto nbr = [&](int q, int i) { return (int)nbl[q * np + i]; };
+    auto deg = [&](int i) { return (int)degl[i]; };
+    for (int l = 0; l < L.layers; ++l) {
+      uint16_t* Hout = Hs + (size_t)(train ? l + 1 : 0) * plane;
+      layer_rows<NWV>(A.W, l, n, np, M.nb_deg, Hl, kHP, Hout, train ? Zs + (size_t)(l + 1) * plane : nullptr, nbr,
+                      deg);
+      __syncthreads();
+      const int chunks = np * (kNetH / 8);
+      for (int c0 = tid(); c0 < chunks; c0 += 4 * NT) {
+        bf16x8 t[4];
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb) {
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) bq[s4][cb] = ld8(Wl + (size_t)(cb * 16 + l16) * 2 * kNetH + 32 * s4 + 8 * kq);
-        bias[cb] = A.W.theta[L.b(l) + cb * 16 + l16];
-      }
-      for (int rb = wave; rb < (np >> 4); rb += 4) {
-        const int row = rb * 16 + l16;
-        bf16x8 aq[4];
-        if (row < n) {
-          aq[0] = ld8(Hin + (size_t)row * kNetH + 8 * kq);
-          aq[1] = ld8(Hin + (size_t)row * kNetH + 32 + 8 * kq);
-          float g0[8], g1[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) g0[e] = g1[e] = 0.f;
-          const int p0 = M.nb_ptr[row], p1 = M.nb_ptr[row + 1];
-          for (int p = p0; p < p1; ++p) {
-            const int j = M.nb_idx[p];
-            const bf16x8 h0 = ld8(Hin + (size_t)j * kNetH + 8 * kq);
-            const bf16x8 h1 = ld8(Hin + (size_t)j * kNetH + 32 + 8 * kq);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              g0[e] += (float)h0[e];
-              g1[e] += (float)h1[e];
-            }
-          }
-          const float inv = 1.0f / (float)(p1 - p0);
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            aq[2][e] = (__bf16)(g0[e] * inv);
-            aq[3][e] = (__bf16)(g1[e] * inv);
-          }
-        } else {
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) aq[s4] = zero8();
+        for (int u = 0; u < 4; ++u) {                   // loads issued together (clamped, always valid)
+          const int c = min(c0 + u * NT, chunks - 1);
+          t[u] = ld8(Hout + (size_t)(c >> 3) * kNetH + 8 * (c & 7));
         }
-        floatx4 acc[4];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-          for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[s4], bq[s4][cb], acc[cb], 0, 0, 0);
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r2 = rb * 16 + 4 * kq + i, col = cb * 16 + l16;
-            const size_t o = (size_t)r2 * kNetH + col;
-            const float z = r2 < n ? acc[cb][i] + bias[cb] : 0.f;
-            const float hn = r2 < n ? bf2f(Hin[o]) + fmaxf(z, 0.f) : 0.f;
-            Hout[o] = f2bf(hn);
-            if (train) Zl[o] = f2bf(z);
-          }
+        for (int u = 0; u < 4; ++u) {
+          const int c = c0 + u * NT;
+          if (c < chunks) *reinterpret_cast<bf16x8*>(Hl + (size_t)(c >> 3) * kHP + 8 * (c & 7)) = t[u];
         }
       }
       __syncthreads();
     }
-
-    // ---- decoder: o = W_d h + b_d; correction s R o (world frame) ---------------------
-    const uint16_t* HL = Hs + (size_t)(train ? L.layers : (L.layers & 1)) * plane;
-    for (int i = tid(); i < n; i += kBlock) {
-      float o[3] = {wd[3 * kNetH], wd[3 * kNetH + 1], wd[3 * kNetH + 2]};
-#pragma unroll
-      for (int q = 0; q < kNetH / 8; ++q) {
-        const bf16x8 hv = ld8(HL + (size_t)i * kNetH + 8 * q);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float hf = (float)hv[e];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) o[c] += wd[c * kNetH + 8 * q + e] * hf;
-        }
-      }
-      if (A.delta) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const double da = s * (R[3 * a] * o[0] + R[3 * a + 1] * o[1] + R[3 * a + 2] * o[2]);
-          A.delta[3 * (voff + i) + a] = (Real)da;
-        }
-      }
-      if (A.S.out) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) A.S.out[((size_t)k * A.S.n_pad_max + i) * 3 + c] = o[c];
-      }
-    }
+    decoder_rows<Real, NWV>(A, k, voff, n, np, Hl, kHP, fr);
     __syncthreads();
   }
 }
@@ -619,10 +748,24 @@ inline int blocks_for(int64_t count, int threads) { return (int)((count + thread
 
 }  // namespace
 
+size_t net_forward_lds_bytes(int n_pad, int nb_deg) {
+  const size_t b = kNetLdsHeader + (size_t)n_pad * (kHP + kNetFeatPad) * 2 + (size_t)nb_deg * n_pad * 2 +
+                   (size_t)n_pad;
+  return (b + 15) / 16 * 16 <= 160 * 1024 && nb_deg <= 255 ? (b + 15) / 16 * 16 : 0;
+}
+
 template <typename Real>
-hipError_t launch_net_forward(const NetFwdArgs<Real>& a, int grid, hipStream_t s) {
+hipError_t launch_net_forward(const NetFwdArgs<Real>& a, int grid, size_t lds_bytes, hipStream_t s) {
   (void)hipGetLastError();
-  hipLaunchKernelGGL(net_forward_kernel<Real>, dim3(grid), dim3(kBlock), 0, s, a);
+  if (lds_bytes > 0) {
+    if (lds_bytes < net_forward_lds_bytes(a.S.n_pad_max, a.nb_deg_max)) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&net_forward_lds_kernel<Real>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(net_forward_lds_kernel<Real>, dim3(grid), dim3(kNetLdsBlock), lds_bytes, s, a);
+  } else {
+    hipLaunchKernelGGL(net_forward_kernel<Real>, dim3(grid), dim3(kBlock), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -669,8 +812,8 @@ hipError_t launch_fill_zero(float* p, int64_t count, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t launch_net_forward<float>(const NetFwdArgs<float>&, int, hipStream_t);
-template hipError_t launch_net_forward<double>(const NetFwdArgs<double>&, int, hipStream_t);
+template hipError_t launch_net_forward<float>(const NetFwdArgs<float>&, int, size_t, hipStream_t);
+template hipError_t launch_net_forward<double>(const NetFwdArgs<double>&, int, size_t, hipStream_t);
 template hipError_t launch_net_loss<float>(const NetLossArgs<float>&, hipStream_t);
 template hipError_t launch_net_loss<double>(const NetLossArgs<double>&, hipStream_t);
 

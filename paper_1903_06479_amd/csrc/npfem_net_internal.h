@@ -24,6 +24,8 @@ struct NetMeshDev {
   int n, n_pad;                // vertices, rows padded to a multiple of 32
   const int* nb_ptr;           // [n+1] CSR neighbours
   const int* nb_idx;
+  const int* nb_ell;           // [nb_deg][n_pad] the same lists padded (ELL), column q at q * n_pad
+  int nb_deg;                  // ELL width (maximum degree)
   const double* Xc;            // [n][3] rest positions minus their mass-weighted centroid
   const double* mass;          // [n]
   double inv_rho;              // 1 / max |X_i - X_c|
@@ -86,6 +88,7 @@ struct NetFwdArgs {
   const int* cell_mesh;
   const int* cells;            // nullable list of batch cells; else cell k of the batch
   int n_cells;
+  int nb_deg_max;              // largest ELL width of the plan's meshes
   double h;
   const Real* x;               // [V][3]
   const Real* v;
@@ -123,8 +126,14 @@ struct NetBwdArgs {
   float* partial;              // [grid][count] per-workgroup gradient sums
 };
 
+// Forward launch: with lds_bytes > 0 the LDS-resident variant (512 threads, the cell's
+// activations and neighbour lists in LDS) is used, else the variant that gathers from
+// memory (any mesh size).
 template <typename Real>
-hipError_t launch_net_forward(const NetFwdArgs<Real>& a, int grid, hipStream_t s);
+hipError_t launch_net_forward(const NetFwdArgs<Real>& a, int grid, size_t lds_bytes, hipStream_t s);
+// LDS the resident variant needs for meshes up to n_pad rows and degree nb_deg (0 if it
+// does not fit a compute unit).
+size_t net_forward_lds_bytes(int n_pad, int nb_deg);
 template <typename Real>
 hipError_t launch_net_loss(const NetLossArgs<Real>& a, hipStream_t s);
 hipError_t launch_net_backward(const NetBwdArgs& a, int grid, hipStream_t s);

@@ -81,25 +81,30 @@ def test_first_guess_matches_oracle():
         assert np.abs(u0[s] - ref).max() <= 1e-10 * np.abs(ref).max() + 4e-16 * np.abs(b.x[s]).max()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_inference_matches_oracle(precision):
-    """delta of every cell (world frame) against the oracle network on the same inputs."""
+@pytest.mark.parametrize("precision,n_verts,variant", [("fp32", 642, "lds"), ("fp64", 642, "lds"),
+                                                      ("fp32", 642, "memory"), ("fp32", 2562, "auto")])
+def test_inference_matches_oracle(precision, n_verts, variant, monkeypatch):
+    """delta of every cell (world frame) against the oracle network on the same inputs,
+    for the LDS-resident forward variant and the one that gathers from memory (forced by
+    NPFEM_NET_NO_LDS, and taken by itself for the 2562-vertex mesh)."""
     from paper_1903_06479_amd import Batch, Net
+    if variant == "memory":
+        monkeypatch.setenv("NPFEM_NET_NO_LDS", "1")
     cfg = mp.NetConfig()
-    b = workloads.shear(n_cells=7, seed=41)
-    X, Tr = b.meshes[642]
-    m = oracle_model(642)
+    b = workloads.shear(n_cells=7 if n_verts == 642 else 3, n_verts=n_verts, seed=41)
+    X, Tr = b.meshes[n_verts]
+    m = oracle_model(n_verts)
     dt = torch.float64 if precision == "fp64" else torch.float32
     x, v = rounded(b.x, precision), rounded(b.v, precision)
     f = rounded(workloads.drag_forces(b, x, v), precision)
     plan = make([(X, Tr)], precision)
-    batch = Batch(plan, np.zeros(7, np.int32))
+    batch = Batch(plan, np.zeros(b.n_cells, np.int32))
     theta = gpu_params(cfg, 3)
     net = Net(plan, theta.astype(np.float32))
     assert np.array_equal(net.get_params(), theta.astype(np.float32))
     delta = net.infer(batch, T(x, dt), T(v, dt), T(f, dt)).cpu().numpy().astype(np.float64)
     A = mp.neighbour_mean_matrix(len(X), Tr)
-    for c in range(7):
+    for c in range(b.n_cells):
         s = b.cell_slice(c)
         ref = mp.predict_delta(theta, X, x[s], v[s], f[s], m.mass, DT, A, cfg)
         assert relerr(delta[s], ref) <= REL, (c, relerr(delta[s], ref))
