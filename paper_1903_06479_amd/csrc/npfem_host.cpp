@@ -734,7 +734,7 @@ npfem_status batch_schedule(npfem_batch* b, int T, int m) {
   const int slots = p->cu_count * per_cu;
   b->grid = p->prm.grid_blocks > 0 ? p->prm.grid_blocks : slots;
   b->grid = std::max(1, std::min(b->grid, b->n_tiles));
-  b->n_vec = 6 + 2 * m;
+  b->n_vec = 5 + 2 * m;
   b->slot_stride = (int64_t)b->n_vec * T * 3 * b->n_pad_max;
   const size_t wbytes = (size_t)b->grid * b->slot_stride * sizeof(Real);
   if ((s = b->sched.alloc(wbytes, &b->work))) return s;

@@ -185,17 +185,18 @@ __device__ inline Real sl2_tau(Real a1, Real a2, Real sig1, Real J) {
 
 template <typename Real>
 __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double h, double Gn,
-                         const Real* xn, const Real* ut, Real* work, const Real* bvec, Real* gout,
+                         const Real* xn, const Real* ut, const Real* bvec, Real* work, Real* gout,
                          double* red, EvalResult& res) {
   const int n = M.n, np = M.n_pad, nt = M.nt, ch = M.chunk;
   const Real inv_h2 = Real(1.0 / (h * h));
   const Real beta = Real(mat.beta), kb = Real(mat.k_bend);
   const Real Cst = Real(mat.C), Bsk = Real(mat.B), Dsk = Real(mat.D);
 
-  // The corner buffer holds, per triangle, the in-plane gradient of its three corners
-  // (9 values) and its volume-gradient vector (e1 x e2)/6 (3 values).  When all
-  // triangles fit one chunk the enclosed volume is summed in the triangle pass itself;
-  // otherwise it is summed first, in a pass of its own.
+  // xn, ut, bvec and gout are the cell's vectors in LDS.  The corner buffer holds, per
+  // triangle, the in-plane gradient of corners a and b (6 values; corner c gets minus
+  // their sum) and the normal e1 x e2 (3 values; the volume gradient of each corner is
+  // a sixth of it).  When all triangles fit one chunk the enclosed volume is summed in
+  // the triangle pass itself; otherwise it is summed first, in a pass of its own.
   const bool single = nt <= ch;
   // ---- pass A: (volume when chunked) and bending residuals R_i -> work -------------
   double accA[3] = {0.0, 0.0, 0.0};   // volume, bending energy, bending Rayleigh energy
@@ -357,12 +358,9 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       work[3 * ch + tt] = gbx;
       work[4 * ch + tt] = gby;
       work[5 * ch + tt] = gbz;
-      work[6 * ch + tt] = -(gax + gbx);
-      work[7 * ch + tt] = -(gay + gby);
-      work[8 * ch + tt] = -(gaz + gbz);
-      work[9 * ch + tt] = nx / Real(6);      // volume gradient of each corner: (e1 x e2) / 6
-      work[10 * ch + tt] = ny / Real(6);
-      work[11 * ch + tt] = nz / Real(6);
+      work[6 * ch + tt] = nx;
+      work[7 * ch + tt] = ny;
+      work[8 * ch + tt] = nz;
       if (single) {
         // x_a . (x_b x x_c) = E1 . (E2 x x_c) with E1 = x_a - x_c, E2 = x_b - x_c (FP64)
         const double cx = (double)xn[c] + (double)ut[c], cy = (double)xn[np + c] + (double)ut[np + c],
@@ -383,7 +381,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     } else {
       __syncthreads();
     }
-    const Real coef = Real(coefd);
+    const Real coef = Real(coefd / 6.0);         // per corner: k C / G_n * (e1 x e2) / 6
     const bool last = t0 + ch >= nt;
     for (int i = tid(); i < n; i += kBlock) {
       Real gx = 0, gy = 0, gz = 0, vx = 0, vy = 0, vz = 0;
@@ -393,12 +391,24 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
         const int t = cid / 3 - t0;
         if (cid >= 0 && t >= 0 && t < tn) {
           const int k = cid - 3 * (cid / 3);
-          gx += work[(3 * k) * ch + t];
-          gy += work[(3 * k + 1) * ch + t];
-          gz += work[(3 * k + 2) * ch + t];
-          vx += work[9 * ch + t];
-          vy += work[10 * ch + t];
-          vz += work[11 * ch + t];
+          const Real ax = work[t], ay = work[ch + t], az = work[2 * ch + t];
+          const Real bx = work[3 * ch + t], by = work[4 * ch + t], bz = work[5 * ch + t];
+          if (k == 0) {
+            gx += ax;
+            gy += ay;
+            gz += az;
+          } else if (k == 1) {
+            gx += bx;
+            gy += by;
+            gz += bz;
+          } else {
+            gx += -(ax + bx);
+            gy += -(ay + by);
+            gz += -(az + bz);
+          }
+          vx += work[6 * ch + t];
+          vy += work[7 * ch + t];
+          vz += work[8 * ch + t];
         }
       }
       gx += coef * vx;
@@ -687,7 +697,7 @@ __device__ inline void tile_product(const MeshDev<Real>& M, const SolverDev& sol
 // ---------------------------------------------------------------------------------
 // The step
 // ---------------------------------------------------------------------------------
-enum { VB = 0, VU, VG, VGT, VD, VQ, VS0 };
+enum { VB = 0, VU, VG, VD, VQ, VS0 };   // per-cell workspace vectors (history from VS0)
 
 template <typename Real>
 struct Tile {
@@ -794,9 +804,11 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
   const MeshDev<Real>& M = A.meshes[td.mesh];
   const int n = M.n, np = M.n_pad, cnt = td.count, len = 3 * np;
   Tile<Real> tl{W, np, A.tile_cells_max};
-  Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);
-  Real* ut = xn + 3 * np;
-  Real* work = ut + 3 * np;
+  Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);   // the current cell's x_n, trial u,
+  Real* ut = xn + 3 * np;                                    // gradient and b in LDS
+  Real* gl = ut + 3 * np;
+  Real* bl = gl + 3 * np;
+  Real* work = bl + 3 * np;
   const double h = A.sol.h;
   const int m = A.sol.m;
   const double eps = Eps<Real>::v;
@@ -849,12 +861,14 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
     const int cell = A.tile_cells[td.first + j];
     stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
     vcopy(ut, tl.vec(VU, j), len);
+    vcopy(bl, tl.vec(VB, j), len);
     __syncthreads();
     EvalResult r;
-    evaluate(M, A.mat, h, CS[j].Gn, xn, ut, work, tl.vec(VB, j), tl.vec(VG, j), red, r);
+    evaluate(M, A.mat, h, CS[j].Gn, xn, ut, bl, work, gl, red, r);
     const bool bad = !isfinite(r.E) || !isfinite(r.resid);
     const bool done = bad || r.resid <= A.sol.tol;
-    if (!done) vcopy(tl.vec(VQ, j), tl.vec(VG, j), len);
+    vcopy(tl.vec(VG, j), gl, len);
+    if (!done) vcopy(tl.vec(VQ, j), gl, len);
     if (tid() == 0) {
       CellState& cs = CS[j];
       cs.E = r.E;
@@ -902,9 +916,10 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
       if (!cs.active) continue;                                  // uniform: read after a barrier
       const int cell = A.tile_cells[td.first + j];
       stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
+      vcopy(bl, tl.vec(VB, j), len);
       Real* U = tl.vec(VU, j);
       Real* G = tl.vec(VG, j);
-      Real* GT = tl.vec(VGT, j);
+      Real* GT = gl;                                             // trial gradient (LDS)
       Real* D = tl.vec(VD, j);
       Real* Q = tl.vec(VQ, j);
       const int hn = cs.hist_n, head = cs.hist_head;
@@ -986,7 +1001,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
           }
           __syncthreads();
         }
-        evaluate(M, A.mat, h, cs.Gn, xn, ut, work, tl.vec(VB, j), GT, red, r);
+        evaluate(M, A.mat, h, cs.Gn, xn, ut, bl, work, GT, red, r);
         const double slack = A.sol.noise * fmax(cs.noise, r.noise);
         accepted = isfinite(r.E) && (r.E <= cs.E + A.sol.c1 * alpha * gd + slack);
         if (accepted) break;
@@ -1202,9 +1217,10 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
   const int64_t voff = A.cell_voff[cell];
   Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);
   Real* ut = xn + 3 * np;
-  Real* work = ut + 3 * np;
-  Real* B = scratch + (size_t)cell * 2 * 3 * A.n_pad_max;
-  Real* G = B + 3 * A.n_pad_max;
+  Real* G = ut + 3 * np;
+  Real* B = G + 3 * np;
+  Real* work = B + 3 * np;
+  (void)scratch;
   stage_aos(xn, A.x + 3 * voff, n, np);
   for (int e = tid(); e < len; e += kBlock) {
     const int c = e / np, i = e - c * np;
@@ -1216,7 +1232,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
   stage_aos(ut, u + 3 * voff, n, np);
   __syncthreads();
   EvalResult r;
-  evaluate(M, A.mat, A.sol.h, Gn, xn, ut, work, B, G, red, r);
+  evaluate(M, A.mat, A.sol.h, Gn, xn, ut, B, work, G, red, r);
   for (int e = tid(); e < 3 * n; e += kBlock) {
     const int i = e / 3, c = e - 3 * i;
     grad[3 * voff + e] = G[c * np + i];
@@ -1271,8 +1287,10 @@ __global__ void drag_kernel(const Real* x, const Real* v, const int64_t* cell_vo
 
 template <typename Real>
 size_t lds_bytes(int n_pad, int chunk, int stage_rows) {
-  const size_t work = (size_t)(3 * n_pad > 12 * chunk ? 3 * n_pad : 12 * chunk);
-  size_t region = sizeof(Real) * (6 * (size_t)n_pad + work);
+  // x_n, trial u, gradient, b (3 n_pad each), then the corner chunks (9 per triangle,
+  // at least 3 n_pad: the bending pass keeps its residuals there)
+  const size_t work = (size_t)(3 * n_pad > 9 * chunk ? 3 * n_pad : 9 * chunk);
+  size_t region = sizeof(Real) * (12 * (size_t)n_pad + work);
   if (stage_rows > 0 && n_pad <= kStageMaxPad) {
     const size_t st = (size_t)stage_rows * (n_pad + 8) * 2;
     region = region > st ? region : st;
