@@ -392,3 +392,64 @@ def test_autotuner_keeps_the_solution():
     x2, _, st = batch.step(xi, vi, fi)
     torch.cuda.synchronize()
     assert (x2 - x0).abs().max().item() <= 1e-5 * np.ptp(X[:, 0])
+
+
+def test_c1_stretch_200_steps_matches_oracle_trajectory():
+    """The full stretch run (200 steps, FP64, m = 5, residual 1e-8 as configured) against
+    the oracle's trajectory written by tests/golden/make_c1_stretch.py (residual 1e-12,
+    or its last iterate where FP64 rounding stalls it).  Each step converged to residual
+    r leaves a position error of about r F_s / (m / h^2): with r = 1e-8, forces up to
+    F_s = 300 pN, m / h^2 = 4e4 pN/um and D = 7.82 um that is 1e-11 D per step, and the
+    errors of successive steps add up along the trajectory, so step k is checked against
+    1e-11 k D.  (Per-step parity at 1e-10 D is checked by the 20-step test above.)"""
+    import json, os
+    from paper_1903_06479_amd import Batch, CONVERGED
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c1_stretch_oracle.json")))
+    b = workloads.stretch()
+    X, Tr = b.meshes[258]
+    D = np.ptp(X[:, 0])
+    # the line-search slack covers the rounding of the GPU's FP64 sums of g (per-thread
+    # partial sums, then a tree: up to ~13 ulps of sum|terms| over 1,280 triangles)
+    plan = make([(X, Tr)], "fp64", tol=1e-8, lbfgs_m=5, noise_factor=64.0)
+    batch = Batch(plan, np.zeros(1, np.int32))
+    xg, vg = T(X, torch.float64), T(np.zeros_like(X), torch.float64)
+    for k in range(1, 201):
+        f = T(workloads.stretch_forces(b, k, total_steps=200), torch.float64)
+        xg, vg, st = batch.step(xg, vg, f)
+        s = batch.stats_to_numpy(st)
+        assert s["status"][0] == CONVERGED, (k, s)
+        if str(k) in golden["x"]:
+            err = np.abs(xg.cpu().numpy() - np.array(golden["x"][str(k)])).max() / D
+            print(f"step {k}: max |x - x_oracle| / D = {err:.2e}")
+            assert err <= 1e-11 * k, (k, err)
+
+
+def test_throughput_full_size_sampled_cells():
+    """The 100,000-cell throughput step in the benchmark's launch configuration (5 cells
+    per tile, history 2, BF16 products, HIP graph): every cell converges, and sampled
+    cells agree with the converged FP64 oracle on the same (FP32) inputs within 1e-5 D."""
+    from paper_1903_06479_amd import Batch, CONVERGED
+    b = workloads.throughput(n_cells=100000)
+    X, Tr = b.meshes[642]
+    D = np.ptp(X[:, 0])
+    plan = make([(X, Tr)], "fp32", inverse_bf16=1)
+    batch = Batch(plan, np.zeros(b.n_cells, np.int32))
+    batch.schedule(cells_per_tile=5, lbfgs_m=2)
+    batch.set_graph(True)
+    x = T(b.x, torch.float32)
+    v = torch.zeros_like(x)
+    zeta = torch.full((b.n_cells,), workloads.drag_coefficient(642), dtype=torch.float64, device=dev())
+    p = b.poiseuille
+    f = batch.drag_forces(x, v, zeta, T(b.shear_rate, torch.float64), T(b.origin, torch.float64),
+                          p["umax"], p["radius"], p["axis_y"], p["axis_z"])
+    xo, vo, st = batch.step(x, v, f)
+    xo, vo, st = batch.step(x, v, f, x_out=xo, v_out=vo, stats=st)       # graph replay
+    torch.cuda.synchronize()
+    s = batch.stats_to_numpy(st)
+    assert np.all(s["status"] == CONVERGED)
+    m = oracle_model(642)
+    xi, vi, fi, xg = (a.cpu().numpy().astype(np.float64) for a in (x, v, f, xo))
+    for c in (0, 49999, 99999):
+        sl = b.cell_slice(c)
+        xr, _, _ = oracle_step(m, xi[sl], vi[sl], fi[sl])
+        assert np.abs(xg[sl] - xr).max() <= 1e-5 * D, c
