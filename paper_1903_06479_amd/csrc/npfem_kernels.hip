@@ -157,6 +157,14 @@ struct EvalResult {
 };
 
 // SL(2) projection of the singular values (section 2.1.2): t = 1 + tau, the largest
+// Reciprocal and square root of the FP32 bulk arithmetic: the hardware instructions
+// (v_rcp_f32, v_sqrt_f32, about 1 ulp) instead of the correctly rounded sequences; the
+// FP64 path keeps the exact operations.
+template <typename Real> __device__ inline Real rcp_(Real x) { return Real(1) / x; }
+template <> __device__ inline float rcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename Real> __device__ inline Real sqrt_(Real x) { return sqrt(x); }
+template <> __device__ inline float sqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // root of t^4 - s1 t^3 + s2 t - 1, written in deviations s_i = 1 + a_i so that small
 // strains lose no digits:  f(tau) = (1+tau)^3 (tau - a1) + tau (1 + a2) + a2.
 // f is convex for t >= s1/2 and f(s1/2) <= 0, so Newton from any start right of the
@@ -168,7 +176,7 @@ __device__ inline Real sl2_tau(Real a1, Real a2, Real sig1, Real J) {
     tau = a1;                                             // f(s1) = J - 1 >= 0
   } else {
     const Real s3 = sig1 * sig1 * sig1;
-    tau = a1 + fmin((Real(1) - J) / fmax(s3, Real(1e-30)), Real(1));
+    tau = a1 + fmin((Real(1) - J) * rcp_(fmax(s3, Real(1e-30))), Real(1));
   }
   const Real tol = Real(Eps<Real>::v) * Real(4);
   for (int it = 0; it < 60; ++it) {
@@ -176,7 +184,7 @@ __device__ inline Real sl2_tau(Real a1, Real a2, Real sig1, Real J) {
     const Real t2 = t * t;
     const Real f = t2 * t * (tau - a1) + tau * (Real(1) + a2) + a2;
     const Real df = t2 * (Real(1) + Real(4) * tau - Real(3) * a1) + Real(1) + a2;
-    const Real step = f / df;
+    const Real step = f * rcp_(df);
     tau -= step;
     if (!(fabs(step) > tol * (Real(1) + fabs(tau)))) break;
   }
@@ -225,11 +233,11 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       uy += w * duy;
       uz += w * duz;
     }
-    const Real Ai = M.vor_area[i], inv_A = Real(1) / Ai;
+    const Real Ai = M.vor_area[i], inv_A = rcp_(Ai);
     lx *= inv_A; ly *= inv_A; lz *= inv_A;
     ux *= inv_A; uy *= inv_A; uz *= inv_A;
-    const Real nrm = sqrt(lx * lx + ly * ly + lz * lz);
-    const Real sc = nrm > Real(1e-30) ? M.ell0[i] / nrm : Real(0);
+    const Real nrm = sqrt_(lx * lx + ly * ly + lz * lz);
+    const Real sc = nrm > Real(1e-30) ? M.ell0[i] * rcp_(nrm) : Real(0);
     const Real rx = lx - sc * lx, ry = ly - sc * ly, rz = lz - sc * lz;
     accA[1] += 0.5 * (double)(kb * Ai) * ((double)rx * rx + (double)ry * ry + (double)rz * rz);
     accA[2] += 0.5 * (double)(beta * kb * Ai) * ((double)ux * ux + (double)uy * uy + (double)uz * uz);
@@ -311,31 +319,38 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       const Real g1x = eu1x * d01 + eu2x * d11, g1y = eu1y * d01 + eu2y * d11, g1z = eu1z * d01 + eu2z * d11;
       const Real c01 = Real(C01);
       const Real nx = Real(Nx), ny = Real(Ny), nz = Real(Nz);
-      const Real nn = sqrt(Real(NN));
+      const Real nn = sqrt_(Real(NN));
       // area ratio J = sigma1 sigma2 = |e1 x e2| / (2 A0)
       const Real Jsq_m1 = Real(NN * M.inv4a2[t] - 1.0);
-      const Real J = sqrt(fmax(Real(1) + Jsq_m1, Real(0)));
-      const Real Jm1 = Jsq_m1 / (J + Real(1));
+      const Real J = sqrt_(fmax(Real(1) + Jsq_m1, Real(0)));
+      const Real Jm1 = Jsq_m1 * rcp_(J + Real(1));
       const Real half = Real(0.5 * (C00 - C11));
-      const Real disc = sqrt(half * half + c01 * c01);
+      const Real disc = sqrt_(half * half + c01 * c01);
       const Real s1m = Real(0.5 * ((C00 - 1.0) + (C11 - 1.0))) + disc;          // sigma1^2 - 1
-      const Real sig1 = sqrt(fmax(Real(1) + s1m, Real(0)));
-      const Real a1 = s1m / (sig1 + Real(1));                                  // sigma1 - 1
-      const Real inv_s1 = sig1 > Real(1e-30) ? Real(1) / sig1 : Real(0);
+      const Real sig1 = sqrt_(fmax(Real(1) + s1m, Real(0)));
+      const Real a1 = s1m * rcp_(sig1 + Real(1));                              // sigma1 - 1
+      const Real inv_s1 = sig1 > Real(1e-30) ? rcp_(sig1) : Real(0);
       const Real a2 = (Jm1 - a1) * inv_s1;                                     // sigma2 - 1
       const Real sig2 = Real(1) + a2;
       // right singular vectors v1, v2 = perp(v1); left u1 = F v1 / sigma1, u2 = nhat x u1
       Real vx, vy;
       if (half >= Real(0)) { vx = half + disc; vy = c01; } else { vx = c01; vy = disc - half; }
-      const Real vn = sqrt(vx * vx + vy * vy);
-      if (vn > Real(0)) { vx /= vn; vy /= vn; } else { vx = Real(1); vy = Real(0); }
+      const Real vn = sqrt_(vx * vx + vy * vy);
+      if (vn > Real(0)) {
+        const Real ivn = rcp_(vn);
+        vx *= ivn;
+        vy *= ivn;
+      } else {
+        vx = Real(1);
+        vy = Real(0);
+      }
       const Real u1x = (f0x * vx + f1x * vy) * inv_s1, u1y = (f0y * vx + f1y * vy) * inv_s1, u1z = (f0z * vx + f1z * vy) * inv_s1;
-      const Real inv_nn = nn > Real(1e-30) ? Real(1) / nn : Real(0);
+      const Real inv_nn = nn > Real(1e-30) ? rcp_(nn) : Real(0);
       const Real hx = nx * inv_nn, hy = ny * inv_nn, hz = nz * inv_nn;
       const Real u2x = hy * u1z - hz * u1y, u2y = hz * u1x - hx * u1z, u2z = hx * u1y - hy * u1x;
       // area PD: closest SL(2) element diag(t, 1/t)
       const Real tau = sl2_tau<Real>(a1, a2, sig1, J);
-      const Real dA1 = a1 - tau, dA2 = a2 + tau / (Real(1) + tau);
+      const Real dA1 = a1 - tau, dA2 = a2 + tau * rcp_(Real(1) + tau);
       // modified Skalak: f'(s) = B/2 s (s^2 - 1) + D (s - 1)^3
       const Real s2m = a2 * (Real(2) + a2);                                    // sigma2^2 - 1
       const Real fp1 = Real(0.5) * Bsk * sig1 * s1m + Dsk * a1 * a1 * a1;
