@@ -927,7 +927,8 @@ npfem_status npfem_batch_autotune(npfem_batch* b, const void* x, const void* v, 
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   double best = 1e300;
-  int bT = b->T, bm = b->m;
+  const int T0 = b->T, m0 = b->m;
+  int bT = T0, bm = m0;
   const int Ts[] = {5, 10, 16, 21};
   const int ms[] = {2, 3, 5, 8};
   npfem_status st = NPFEM_OK;
@@ -957,7 +958,12 @@ npfem_status npfem_batch_autotune(npfem_batch* b, const void* x, const void* v, 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->use_graph = use_graph;
-  if (st) return st;
+  if (st) {
+    const std::string msg = g_err;
+    (void)schedule(b, T0, m0);               // leave the batch on the schedule it had
+    g_err = msg;
+    return st;
+  }
   if (best_ms) *best_ms = best;
   return schedule(b, bT, bm);
 }
