@@ -366,7 +366,7 @@ struct DeviceBuffers {
 
 struct MeshPlan {
   const npfem_mesh* mesh;
-  int n_pad, chunk;
+  int n_pad, chunk, vec_lds = 1;
   std::vector<double> mass;
   double floor_force;
   MeshDev<float> dev32;
@@ -405,6 +405,7 @@ npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>&
   d.nt = m->nt;
   d.n_pad = np;
   d.chunk = mp.chunk;
+  d.vec_lds = mp.vec_lds;
   npfem_status s;
   if ((s = p->buf.upload(m->tri.data(), m->tri.size(), &d.tri))) return s;
   auto w = conv(m->nb_w), va = conv(m->vor_area), e0 = conv(m->ell0), ms = conv(mp.mass);
@@ -474,12 +475,31 @@ npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>&
 
 // Largest triangle chunk for which the step's LDS fits the budget.
 template <typename Real>
-int choose_chunk(int np, int nt, size_t budget) {
-  if (lds_bytes<Real>(np, nt, 0) <= budget) return nt;
+int choose_chunk(int np, int nt, size_t budget, int vec_lds) {
+  if (lds_bytes<Real>(np, nt, 0, vec_lds) <= budget) return nt;
   int lo = 0;
   for (int ch = nt; ch >= 64; ch -= 64)
-    if (lds_bytes<Real>(np, ch, 0) <= budget) { lo = ch; break; }
+    if (lds_bytes<Real>(np, ch, 0, vec_lds) <= budget) { lo = ch; break; }
   return lo;
+}
+
+// LDS layout of a mesh: the first fit of (gradient and b in LDS, whole triangle list in
+// one chunk, two workgroups per CU), (in the workspace, one chunk, two per CU), (in LDS,
+// one chunk, one per CU), (in the workspace, largest chunk, one per CU).
+template <typename Real>
+void choose_layout(int np, int nt, size_t half, size_t cap, int* chunk, int* vec_lds) {
+  const size_t budgets[4] = {half, half, cap, cap};
+  const int vls[4] = {1, 0, 1, 0};
+  for (int k = 0; k < 4; ++k) {
+    const int ch = choose_chunk<Real>(np, nt, budgets[k], vls[k]);
+    if (ch == nt || (k == 3 && ch > 0)) {
+      *chunk = ch;
+      *vec_lds = vls[k];
+      return;
+    }
+  }
+  *chunk = 0;
+  *vec_lds = 0;
 }
 
 }  // namespace
@@ -534,9 +554,10 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
     mp.n_pad = round_up(n, 32);
     // two workgroups per CU when the whole triangle list fits in half the LDS
     const size_t half = 80 * 1024 - 512;
-    mp.chunk = fp64 ? choose_chunk<double>(mp.n_pad, m->nt, half) : choose_chunk<float>(mp.n_pad, m->nt, half);
-    if (mp.chunk < std::min(m->nt, 256))
-      mp.chunk = fp64 ? choose_chunk<double>(mp.n_pad, m->nt, lds_cap) : choose_chunk<float>(mp.n_pad, m->nt, lds_cap);
+    if (fp64)
+      choose_layout<double>(mp.n_pad, m->nt, half, lds_cap, &mp.chunk, &mp.vec_lds);
+    else
+      choose_layout<float>(mp.n_pad, m->nt, half, lds_cap, &mp.chunk, &mp.vec_lds);
     if (mp.chunk <= 0)
       return fail(NPFEM_E_UNSUPPORTED, "plan_create: mesh too large for the LDS in this precision");
     // lumped mass by barycentric area (section 2.1)
@@ -637,7 +658,7 @@ struct npfem_batch {
   const int* mesh_n = nullptr;
   void* eval_scratch = nullptr;
   // schedule: tiling, history length and workspace (rebuilt by the autotuner)
-  int T = 0, m = 0, n_tiles = 0, grid = 0, n_vec = 0;
+  int T = 0, m = 0, n_tiles = 0, grid = 0, n_vec = 0, stage_k = 0;
   size_t lds = 0;
   int64_t slot_stride = 0;
   DeviceBuffers sched;
@@ -686,6 +707,7 @@ StepArgs<Real> make_args(npfem_batch* b) {
   a.work = static_cast<Real*>(b->work);
   a.cstate = b->cstate;
   a.n_pad_max = b->n_pad_max;
+  a.stage_k = b->stage_k;
   return a;
 }
 
@@ -725,8 +747,10 @@ npfem_status batch_schedule(npfem_batch* b, int T, int m) {
   const int stage_rows = (p->prm.inverse_bf16 && std::is_same<Real, float>::value) ? 16 * ((3 * T + 15) / 16) : 0;
   for (int mi = 0; mi < nm; ++mi)
     if (!b->by_mesh[mi].empty())
-      lds = std::max(lds, lds_bytes<Real>(p->meshes[mi].n_pad, p->meshes[mi].chunk, stage_rows));
+      lds = std::max(lds, lds_bytes<Real>(p->meshes[mi].n_pad, p->meshes[mi].chunk, stage_rows,
+                                          p->meshes[mi].vec_lds));
   b->lds = lds;
+  b->stage_k = stage_cols(lds, stage_rows, b->n_pad_max);
   HIP_TRY(set_lds_limit<Real>(lds));
   int per_cu = 0;
   HIP_TRY(occupancy<Real>(&per_cu, lds));
@@ -734,7 +758,11 @@ npfem_status batch_schedule(npfem_batch* b, int T, int m) {
   const int slots = p->cu_count * per_cu;
   b->grid = p->prm.grid_blocks > 0 ? p->prm.grid_blocks : slots;
   b->grid = std::max(1, std::min(b->grid, b->n_tiles));
-  b->n_vec = 5 + 2 * m;
+  // b, u, grad, d, q, the history, and a trial gradient if some mesh keeps it out of LDS
+  bool any_global = false;
+  for (int mi = 0; mi < nm; ++mi)
+    if (!b->by_mesh[mi].empty() && !p->meshes[mi].vec_lds) any_global = true;
+  b->n_vec = 5 + 2 * m + (any_global ? 1 : 0);
   b->slot_stride = (int64_t)b->n_vec * T * 3 * b->n_pad_max;
   const size_t wbytes = (size_t)b->grid * b->slot_stride * sizeof(Real);
   if ((s = b->sched.alloc(wbytes, &b->work))) return s;

@@ -17,6 +17,7 @@ template <typename Real>
 struct MeshDev {
   int n, nt, n_pad;            // vertices, triangles, n rounded up to 32
   int chunk;                   // triangles per LDS corner chunk
+  int vec_lds;                 // 1: the current cell's gradient and b live in LDS (else in the workspace)
   const int* tri;              // [nt][3]
   const double* dminv;         // [nt][4] D_m^-1 row-major (FP64 in every precision: the
   const double* area;          // [nt] rest area            triangle geometry is formed in FP64)
@@ -88,6 +89,7 @@ struct StepArgs {
   Real* work;                  // [slots][n_vec_slot][T][3][n_pad_max]
   CellState* cstate;           // [slots][T]
   int n_pad_max;
+  int stage_k;                 // k columns per LDS chunk of the BF16 tile product (0: unstaged)
   const Real* x;               // [V][3]
   const Real* v;
   const Real* f;
@@ -115,9 +117,11 @@ hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, c
                        const int* mesh_n, int n_cells, const double* zeta, const double* rate,
                        const double* origin, double umax, double radius, double ay, double az,
                        Real* f, hipStream_t s);
-// LDS of the step kernel; stage_rows > 0: rows of the BF16 tile product staged in LDS.
+// LDS of the step kernel; stage_rows > 0: rows of the BF16 tile product staged in LDS;
+// vec_lds: the gradient and b of the current cell are kept in LDS too.
 template <typename Real>
-size_t lds_bytes(int n_pad, int chunk, int stage_rows);
+size_t lds_bytes(int n_pad, int chunk, int stage_rows, int vec_lds);
+int stage_cols(size_t lds, int stage_rows, int n_pad);
 template <typename Real>
 hipError_t set_lds_limit(size_t bytes);
 template <typename Real>

@@ -612,77 +612,82 @@ __device__ inline void tile_gemm_bf16(const uint16_t* __restrict__ Abits, const 
   }
 }
 
-// Same product with the tile's rows staged once in LDS as BF16 (rows padded to 16),
-// and each wave carrying four column blocks at a time, so that four independent
-// B fragments are in flight per k step and every A fragment read from LDS feeds four
-// matrix instructions.  Needs 16 ceil(rows/16) (n_pad + 8) BF16 of LDS at `stage`.
-constexpr int kStageMaxPad = 1024;
+// Same product with the tile's rows staged in LDS as BF16 (rows padded to 16), in
+// chunks of at most kc_max columns of k (one chunk when the rows fit the LDS region),
+// and each wave carrying four column blocks at a time, so that four independent B
+// fragments are in flight per k step and every A fragment read from LDS feeds four
+// matrix instructions.  A chunk needs 16 ceil(rows/16) (kc + 8) BF16 of LDS at `stage`;
+// the partial products of later chunks are added to Out by the lane that wrote it.
+constexpr int kStageMaxPad = 1024;     // n_pad up to which the whole k range is staged
 __device__ inline void tile_gemm_bf16_lds(const uint16_t* __restrict__ Abits, const float* __restrict__ diag,
                                           int np, const float* __restrict__ In, float* __restrict__ Out,
-                                          int rows, __bf16* stage) {
+                                          int rows, __bf16* stage, int kc_max) {
   const __bf16* A = reinterpret_cast<const __bf16*>(Abits);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
   const int mb_n = (rows + 15) >> 4;
-  const int ldk = np + 8;
-  const int k8n = np >> 3;
-  __syncthreads();
-  for (int e = tid(); e < mb_n * 16 * k8n; e += kBlock) {
-    const int r = e / k8n, k8 = (e - r * k8n) << 3;
-    bf16x8 v;
-    if (r < rows) {
-      const floatx4 lo = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + k8);
-      const floatx4 hi = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + k8 + 4);
-      v = bf16x8{(__bf16)lo.x, (__bf16)lo.y, (__bf16)lo.z, (__bf16)lo.w,
-                 (__bf16)hi.x, (__bf16)hi.y, (__bf16)hi.z, (__bf16)hi.w};
-    } else {
-      v = bf16x8{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f,
-                 (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-    }
-    *reinterpret_cast<bf16x8*>(stage + r * ldk + k8) = v;
-  }
-  __syncthreads();
   constexpr int NB = 4;
   const int ncb = np >> 4;
-  for (int g0 = wave; g0 < ncb; g0 += 4 * NB) {
-    floatx4 acc[4][NB];
-    const __bf16* arow[NB];
-    bool valid[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int cb = g0 + 4 * q;
-      valid[q] = cb < ncb;
-      arow[q] = A + (size_t)((valid[q] ? cb : 0) * 16 + l16) * np + 8 * kq;
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) acc[mb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int kb0 = 0; kb0 < np; kb0 += kc_max) {
+    const int kc = min(kc_max, np - kb0);               // a multiple of 32
+    const int ldk = kc + 8;
+    const int k8n = kc >> 3;
+    __syncthreads();
+    for (int e = tid(); e < mb_n * 16 * k8n; e += kBlock) {
+      const int r = e / k8n, k8 = (e - r * k8n) << 3;
+      bf16x8 v;
+      if (r < rows) {
+        const floatx4 lo = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + kb0 + k8);
+        const floatx4 hi = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + kb0 + k8 + 4);
+        v = bf16x8{(__bf16)lo.x, (__bf16)lo.y, (__bf16)lo.z, (__bf16)lo.w,
+                   (__bf16)hi.x, (__bf16)hi.y, (__bf16)hi.z, (__bf16)hi.w};
+      } else {
+        v = bf16x8{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f,
+                   (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+      }
+      *reinterpret_cast<bf16x8*>(stage + r * ldk + k8) = v;
     }
-    for (int k0 = 0; k0 < np; k0 += 32) {
-      bf16x8 bq[NB];
+    __syncthreads();
+    for (int g0 = wave; g0 < ncb; g0 += 4 * NB) {
+      floatx4 acc[4][NB];
+      const __bf16* arow[NB];
+      bool valid[NB];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) bq[q] = *reinterpret_cast<const bf16x8*>(arow[q] + k0);
+      for (int q = 0; q < NB; ++q) {
+        const int cb = g0 + 4 * q;
+        valid[q] = cb < ncb;
+        arow[q] = A + (size_t)((valid[q] ? cb : 0) * 16 + l16) * np + kb0 + 8 * kq;
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        if (mb < mb_n) {
-          const bf16x8 aq = *reinterpret_cast<const bf16x8*>(stage + (mb * 16 + l16) * ldk + k0 + 8 * kq);
+        for (int mb = 0; mb < 4; ++mb) acc[mb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+      }
+      for (int k0 = 0; k0 < kc; k0 += 32) {
+        bf16x8 bq[NB];
 #pragma unroll
-          for (int q = 0; q < NB; ++q) acc[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, bq[q], acc[mb][q], 0, 0, 0);
+        for (int q = 0; q < NB; ++q) bq[q] = *reinterpret_cast<const bf16x8*>(arow[q] + k0);
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          if (mb < mb_n) {
+            const bf16x8 aq = *reinterpret_cast<const bf16x8*>(stage + (mb * 16 + l16) * ldk + k0 + 8 * kq);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) acc[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, bq[q], acc[mb][q], 0, 0, 0);
+          }
         }
       }
-    }
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      if (!valid[q]) continue;
-      const int n = (g0 + 4 * q) * 16 + l16;
-      const float dn = diag[n];
+      for (int q = 0; q < NB; ++q) {
+        if (!valid[q]) continue;
+        const int n = (g0 + 4 * q) * 16 + l16;
+        const float dn = diag[n];
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        if (mb < mb_n) {
+        for (int mb = 0; mb < 4; ++mb) {
+          if (mb < mb_n) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r = mb * 16 + 4 * kq + i;
-            if (r < rows) {
-              const size_t o = (size_t)r * np + n;
-              Out[o] = acc[mb][q][i] + dn * In[o];
+            for (int i = 0; i < 4; ++i) {
+              const int r = mb * 16 + 4 * kq + i;
+              if (r < rows) {
+                const size_t o = (size_t)r * np + n;
+                Out[o] = acc[mb][q][i] + (kb0 == 0 ? dn * In[o] : Out[o]);
+              }
             }
           }
         }
@@ -694,13 +699,13 @@ __device__ inline void tile_gemm_bf16_lds(const uint16_t* __restrict__ Abits, co
 // The tile's product with H~^-1 (which 0) or h^2 M~^-1 (which 1) in the plan's format.
 template <typename Real>
 __device__ inline void tile_product(const MeshDev<Real>& M, const SolverDev& sol, int which, const Real* In,
-                                    Real* Out, int rows, unsigned char* stage) {
+                                    Real* Out, int rows, unsigned char* stage, int stage_k) {
   if constexpr (std::is_same<Real, float>::value) {
     if (sol.bf16) {
       const uint16_t* Ab = which == 0 ? M.hinv_bf : M.minv_bf;
       const float* dg = which == 0 ? M.hinv_diag : M.minv_diag;
-      if (M.n_pad <= kStageMaxPad)
-        tile_gemm_bf16_lds(Ab, dg, M.n_pad, In, Out, rows, reinterpret_cast<__bf16*>(stage));
+      if (stage_k >= 32)
+        tile_gemm_bf16_lds(Ab, dg, M.n_pad, In, Out, rows, reinterpret_cast<__bf16*>(stage), stage_k);
       else
         tile_gemm_bf16(Ab, dg, M.n_pad, In, Out, rows);
       return;
@@ -819,15 +824,19 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
   const MeshDev<Real>& M = A.meshes[td.mesh];
   const int n = M.n, np = M.n_pad, cnt = td.count, len = 3 * np;
   Tile<Real> tl{W, np, A.tile_cells_max};
-  Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);   // the current cell's x_n, trial u,
-  Real* ut = xn + 3 * np;                                    // gradient and b in LDS
+  Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);   // the current cell's x_n, trial u
+  Real* ut = xn + 3 * np;                                    // (and gradient and b) in LDS
+  const bool vl = M.vec_lds != 0;
   Real* gl = ut + 3 * np;
   Real* bl = gl + 3 * np;
-  Real* work = bl + 3 * np;
+  Real* work = xn + (vl ? 12 : 6) * np;
   const double h = A.sol.h;
   const int m = A.sol.m;
   const double eps = Eps<Real>::v;
   __shared__ double s_vol[kMaxTile];
+  // per cell: gradient and b in LDS, or (meshes too large for that) in the workspace
+  auto gvec = [&](int j) { return vl ? gl : tl.vec(VS0 + 2 * m, j); };
+  auto bvec = [&](int j) { return vl ? bl : tl.vec(VB, j); };
 
   // ---- initial state: b = M v_n / h + F_ext, |grad V(x_n)|^2, first guess --------
   for (int j = 0; j < cnt; ++j) {
@@ -852,7 +861,8 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
     __syncthreads();
   }
   if (!A.u_guess) {
-    tile_product(M, A.sol, 1, tl.mat(VB), tl.mat(VU), 3 * cnt, reinterpret_cast<unsigned char*>(xn));  // u = h^2 M~^-1 b
+    tile_product(M, A.sol, 1, tl.mat(VB), tl.mat(VU), 3 * cnt, reinterpret_cast<unsigned char*>(xn),
+                 A.stage_k);                                              // u = h^2 M~^-1 b
     __syncthreads();
     if (A.guess_only || A.u_delta) {
       for (int j = 0; j < cnt; ++j) {
@@ -876,14 +886,14 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
     const int cell = A.tile_cells[td.first + j];
     stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
     vcopy(ut, tl.vec(VU, j), len);
-    vcopy(bl, tl.vec(VB, j), len);
+    if (vl) vcopy(bl, tl.vec(VB, j), len);
     __syncthreads();
     EvalResult r;
-    evaluate(M, A.mat, h, CS[j].Gn, xn, ut, bl, work, gl, red, r);
+    evaluate(M, A.mat, h, CS[j].Gn, xn, ut, bvec(j), work, gvec(j), red, r);
     const bool bad = !isfinite(r.E) || !isfinite(r.resid);
     const bool done = bad || r.resid <= A.sol.tol;
-    vcopy(tl.vec(VG, j), gl, len);
-    if (!done) vcopy(tl.vec(VQ, j), gl, len);
+    vcopy(tl.vec(VG, j), gvec(j), len);
+    if (!done) vcopy(tl.vec(VQ, j), gvec(j), len);
     if (tid() == 0) {
       CellState& cs = CS[j];
       cs.E = r.E;
@@ -924,17 +934,18 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
     }
     __syncthreads();
     if (sint[1] == 0) break;
-    tile_product(M, A.sol, 0, tl.mat(VQ), tl.mat(VD), 3 * cnt, reinterpret_cast<unsigned char*>(xn));  // r = H~^-1 q
+    tile_product(M, A.sol, 0, tl.mat(VQ), tl.mat(VD), 3 * cnt, reinterpret_cast<unsigned char*>(xn),
+                 A.stage_k);                                              // r = H~^-1 q
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
       CellState& cs = CS[j];
       if (!cs.active) continue;                                  // uniform: read after a barrier
       const int cell = A.tile_cells[td.first + j];
       stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
-      vcopy(bl, tl.vec(VB, j), len);
+      if (vl) vcopy(bl, tl.vec(VB, j), len);
       Real* U = tl.vec(VU, j);
       Real* G = tl.vec(VG, j);
-      Real* GT = gl;                                             // trial gradient (LDS)
+      Real* GT = gvec(j);                                        // trial gradient
       Real* D = tl.vec(VD, j);
       Real* Q = tl.vec(VQ, j);
       const int hn = cs.hist_n, head = cs.hist_head;
@@ -1016,7 +1027,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
           }
           __syncthreads();
         }
-        evaluate(M, A.mat, h, cs.Gn, xn, ut, bl, work, GT, red, r);
+        evaluate(M, A.mat, h, cs.Gn, xn, ut, bvec(j), work, GT, red, r);
         const double slack = A.sol.noise * fmax(cs.noise, r.noise);
         accepted = isfinite(r.E) && (r.E <= cs.E + A.sol.c1 * alpha * gd + slack);
         if (accepted) break;
@@ -1232,10 +1243,10 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
   const int64_t voff = A.cell_voff[cell];
   Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);
   Real* ut = xn + 3 * np;
-  Real* G = ut + 3 * np;
-  Real* B = G + 3 * np;
-  Real* work = B + 3 * np;
-  (void)scratch;
+  const bool vl = M.vec_lds != 0;
+  Real* G = vl ? ut + 3 * np : scratch + (size_t)cell * 2 * 3 * A.n_pad_max;
+  Real* B = vl ? G + 3 * np : G + 3 * A.n_pad_max;
+  Real* work = xn + (vl ? 12 : 6) * np;
   stage_aos(xn, A.x + 3 * voff, n, np);
   for (int e = tid(); e < len; e += kBlock) {
     const int c = e / np, i = e - c * np;
@@ -1300,12 +1311,21 @@ __global__ void drag_kernel(const Real* x, const Real* v, const int64_t* cell_vo
 
 }  // namespace
 
+// k columns of the BF16 tile product staged per chunk: what the LDS region of `lds`
+// bytes holds for stage_rows rows (a multiple of 32, capped at n_pad; 0: not staged).
+int stage_cols(size_t lds, int stage_rows, int n_pad) {
+  if (stage_rows <= 0 || lds <= (size_t)kLdsHeader) return 0;
+  const long kc = (long)((lds - kLdsHeader) / (2 * (size_t)stage_rows)) - 8;
+  const long k32 = kc / 32 * 32;
+  return (int)(k32 >= n_pad ? n_pad : (k32 >= 32 ? k32 : 0));
+}
+
 template <typename Real>
-size_t lds_bytes(int n_pad, int chunk, int stage_rows) {
-  // x_n, trial u, gradient, b (3 n_pad each), then the corner chunks (9 per triangle,
-  // at least 3 n_pad: the bending pass keeps its residuals there)
+size_t lds_bytes(int n_pad, int chunk, int stage_rows, int vec_lds) {
+  // x_n, trial u (and, with vec_lds, the gradient and b), 3 n_pad each, then the corner
+  // chunks (9 per triangle, at least 3 n_pad: the bending pass keeps its residuals there)
   const size_t work = (size_t)(3 * n_pad > 9 * chunk ? 3 * n_pad : 9 * chunk);
-  size_t region = sizeof(Real) * (12 * (size_t)n_pad + work);
+  size_t region = sizeof(Real) * ((vec_lds ? 12 : 6) * (size_t)n_pad + work);
   if (stage_rows > 0 && n_pad <= kStageMaxPad) {
     const size_t st = (size_t)stage_rows * (n_pad + 8) * 2;
     region = region > st ? region : st;
@@ -1381,7 +1401,7 @@ hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, c
 }
 
 #define NPFEM_INSTANTIATE(R)                                                                       \
-  template size_t lds_bytes<R>(int, int, int);                                                     \
+  template size_t lds_bytes<R>(int, int, int, int);                                                     \
   template hipError_t set_lds_limit<R>(size_t);                                                    \
   template hipError_t occupancy<R>(int*, size_t);                                                  \
   template hipError_t launch_step<R>(const StepArgs<R>&, int, size_t, hipStream_t, int*);          \
