@@ -51,7 +51,7 @@ typedef enum {
   NPFEM_E_NOT_SPD = -3,      /* M~ or H~ not symmetric positive definite */
   NPFEM_E_HIP = -4,          /* HIP runtime failure */
   NPFEM_E_OOM = -5,          /* device or host allocation failed */
-  NPFEM_E_UNSUPPORTED = -6   /* valid request this build does not support */
+  NPFEM_E_UNSUPPORTED = -6   /* valid request the library does not support */
 } npfem_status;
 
 typedef enum { NPFEM_FP32 = 0, NPFEM_FP64 = 1 } npfem_precision;

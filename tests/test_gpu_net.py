@@ -5,8 +5,9 @@ The GPU applies the weight matrices in BF16 and stores activations in BF16 (FP32
 accumulation); the oracle runs in FP64 with the same BF16-rounded weight matrices and
 FP32 biases.  Each BF16 rounding of an activation has relative error <= 2^-9, and the
 network rounds features, the neighbour means and every layer's output (about 10
-roundings along any path), so the outputs and gradients are compared in the relative
-L2 norm with a bound of 2e-2 (10 x 2^-9 = 1.95e-2)."""
+roundings along any path); rounding errors of independent sign add in quadrature
+(sqrt(10) 2^-9 = 6.2e-3), so outputs and gradients are compared in the relative L2
+norm with a bound of 1e-2 (single parameter blocks, which sum fewer terms: 3e-2)."""
 import numpy as np
 import pytest
 
@@ -19,7 +20,7 @@ from conftest import oracle_model
 pytestmark = pytest.mark.gpu
 
 DT = workloads.DT_US
-REL = 2e-2
+REL = 1e-2
 
 
 @pytest.fixture(autouse=True)
@@ -143,6 +144,7 @@ def test_loss_and_gradient_match_oracle():
         data.append((feats, mp.target(R, sc, delta)))
     Lr, gr = mp.loss_and_grad(theta, data, A, cfg)
     g = grad.cpu().numpy().astype(np.float64)
+    print(f"loss rel. error {abs(loss - Lr) / Lr:.2e}, gradient rel. L2 error {relerr(g, gr):.2e}")
     assert abs(loss - Lr) <= REL * Lr
     assert relerr(g, gr) <= REL
     # block by block (each weight matrix and bias vector)
@@ -233,3 +235,27 @@ def test_training_reduces_the_loss():
         net.adam_step(g, lr=3e-3)
     assert np.all(np.isfinite(losses))
     assert losses[-1] < 0.8 * losses[0], losses
+
+
+def test_trained_network_cuts_iterations_on_held_out_cells():
+    """The committed weights (trained on runs 0-3 of the training workload) on cells of a
+    held-out run (100), from the state after one plain step: fewer quasi-Newton
+    iterations than the plain start, every cell converged, and the same positions
+    within 1e-5 of the cell diameter."""
+    import os
+    from paper_1903_06479_amd import Batch, Net
+    from paper_1903_06479_amd import warmstart as ws
+    b = workloads.training(100, n_cells=256)
+    X, Tr = b.meshes[642]
+    plan = make([(X, Tr)], "fp32", inverse_bf16=1)
+    batch = Batch(plan, np.zeros(b.n_cells, np.int32))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    net = Net(plan, np.load(os.path.join(root, "paper_1903_06479_amd", "data", "warmstart_642.npy")))
+    flow = ws.Flow(batch, np.full(b.n_cells, workloads.drag_coefficient(642)), b.shear_rate, b.origin, b.poiseuille)
+    tr = ws.collect(batch, flow, T(b.x), T(b.v), 4)
+    later = {k: v[1:] for k, v in tr.items()}
+    r = ws.compare(batch, net, later, float(np.ptp(X[:, 0])))
+    print(r)
+    assert r["all_converged"]
+    assert r["iterations_learned"] <= r["iterations_plain"] - 0.3, r
+    assert r["max_dx_over_D"] <= 1e-5, r
