@@ -436,17 +436,25 @@ def main():
     pl = forms["plain"]
     n = 642
     mean_kernel_s = pl["step_call_ms"] / 1e3
-    # roofline of the dominant kernel: the step kernel of the plain form
+    # roofline of the dominant kernel: the step kernel of the plain form.  Algorithmic
+    # bytes per cell-step in the streaming form of the method: state in/out 60 n; per
+    # iteration the two-loop recursion over the history (4 m 12 n + 36 n) and the
+    # product's input and output (24 n); per evaluation x_n, u, b in and the gradient out
+    # (48 n).
     I, E = pl["iterations_mean"], pl["evaluations_mean"]
-    f32, f64, mfma = cell_step_flops(n, mesh.nt, mesh.ne, I, E, sched["lbfgs_m"])
-    # vector arithmetic in FP32-equivalent flops: a double flop costs two single ones
-    alu_flops = b.n_cells * (f32 + 2.0 * f64)
-    io_bytes = b.n_cells * 60.0 * n                                  # x, v, f in; x, v out (FP32)
-    roof = {"bound": "alu", "achieved": alu_flops / mean_kernel_s / 1e12, "peak": VALU_FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": None, "traffic": None}
+    mh = sched["lbfgs_m"]
+    cell_bytes = 60.0 * n + I * (4 * mh * 12 * n + 36 * n + 24 * n) + E * 48.0 * n
+    roof = {"bound": "hbm", "achieved": b.n_cells * cell_bytes / mean_kernel_s / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": None, "traffic": None}
     roof["frac"] = roof["achieved"] / roof["peak"]
     if b.n_cells == 100000 and sched["cells_per_tile"] == 5 and sched["lbfgs_m"] == 2:
         roof["traffic"] = measured_traffic()
+    # the same kernel against the vector-arithmetic and matrix-core peaks
+    f32, f64, mfma = cell_step_flops(n, mesh.nt, mesh.ne, I, E, mh)
+    alu_flops = b.n_cells * (f32 + 2.0 * f64)         # a double flop costs two single ones
+    roof_alu = {"achieved": alu_flops / mean_kernel_s / 1e12, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    roof_alu["frac"] = roof_alu["achieved"] / roof_alu["peak"]
+    io_bytes = b.n_cells * 60.0 * n                                  # x, v, f in; x, v out (FP32)
     ch = forms[chosen]
     out = {
         "metric": "RBC cell-steps/sec at residual <=1e-6, plain vs batched+learned warm start",
@@ -461,6 +469,8 @@ def main():
         "forms": forms,
         "roofline": roof,
         "roofline_kernel": "step kernel, plain form",
+        "roofline_alu": roof_alu,
+        "algorithmic_bytes_per_cell_step": cell_bytes,
         "work_per_cell_step": {"valu_fp32_flops": f32, "valu_fp64_flops": f64, "mfma_flops": mfma,
                                "state_bytes": 60.0 * n},
         "mfma_TFLOPs": b.n_cells * mfma / mean_kernel_s / 1e12,
