@@ -60,6 +60,15 @@ __device__ inline void vcopy(Real* dst, const Real* src, int len) {
   for (int e = W * tid(); e < len; e += W * kBlock) vstore(dst, e, vload(src, e));
 }
 
+// Reads of the per-mesh tables (global memory shared by every cell): with the address
+// space explicit the compiler emits global loads with a scalar base and a 32-bit offset,
+// not flat loads, which would also hold up every wait on the LDS.
+template <typename T>
+__device__ inline T gld(const T* p, int i) {
+  typedef const T __attribute__((address_space(1))) GT;
+  return ((GT*)p)[(unsigned)i];
+}
+
 // Sum N (<= 32) doubles over the workgroup; fixed order, so deterministic.
 template <int N>
 __device__ inline void block_sum(double (&v)[N], double* red) {
@@ -95,13 +104,40 @@ __device__ inline double dot_vec(const Real* a, const Real* b, int len, double* 
 // LDS staging
 // ---------------------------------------------------------------------------------
 
-// x_n of one cell: global AoS [n][3] -> LDS SoA [3][np] (padding zero).
+// One cell's AoS [n][3] values -> SoA [3][np] (padding zero); load(e) yields AoS element
+// e = 3 i + c.  Each thread issues the loads of up to kStageBatch elements before its
+// first store, so staging a cell costs one memory latency rather than one per element.
+constexpr int kStageBatch = 8;
+template <typename Real, typename Load>
+__device__ inline void aos_to_soa(Real* dst, int n, int np, Load load) {
+  const int len = 3 * n;
+  for (int base = 0; base < len; base += kStageBatch * kBlock) {
+    Real v[kStageBatch];
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) {
+      const int e = base + k * kBlock + tid();
+      v[k] = e < len ? load(e) : Real(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kStageBatch; ++k) {
+      const int e = base + k * kBlock + tid();
+      if (e < len) {
+        const int i = e / 3, c = e - 3 * i;
+        dst[c * np + i] = v[k];
+      }
+    }
+  }
+  const int pad = np - n;
+  for (int e = tid(); e < 3 * pad; e += kBlock) {
+    const int c = e / pad, i = n + (e - c * pad);
+    dst[c * np + i] = Real(0);
+  }
+}
+
+// x_n of one cell: global AoS [n][3] -> LDS SoA [3][np].
 template <typename Real>
 __device__ inline void stage_aos(Real* dst, const Real* src, int n, int np) {
-  for (int e = tid(); e < 3 * np; e += kBlock) {
-    const int c = e / np, i = e - c * np;
-    dst[e] = i < n ? src[3 * i + c] : Real(0);
-  }
+  aos_to_soa(dst, n, np, [&](int e) { return src[e]; });
 }
 
 // ---------------------------------------------------------------------------------
@@ -117,7 +153,7 @@ __device__ double volume_normaliser(const MeshDev<Real>& M, const Real* xn, Real
     const int tn = min(ch, nt - t0);
     for (int tt = tid(); tt < tn; tt += kBlock) {
       const int t = t0 + tt;
-      const int a = M.tri[3 * t], b = M.tri[3 * t + 1], c = M.tri[3 * t + 2];
+      const int a = gld(M.tri, 3 * t), b = gld(M.tri, 3 * t + 1), c = gld(M.tri, 3 * t + 2);
       const Real e1x = xn[a] - xn[c], e1y = xn[np + a] - xn[np + c], e1z = xn[2 * np + a] - xn[2 * np + c];
       const Real e2x = xn[b] - xn[c], e2y = xn[np + b] - xn[np + c], e2z = xn[2 * np + b] - xn[2 * np + c];
       work[tt] = (e1y * e2z - e1z * e2y) / Real(6);
@@ -127,8 +163,8 @@ __device__ double volume_normaliser(const MeshDev<Real>& M, const Real* xn, Real
     __syncthreads();
     for (int i = tid(); i < n; i += kBlock) {
       Real gx = 0, gy = 0, gz = 0;
-      for (int q = M.vc_ptr[i]; q < M.vc_ptr[i + 1]; ++q) {
-        const int t = M.vc_idx[q] / 3 - t0;
+      for (int q = gld(M.vc_ptr, i); q < gld(M.vc_ptr, i + 1); ++q) {
+        const int t = gld(M.vc_idx, q) / 3 - t0;
         if (t >= 0 && t < tn) {
           gx += work[t];
           gy += work[ch + t];
@@ -210,7 +246,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
   double accA[3] = {0.0, 0.0, 0.0};   // volume, bending energy, bending Rayleigh energy
   if (!single) {
     for (int t = tid(); t < nt; t += kBlock) {
-      const int a = M.tri[3 * t], b = M.tri[3 * t + 1], c = M.tri[3 * t + 2];
+      const int a = gld(M.tri, 3 * t), b = gld(M.tri, 3 * t + 1), c = gld(M.tri, 3 * t + 2);
       const double ax = (double)xn[a] + ut[a], ay = (double)xn[np + a] + ut[np + a], az = (double)xn[2 * np + a] + ut[2 * np + a];
       const double bx = (double)xn[b] + ut[b], by = (double)xn[np + b] + ut[np + b], bz = (double)xn[2 * np + b] + ut[2 * np + b];
       const double cx = (double)xn[c] + ut[c], cy = (double)xn[np + c] + ut[np + c], cz = (double)xn[2 * np + c] + ut[2 * np + c];
@@ -223,8 +259,8 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     const Real uix = ut[i], uiy = ut[np + i], uiz = ut[2 * np + i];
 #pragma unroll 6
     for (int q = 0; q < M.nb_deg; ++q) {
-      const int j = M.nb_ell[q * np + i];
-      const Real w = M.nbw_ell[q * np + i];
+      const int j = gld(M.nb_ell, q * np + i);
+      const Real w = gld(M.nbw_ell, q * np + i);
       const Real dux = ut[j] - uix, duy = ut[np + j] - uiy, duz = ut[2 * np + j] - uiz;
       lx += w * ((xn[j] - xix) + dux);
       ly += w * ((xn[np + j] - xiy) + duy);
@@ -233,11 +269,11 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       uy += w * duy;
       uz += w * duz;
     }
-    const Real Ai = M.vor_area[i], inv_A = rcp_(Ai);
+    const Real Ai = gld(M.vor_area, i), inv_A = rcp_(Ai);
     lx *= inv_A; ly *= inv_A; lz *= inv_A;
     ux *= inv_A; uy *= inv_A; uz *= inv_A;
     const Real nrm = sqrt_(lx * lx + ly * ly + lz * lz);
-    const Real sc = nrm > Real(1e-30) ? M.ell0[i] * rcp_(nrm) : Real(0);
+    const Real sc = nrm > Real(1e-30) ? gld(M.ell0, i) * rcp_(nrm) : Real(0);
     const Real rx = lx - sc * lx, ry = ly - sc * ly, rz = lz - sc * lz;
     accA[1] += 0.5 * (double)(kb * Ai) * ((double)rx * rx + (double)ry * ry + (double)rz * rz);
     accA[2] += 0.5 * (double)(beta * kb * Ai) * ((double)ux * ux + (double)uy * uy + (double)uz * uz);
@@ -264,13 +300,13 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     const Real rix = work[i], riy = work[np + i], riz = work[2 * np + i];
 #pragma unroll 6
     for (int q = 0; q < M.nb_deg; ++q) {
-      const int j = M.nb_ell[q * np + i];
-      const Real w = M.nbw_ell[q * np + i];
+      const int j = gld(M.nb_ell, q * np + i);
+      const Real w = gld(M.nbw_ell, q * np + i);
       gx += w * (work[j] - rix);
       gy += w * (work[np + j] - riy);
       gz += w * (work[2 * np + j] - riz);
     }
-    const Real mi = M.mass[i] * inv_h2;
+    const Real mi = gld(M.mass, i) * inv_h2;
     const Real ux = ut[i], uy = ut[np + i], uz = ut[2 * np + i];
     const Real bx = bvec[i], by = bvec[np + i], bz = bvec[2 * np + i];
     gout[i] = kb * gx + (mi * ux - bx);
@@ -289,10 +325,10 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     const int tn = min(ch, nt - t0);
     for (int tt = tid(); tt < tn; tt += kBlock) {
       const int t = t0 + tt;
-      const int a = M.tri[3 * t], b = M.tri[3 * t + 1], c = M.tri[3 * t + 2];
-      const double D00 = M.dminv[4 * t], D01 = M.dminv[4 * t + 1], D10 = M.dminv[4 * t + 2], D11 = M.dminv[4 * t + 3];
+      const int a = gld(M.tri, 3 * t), b = gld(M.tri, 3 * t + 1), c = gld(M.tri, 3 * t + 2);
+      const double D00 = gld(M.dminv, 4 * t), D01 = gld(M.dminv, 4 * t + 1), D10 = gld(M.dminv, 4 * t + 2), D11 = gld(M.dminv, 4 * t + 3);
       const Real d00 = Real(D00), d01 = Real(D01), d10 = Real(D10), d11 = Real(D11);
-      const Real A0 = Real(M.area[t]);
+      const Real A0 = Real(gld(M.area, t));
       // The strain measures (sigma - 1, area ratio - 1) are small differences of O(1)
       // quantities, so the edges, F = [e1 e2] D_m^-1, F^T F and |e1 x e2|^2 are formed
       // in FP64 from the stored values (exact differences); everything after that works
@@ -321,7 +357,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       const Real nx = Real(Nx), ny = Real(Ny), nz = Real(Nz);
       const Real nn = sqrt_(Real(NN));
       // area ratio J = sigma1 sigma2 = |e1 x e2| / (2 A0)
-      const Real Jsq_m1 = Real(NN * M.inv4a2[t] - 1.0);
+      const Real Jsq_m1 = Real(NN * gld(M.inv4a2, t) - 1.0);
       const Real J = sqrt_(fmax(Real(1) + Jsq_m1, Real(0)));
       const Real Jm1 = Jsq_m1 * rcp_(J + Real(1));
       const Real half = Real(0.5 * (C00 - C11));
@@ -402,7 +438,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       Real gx = 0, gy = 0, gz = 0, vx = 0, vy = 0, vz = 0;
 #pragma unroll 6
       for (int q = 0; q < M.vc_deg; ++q) {
-        const int cid = M.vc_ell[q * np + i];
+        const int cid = gld(M.vc_ell, q * np + i);
         const int t = cid / 3 - t0;
         if (cid >= 0 && t >= 0 && t < tn) {
           const int k = cid - 3 * (cid / 3);
@@ -436,7 +472,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       gout[np + i] = gy;
       gout[2 * np + i] = gz;
       if (last) {
-        const Real mi = M.mass[i] * inv_h2;
+        const Real mi = gld(M.mass, i) * inv_h2;
         const Real ux = ut[i], uy = ut[np + i], uz = ut[2 * np + i];
         const Real bx = bvec[i], by = bvec[np + i], bz = bvec[2 * np + i];
         const double mux = (double)mi * ux, muy = (double)mi * uy, muz = (double)mi * uz;
@@ -728,11 +764,10 @@ struct Tile {
 };
 
 template <typename Real>
-__device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, const Tile<Real>& tl,
-                              int j, int cell, CellState& cs, const Real* xn, double* red, double* bc) {
+__device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, int cell, CellState& cs,
+                              const Real* xn, const Real* U, double* red, double* bc) {
   const int n = M.n, np = M.n_pad;
   const int64_t voff = A.cell_voff[cell];
-  const Real* U = tl.vec(VU, j);
   const double h = A.sol.h;
   Real* xo = A.x_out + 3 * voff;
   Real* vo = A.v_out + 3 * voff;
@@ -746,7 +781,7 @@ __device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, c
     // v = u / h, then damp its departure from the best-fit rigid motion (section 2.1.4)
     double s1[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int i = tid(); i < n; i += kBlock) {
-      const double m = M.mass[i];
+      const double m = gld(M.mass, i);
       s1[0] += m;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -760,7 +795,7 @@ __device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, c
     const double vc[3] = {s1[4] / s1[0], s1[5] / s1[0], s1[6] / s1[0]};
     double s2[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // L (3), I_xx I_yy I_zz I_xy I_xz I_yz
     for (int i = tid(); i < n; i += kBlock) {
-      const double m = M.mass[i];
+      const double m = gld(M.mass, i);
       const double rx = (double)xn[i] + (double)U[i] - xc[0];
       const double ry = (double)xn[np + i] + (double)U[np + i] - xc[1];
       const double rz = (double)xn[2 * np + i] + (double)U[2 * np + i] - xc[2];
@@ -843,12 +878,12 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
     const int cell = A.tile_cells[td.first + j];
     const int64_t voff = A.cell_voff[cell];
     stage_aos(xn, A.x + 3 * voff, n, np);
-    Real* B = tl.vec(VB, j);
-    Real* U = tl.vec(VU, j);
-    for (int e = tid(); e < len; e += kBlock) {
-      const int c = e / np, i = e - c * np;
-      B[e] = i < n ? M.mass[i] * A.v[3 * (voff + i) + c] / Real(h) + A.f[3 * (voff + i) + c] : Real(0);
-      if (A.u_guess) U[e] = i < n ? A.u_guess[3 * (voff + i) + c] : Real(0);
+    const Real* vs = A.v + 3 * voff;
+    const Real* fs = A.f + 3 * voff;
+    aos_to_soa(tl.vec(VB, j), n, np, [&](int e) { return gld(M.mass, e / 3) * vs[e] / Real(h) + fs[e]; });
+    if (A.u_guess) {
+      const Real* gs = A.u_guess + 3 * voff;
+      aos_to_soa(tl.vec(VU, j), n, np, [&](int e) { return gs[e]; });
     }
     __syncthreads();
     const double Gn = volume_normaliser(M, xn, ut, work, red);
@@ -941,8 +976,6 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
       CellState& cs = CS[j];
       if (!cs.active) continue;                                  // uniform: read after a barrier
       const int cell = A.tile_cells[td.first + j];
-      stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
-      if (vl) vcopy(bl, tl.vec(VB, j), len);
       Real* U = tl.vec(VU, j);
       Real* G = tl.vec(VG, j);
       Real* GT = gvec(j);                                        // trial gradient
@@ -950,21 +983,58 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
       Real* Q = tl.vec(VQ, j);
       const int hn = cs.hist_n, head = cs.hist_head;
       auto slot = [&](int p) { return (head - hn + p + m) % m; };   // p = 0 oldest .. hn-1 newest
-      // second half: y_p . r for every stored pair (one pass)
       constexpr int W = Vec16<Real>::W;
+      typedef typename Vec16<Real>::type V;
+      // When a vector takes at most two 16-byte slots per thread, r and the stored y_p are
+      // loaded in one batch together with the staging of x_n and b and kept in registers
+      // until the direction is formed, so the two halves below cost two memory round
+      // trips instead of four.  The sums run in the same order either way.
+      const bool fused = len <= 2 * W * kBlock;
+      const V zero = {};
+      V rr[2], ys[H][2];
+      const int ek[2] = {W * tid(), W * tid() + W * kBlock};
+      if (fused) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const bool in = ek[k] < len;
+          rr[k] = in ? vload(D, ek[k]) : zero;
+#pragma unroll
+          for (int p = 0; p < H; ++p) {
+            ys[p][k] = in && p < hn ? vload(tl.vec(VS0 + m + slot(p), j), ek[k]) : zero;
+          }
+        }
+      }
+      stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
+      if (vl) vcopy(bl, tl.vec(VB, j), len);
+      // second half: y_p . r for every stored pair (one pass)
       double yr[H];
 #pragma unroll
       for (int p = 0; p < H; ++p) yr[p] = 0.0;
       if (hn > 0) {
+        if (fused) {
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            if (ek[k] < len) {
+#pragma unroll
+              for (int p = 0; p < H; ++p) {
+                if (p < hn) {
+#pragma unroll
+                  for (int w = 0; w < W; ++w) yr[p] += (double)ys[p][k][w] * rr[k][w];
+                }
+              }
+            }
+          }
+        } else {
 #pragma unroll 2
-        for (int e = W * tid(); e < len; e += W * kBlock) {
-          const auto rv = vload(D, e);
+          for (int e = W * tid(); e < len; e += W * kBlock) {
+            const auto rv = vload(D, e);
 #pragma unroll
-          for (int p = 0; p < H; ++p) {
-            if (p < hn) {
-              const auto yv = vload(tl.vec(VS0 + m + slot(p), j), e);
+            for (int p = 0; p < H; ++p) {
+              if (p < hn) {
+                const auto yv = vload(tl.vec(VS0 + m + slot(p), j), e);
 #pragma unroll
-              for (int w = 0; w < W; ++w) yr[p] += (double)yv[w] * rv[w];
+                for (int w = 0; w < W; ++w) yr[p] += (double)yv[w] * rv[w];
+              }
             }
           }
         }
@@ -985,22 +1055,19 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
       // d = -(r + sum_p cf_p s_p), g . d, and the first trial point u + d staged in LDS
       // (one pass)
       double gdv[1] = {0.0};
-#pragma unroll 2
-      for (int e = W * tid(); e < len; e += W * kBlock) {
-        const auto rv = vload(D, e);
+      auto d_slot = [&](int e, const V& rv, const V& gv, const V& uv, auto&& s_of) {
         double z[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) z[w] = rv[w];
 #pragma unroll
         for (int p = 0; p < H; ++p) {
           if (p < hn) {
-            const auto sv = vload(tl.vec(VS0 + slot(p), j), e);
+            const V sv = s_of(p);
 #pragma unroll
             for (int w = 0; w < W; ++w) z[w] += cf[p] * (double)sv[w];
           }
         }
-        const auto gv = vload(G, e), uv = vload(U, e);
-        typename Vec16<Real>::type dv, tv;
+        V dv, tv;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
           dv[w] = Real(-z[w]);
@@ -1009,6 +1076,16 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
         }
         vstore(D, e, dv);
         vstore(ut, e, tv);
+      };
+      if (fused) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+          if (ek[k] < len)
+            d_slot(ek[k], rr[k], vload(G, ek[k]), vload(U, ek[k]), [&](int p) { return vload(tl.vec(VS0 + slot(p), j), ek[k]); });
+      } else {
+#pragma unroll 2
+        for (int e = W * tid(); e < len; e += W * kBlock)
+          d_slot(e, vload(D, e), vload(G, e), vload(U, e), [&](int p) { return vload(tl.vec(VS0 + slot(p), j), e); });
       }
       block_sum<1>(gdv, red);
       const double gd = gdv[0];
@@ -1197,10 +1274,11 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
   for (int j = 0; j < cnt; ++j) {
     const int cell = A.tile_cells[td.first + j];
     stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
+    vcopy(ut, tl.vec(VU, j), len);
     __syncthreads();
     double bc[1] = {s_vol[j]};
     CellState cs = CS[j];
-    finalize_cell(A, M, tl, j, cell, cs, xn, red, bc);
+    finalize_cell(A, M, cell, cs, xn, ut, red, bc);
     __syncthreads();
   }
 }
@@ -1248,10 +1326,9 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
   Real* B = vl ? G + 3 * np : G + 3 * A.n_pad_max;
   Real* work = xn + (vl ? 12 : 6) * np;
   stage_aos(xn, A.x + 3 * voff, n, np);
-  for (int e = tid(); e < len; e += kBlock) {
-    const int c = e / np, i = e - c * np;
-    B[e] = i < n ? M.mass[i] * A.v[3 * (voff + i) + c] / Real(A.sol.h) + A.f[3 * (voff + i) + c] : Real(0);
-  }
+  const Real* vs = A.v + 3 * voff;
+  const Real* fs = A.f + 3 * voff;
+  aos_to_soa(B, n, np, [&](int e) { return gld(M.mass, e / 3) * vs[e] / Real(A.sol.h) + fs[e]; });
   __syncthreads();
   const double Gn = volume_normaliser(M, xn, ut, work, red);
   __syncthreads();
