@@ -32,11 +32,17 @@ template <typename Real> struct Eps;
 template <> struct Eps<float> { static constexpr double v = 1.1920928955078125e-07; };
 template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
 
-// LDS: [red: 4 waves x 32 doubles][32 doubles][ints: 32][xn 3*np][ut 3*np][work max(3*np, 12*chunk)];
-// during the BF16 tile product the region from xn on holds the tile's rows in BF16.
+// LDS: [red: 4 waves x 32 doubles][32 doubles][ints: 32][mesh descriptor][cell vectors ...];
+// during the BF16 tile product the region from the cell vectors on holds the tile's rows
+// in BF16.  The current tile's mesh descriptor is copied to LDS so that reading its table
+// pointers waits on the LDS counter only, never on global loads in flight.
 constexpr int kRedStride = 32;
 constexpr int kRedDoubles = 4 * kRedStride;
-constexpr int kLdsHeader = kRedDoubles * 8 + 32 * 8 + 32 * 4;   // reduction, picked sums, ints
+constexpr int kMeshLds = 256;
+constexpr int kLdsMesh = kRedDoubles * 8 + 32 * 8 + 32 * 4;
+constexpr int kLdsHeader = kLdsMesh + kMeshLds;   // reduction, picked sums, ints, mesh
+static_assert(sizeof(MeshDev<double>) <= kMeshLds && sizeof(MeshDev<float>) <= kMeshLds, "mesh descriptor");
+static_assert(sizeof(MeshDev<double>) % 4 == 0 && sizeof(MeshDev<float>) % 4 == 0, "mesh descriptor");
 
 __device__ inline int tid() { return threadIdx.x; }
 
@@ -68,6 +74,9 @@ __device__ inline T gld(const T* p, int i) {
   typedef const T __attribute__((address_space(1))) GT;
   return ((GT*)p)[(unsigned)i];
 }
+
+// Entries of a vertex's ELL lists (neighbours, incident corners) fetched per group.
+constexpr int kEllGroup = 6;
 
 // Sum N (<= 32) doubles over the workgroup; fixed order, so deterministic.
 template <int N>
@@ -257,23 +266,41 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     Real lx = 0, ly = 0, lz = 0, ux = 0, uy = 0, uz = 0;
     const Real xix = xn[i], xiy = xn[np + i], xiz = xn[2 * np + i];
     const Real uix = ut[i], uiy = ut[np + i], uiz = ut[2 * np + i];
-#pragma unroll 6
-    for (int q = 0; q < M.nb_deg; ++q) {
-      const int j = gld(M.nb_ell, q * np + i);
-      const Real w = gld(M.nbw_ell, q * np + i);
-      const Real dux = ut[j] - uix, duy = ut[np + j] - uiy, duz = ut[2 * np + j] - uiz;
-      lx += w * ((xn[j] - xix) + dux);
-      ly += w * ((xn[np + j] - xiy) + duy);
-      lz += w * ((xn[2 * np + j] - xiz) + duz);
-      ux += w * dux;
-      uy += w * duy;
-      uz += w * duz;
+    Real Ai = 0, l0 = 0;
+    for (int q0 = 0; q0 < M.nb_deg; q0 += kEllGroup) {
+      // a group's neighbours and weights (padding: the vertex itself, weight 0) are all
+      // requested before the first is used; the scheduling barrier keeps them together
+      int jj[kEllGroup];
+      Real ww[kEllGroup];
+#pragma unroll
+      for (int u = 0; u < kEllGroup; ++u) {
+        const bool in = q0 + u < M.nb_deg;
+        jj[u] = in ? gld(M.nb_ell, (q0 + u) * np + i) : i;
+        ww[u] = in ? gld(M.nbw_ell, (q0 + u) * np + i) : Real(0);
+      }
+      if (q0 == 0) {
+        Ai = gld(M.vor_area, i);
+        l0 = gld(M.ell0, i);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kEllGroup; ++u) {
+        const int j = jj[u];
+        const Real w = ww[u];
+        const Real dux = ut[j] - uix, duy = ut[np + j] - uiy, duz = ut[2 * np + j] - uiz;
+        lx += w * ((xn[j] - xix) + dux);
+        ly += w * ((xn[np + j] - xiy) + duy);
+        lz += w * ((xn[2 * np + j] - xiz) + duz);
+        ux += w * dux;
+        uy += w * duy;
+        uz += w * duz;
+      }
     }
-    const Real Ai = gld(M.vor_area, i), inv_A = rcp_(Ai);
+    const Real inv_A = rcp_(Ai);
     lx *= inv_A; ly *= inv_A; lz *= inv_A;
     ux *= inv_A; uy *= inv_A; uz *= inv_A;
     const Real nrm = sqrt_(lx * lx + ly * ly + lz * lz);
-    const Real sc = nrm > Real(1e-30) ? gld(M.ell0, i) * rcp_(nrm) : Real(0);
+    const Real sc = nrm > Real(1e-30) ? l0 * rcp_(nrm) : Real(0);
     const Real rx = lx - sc * lx, ry = ly - sc * ly, rz = lz - sc * lz;
     accA[1] += 0.5 * (double)(kb * Ai) * ((double)rx * rx + (double)ry * ry + (double)rz * rz);
     accA[2] += 0.5 * (double)(beta * kb * Ai) * ((double)ux * ux + (double)uy * uy + (double)uz * uz);
@@ -436,30 +463,31 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     const bool last = t0 + ch >= nt;
     for (int i = tid(); i < n; i += kBlock) {
       Real gx = 0, gy = 0, gz = 0, vx = 0, vy = 0, vz = 0;
-#pragma unroll 6
-      for (int q = 0; q < M.vc_deg; ++q) {
-        const int cid = gld(M.vc_ell, q * np + i);
-        const int t = cid / 3 - t0;
-        if (cid >= 0 && t >= 0 && t < tn) {
-          const int k = cid - 3 * (cid / 3);
-          const Real ax = work[t], ay = work[ch + t], az = work[2 * ch + t];
-          const Real bx = work[3 * ch + t], by = work[4 * ch + t], bz = work[5 * ch + t];
-          if (k == 0) {
-            gx += ax;
-            gy += ay;
-            gz += az;
-          } else if (k == 1) {
-            gx += bx;
-            gy += by;
-            gz += bz;
-          } else {
-            gx += -(ax + bx);
-            gy += -(ay + by);
-            gz += -(az + bz);
-          }
-          vx += work[6 * ch + t];
-          vy += work[7 * ch + t];
-          vz += work[8 * ch + t];
+      // Branch-free, so that the reads of all corners are in flight together: a padding
+      // entry, or a corner outside this chunk, reads the chunk's first triangle and adds
+      // zero; corner k adds g_a, g_b or -(g_a + g_b) (the same roundings as adding each
+      // case on its own).
+      for (int q0 = 0; q0 < M.vc_deg; q0 += kEllGroup) {
+        int cc[kEllGroup];
+#pragma unroll
+        for (int u = 0; u < kEllGroup; ++u) cc[u] = q0 + u < M.vc_deg ? gld(M.vc_ell, (q0 + u) * np + i) : -1;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kEllGroup; ++u) {
+          const int cid = cc[u];
+          const int tri = cid / 3, k = cid - 3 * tri, t = tri - t0;
+          const bool ok = cid >= 0 && t >= 0 && t < tn;
+          const int tc = ok ? t : 0;
+          const Real ax = work[tc], ay = work[ch + tc], az = work[2 * ch + tc];
+          const Real bx = work[3 * ch + tc], by = work[4 * ch + tc], bz = work[5 * ch + tc];
+          const Real nx = work[6 * ch + tc], ny = work[7 * ch + tc], nz = work[8 * ch + tc];
+          const Real sg = ok ? (k == 2 ? Real(-1) : Real(1)) : Real(0);
+          gx += sg * (k == 0 ? ax : (k == 1 ? bx : ax + bx));
+          gy += sg * (k == 0 ? ay : (k == 1 ? by : ay + by));
+          gz += sg * (k == 0 ? az : (k == 1 ? bz : az + bz));
+          vx += ok ? nx : Real(0);
+          vy += ok ? ny : Real(0);
+          vz += ok ? nz : Real(0);
         }
       }
       gx += coef * vx;
@@ -856,7 +884,14 @@ template <typename Real, int H>
 __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* CS, double* red,
                          int* sint, unsigned char* lds) {
   const TileDesc td = A.tiles[tile];
-  const MeshDev<Real>& M = A.meshes[td.mesh];
+  MeshDev<Real>* Ml = reinterpret_cast<MeshDev<Real>*>(lds + kLdsMesh);
+  {
+    constexpr int nw = sizeof(MeshDev<Real>) / 4;
+    const int* src = reinterpret_cast<const int*>(A.meshes + td.mesh);
+    if (tid() < nw) reinterpret_cast<int*>(Ml)[tid()] = src[tid()];
+    __syncthreads();
+  }
+  const MeshDev<Real>& M = *Ml;
   const int n = M.n, np = M.n_pad, cnt = td.count, len = 3 * np;
   Tile<Real> tl{W, np, A.tile_cells_max};
   Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);   // the current cell's x_n, trial u
