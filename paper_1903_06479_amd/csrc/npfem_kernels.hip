@@ -78,17 +78,35 @@ __device__ inline T gld(const T* p, int i) {
 // Entries of a vertex's ELL lists (neighbours, incident corners) fetched per group.
 constexpr int kEllGroup = 6;
 
+// Lane permutation of a double within rows of 16 lanes (DPP, on the vector ALU).
+template <int CTRL>
+__device__ inline double dpp_row(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double read_lane(double x, int lane) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, lane), hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Sum of a double over the wave: within each row of 16 lanes by DPP (pairs, quads, half
+// rows, rows), then the four row sums; the same on every lane, fixed order.
+__device__ inline double wave_sum(double x) {
+  x += dpp_row<0xB1>(x);    // quad_perm [1,0,3,2]
+  x += dpp_row<0x4E>(x);    // quad_perm [2,3,0,1]
+  x += dpp_row<0x141>(x);   // row_half_mirror
+  x += dpp_row<0x140>(x);   // row_mirror
+  return (read_lane(x, 0) + read_lane(x, 16)) + (read_lane(x, 32) + read_lane(x, 48));
+}
+
 // Sum N (<= 32) doubles over the workgroup; fixed order, so deterministic.
 template <int N>
 __device__ inline void block_sum(double (&v)[N], double* red) {
   static_assert(N <= kRedStride, "block_sum: too many values");
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    double x = v[i];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    v[i] = x;
-  }
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) {
@@ -1035,7 +1053,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
           rr[k] = in ? vload(D, ek[k]) : zero;
 #pragma unroll
           for (int p = 0; p < H; ++p) {
-            ys[p][k] = in && p < hn ? vload(tl.vec(VS0 + m + slot(p), j), ek[k]) : zero;
+            ys[p][k] = in && hn > 0 ? vload(tl.vec(VS0 + m + slot(p), j), ek[k]) : zero;
           }
         }
       }
@@ -1052,10 +1070,8 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
             if (ek[k] < len) {
 #pragma unroll
               for (int p = 0; p < H; ++p) {
-                if (p < hn) {
 #pragma unroll
-                  for (int w = 0; w < W; ++w) yr[p] += (double)ys[p][k][w] * rr[k][w];
-                }
+                for (int w = 0; w < W; ++w) yr[p] += (double)(p < hn ? ys[p][k][w] : Real(0)) * rr[k][w];
               }
             }
           }
@@ -1096,11 +1112,9 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
         for (int w = 0; w < W; ++w) z[w] = rv[w];
 #pragma unroll
         for (int p = 0; p < H; ++p) {
-          if (p < hn) {
-            const V sv = s_of(p);
+          const V sv = s_of(p);
 #pragma unroll
-            for (int w = 0; w < W; ++w) z[w] += cf[p] * (double)sv[w];
-          }
+          for (int w = 0; w < W; ++w) z[w] += cf[p] * (double)(p < hn ? sv[w] : Real(0));
         }
         V dv, tv;
 #pragma unroll
@@ -1116,7 +1130,8 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
 #pragma unroll
         for (int k = 0; k < 2; ++k)
           if (ek[k] < len)
-            d_slot(ek[k], rr[k], vload(G, ek[k]), vload(U, ek[k]), [&](int p) { return vload(tl.vec(VS0 + slot(p), j), ek[k]); });
+            d_slot(ek[k], rr[k], vload(G, ek[k]), vload(U, ek[k]),
+                   [&](int p) { return hn > 0 ? vload(tl.vec(VS0 + slot(p), j), ek[k]) : zero; });
       } else {
 #pragma unroll 2
         for (int e = W * tid(); e < len; e += W * kBlock)
@@ -1184,14 +1199,17 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
           const auto yv = gt - gv;
 #pragma unroll
           for (int p = 0; p < H; ++p) {
-            if (p < hn && !(full && p == 0)) {                   // p = 0 is the slot being replaced when full
-              const auto so = vload(tl.vec(VS0 + slot(p), j), e), yo = vload(tl.vec(VS0 + m + slot(p), j), e);
+            // every slot is read (its index is always inside the ring) and the terms of
+            // pairs not in use are switched off, so that all reads are in flight together;
+            // p = 0 is the slot being replaced when the ring is full
+            const bool use = p < hn && !(full && p == 0);
+            const auto so = vload(tl.vec(VS0 + slot(p), j), e), yo = vload(tl.vec(VS0 + m + slot(p), j), e);
 #pragma unroll
-              for (int w = 0; w < W; ++w) {
-                acc[4 + p] += (double)so[w] * gt[w];
-                acc[4 + H + p] += (double)sv[w] * yo[w];
-                acc[4 + 2 * H + p] += (double)yv[w] * so[w];
-              }
+            for (int w = 0; w < W; ++w) {
+              const double sw = use ? (double)so[w] : 0.0, yw = use ? (double)yo[w] : 0.0;
+              acc[4 + p] += sw * gt[w];
+              acc[4 + H + p] += (double)sv[w] * yw;
+              acc[4 + 2 * H + p] += (double)yv[w] * sw;
             }
           }
           vstore(Sn, e, sv);
@@ -1289,11 +1307,9 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
         for (int w = 0; w < W; ++w) qv[w] = gv[w];
 #pragma unroll
         for (int p = 0; p < H; ++p) {
-          if (p < hn2) {
-            const auto yv = vload(tl.vec(VS0 + m + slot2(p), j), e);
+          const auto yv = m > 0 ? vload(tl.vec(VS0 + m + slot2(p), j), e) : gv;
 #pragma unroll
-            for (int w = 0; w < W; ++w) qv[w] -= al_new[p] * (double)yv[w];
-          }
+          for (int w = 0; w < W; ++w) qv[w] -= al_new[p] * (double)(p < hn2 ? yv[w] : Real(0));
         }
         typename Vec16<Real>::type o;
 #pragma unroll
