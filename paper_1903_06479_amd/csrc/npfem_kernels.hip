@@ -190,12 +190,23 @@ __device__ double volume_normaliser(const MeshDev<Real>& M, const Real* xn, Real
     __syncthreads();
     for (int i = tid(); i < n; i += kBlock) {
       Real gx = 0, gy = 0, gz = 0;
-      for (int q = gld(M.vc_ptr, i); q < gld(M.vc_ptr, i + 1); ++q) {
-        const int t = gld(M.vc_idx, q) / 3 - t0;
-        if (t >= 0 && t < tn) {
-          gx += work[t];
-          gy += work[ch + t];
-          gz += work[2 * ch + t];
+      // incident corners from the ELL list, a group of indices in flight together;
+      // padding and corners outside this chunk add zero
+      for (int q0 = 0; q0 < M.vc_deg; q0 += kEllGroup) {
+        int cc[kEllGroup];
+#pragma unroll
+        for (int u = 0; u < kEllGroup; ++u) cc[u] = q0 + u < M.vc_deg ? gld(M.vc_ell, (q0 + u) * np + i) : -1;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kEllGroup; ++u) {
+          const int cid = cc[u];
+          const int t = cid / 3 - t0;
+          const bool ok = cid >= 0 && t >= 0 && t < tn;
+          const int tc = ok ? t : 0;
+          const Real wx = work[tc], wy = work[ch + tc], wz = work[2 * ch + tc];
+          gx += ok ? wx : Real(0);
+          gy += ok ? wy : Real(0);
+          gz += ok ? wz : Real(0);
         }
       }
       acc[i] += gx;
