@@ -658,7 +658,7 @@ struct npfem_batch {
   const int* mesh_n = nullptr;
   void* eval_scratch = nullptr;
   // schedule: tiling, history length and workspace (rebuilt by the autotuner)
-  int T = 0, m = 0, n_tiles = 0, grid = 0, n_vec = 0, stage_k = 0;
+  int T = 0, m = 0, n_tiles = 0, grid = 0, n_vec = 0, stage_k = 0, cs_lds = -1;
   size_t lds = 0;
   int64_t slot_stride = 0;
   DeviceBuffers sched;
@@ -706,6 +706,7 @@ StepArgs<Real> make_args(npfem_batch* b) {
   a.slot_stride = b->slot_stride;
   a.work = static_cast<Real*>(b->work);
   a.cstate = b->cstate;
+  a.cs_lds = b->cs_lds;
   a.n_pad_max = b->n_pad_max;
   a.stage_k = b->stage_k;
   return a;
@@ -749,8 +750,19 @@ npfem_status batch_schedule(npfem_batch* b, int T, int m) {
     if (!b->by_mesh[mi].empty())
       lds = std::max(lds, lds_bytes<Real>(p->meshes[mi].n_pad, p->meshes[mi].chunk, stage_rows,
                                           p->meshes[mi].vec_lds));
+  b->stage_k = stage_cols(lds, stage_rows, b->n_pad_max);   // the staging stays below the cell states
+  // the tile's cell states go to LDS (after everything else) when that costs no
+  // workgroups per CU
+  {
+    const size_t base = (lds + 15) / 16 * 16, with_cs = base + (size_t)T * cell_state_bytes(m);
+    HIP_TRY(set_lds_limit<Real>(with_cs));
+    int per_base = 0, per_cs = 0;
+    HIP_TRY(occupancy<Real>(&per_base, lds));
+    HIP_TRY(occupancy<Real>(&per_cs, with_cs));
+    b->cs_lds = (per_cs >= per_base && per_cs > 0 && with_cs < ((size_t)1 << 31)) ? (int)base : -1;
+    if (b->cs_lds >= 0) lds = with_cs;
+  }
   b->lds = lds;
-  b->stage_k = stage_cols(lds, stage_rows, b->n_pad_max);
   HIP_TRY(set_lds_limit<Real>(lds));
   int per_cu = 0;
   HIP_TRY(occupancy<Real>(&per_cu, lds));

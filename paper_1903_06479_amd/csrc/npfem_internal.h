@@ -54,17 +54,28 @@ struct SolverDev {
   int bf16;                    // products with the inverses on the BF16 matrix cores
 };
 
-// Per-cell scalar state of the step, kept in the workspace between kernel phases.
-struct CellState {
+// Per-cell scalar state of the step for a history of at most H pairs (the arrays are
+// indexed by history slot < m <= H).  The step kernel keeps a tile's states in LDS when
+// that costs no workgroups per CU, else in the workspace.
+template <int H>
+struct CellStateT {
   double E;                    // objective at the current iterate
   double noise;                // sum of |terms| of E (line-search rounding scale)
   double Gn;                   // |grad V(x_n)|^2
   double resid;
-  double rho[kMaxHistory];
-  double alpha[kMaxHistory];
-  double SY[kMaxHistory][kMaxHistory];   // s_i . y_j over the history slots
+  double rho[H];
+  double alpha[H];
+  double SY[H][H];             // s_i . y_j over the history slots
   int hist_n, hist_head, iter, evals, status, active, retry, halvings;
 };
+using CellState = CellStateT<kMaxHistory>;
+
+// History bound of the step kernel variant that runs a history of m pairs.
+inline int history_bound(int m) { return m <= 2 ? 2 : (m <= 5 ? 5 : kMaxHistory); }
+inline size_t cell_state_bytes(int m) {
+  const int H = history_bound(m);
+  return H == 2 ? sizeof(CellStateT<2>) : (H == 5 ? sizeof(CellStateT<5>) : sizeof(CellStateT<kMaxHistory>));
+}
 
 struct TileDesc {
   int mesh;                    // mesh type
@@ -87,7 +98,8 @@ struct StepArgs {
   int n_vec_slot;              // vectors per workspace slot
   int64_t slot_stride;         // Reals per slot
   Real* work;                  // [slots][n_vec_slot][T][3][n_pad_max]
-  CellState* cstate;           // [slots][T]
+  CellState* cstate;           // [slots][T] (read as CellStateT<H>) when cs_lds < 0
+  int cs_lds;                  // byte offset of the tile's cell states in LDS, or -1
   int n_pad_max;
   int stage_k;                 // k columns per LDS chunk of the BF16 tile product (0: unstaged)
   const Real* x;               // [V][3]

@@ -820,8 +820,8 @@ struct Tile {
   __device__ Real* mat(int v) const { return W + (size_t)v * T * 3 * np; }
 };
 
-template <typename Real>
-__device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, int cell, CellState& cs,
+template <typename Real, typename CST>
+__device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, int cell, CST& cs,
                               const Real* xn, const Real* U, double* red, double* bc) {
   const int n = M.n, np = M.n_pad;
   const int64_t voff = A.cell_voff[cell];
@@ -909,8 +909,8 @@ __device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, i
   }
 }
 
-template <typename Real, int H>
-__device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* CS, double* red,
+template <typename Real, int H, typename CST>
+__device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Real>& A, int tile, Real* W, CST* CS, double* red,
                          int* sint, unsigned char* lds) {
   const TileDesc td = A.tiles[tile];
   MeshDev<Real>* Ml = reinterpret_cast<MeshDev<Real>*>(lds + kLdsMesh);
@@ -952,7 +952,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
     __syncthreads();
     const double Gn = volume_normaliser(M, xn, ut, work, red);
     if (tid() == 0) {
-      CellState& cs = CS[j];
+      auto& cs = CS[j];
       cs.Gn = Gn;
       cs.hist_n = cs.hist_head = cs.iter = cs.evals = cs.status = cs.retry = cs.halvings = 0;
       cs.active = 1;
@@ -994,7 +994,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
     vcopy(tl.vec(VG, j), gvec(j), len);
     if (!done) vcopy(tl.vec(VQ, j), gvec(j), len);
     if (tid() == 0) {
-      CellState& cs = CS[j];
+      auto& cs = CS[j];
       cs.E = r.E;
       cs.noise = r.noise;
       cs.resid = r.resid;
@@ -1037,7 +1037,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
                  A.stage_k);                                              // r = H~^-1 q
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
-      CellState& cs = CS[j];
+      auto& cs = CS[j];
       if (!cs.active) continue;                                  // uniform: read after a barrier
       const int cell = A.tile_cells[td.first + j];
       Real* U = tl.vec(VU, j);
@@ -1339,7 +1339,7 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
     vcopy(ut, tl.vec(VU, j), len);
     __syncthreads();
     double bc[1] = {s_vol[j]};
-    CellState cs = CS[j];
+    auto cs = CS[j];
     finalize_cell(A, M, cell, cs, xn, ut, red, bc);
     __syncthreads();
   }
@@ -1348,14 +1348,16 @@ __device__ void run_tile(const StepArgs<Real>& A, int tile, Real* W, CellState* 
 #ifndef NPFEM_STEP_WAVES_PER_SIMD
 #define NPFEM_STEP_WAVES_PER_SIMD 2
 #endif
-// H: compile-time bound on the L-BFGS history (the loops over pairs are unrolled to H)
-template <typename Real, int H>
+// H: compile-time bound on the L-BFGS history (the loops over pairs are unrolled to H);
+// CSL: the tile's cell states live in LDS at byte offset A.cs_lds (else in the workspace).
+template <typename Real, int H, bool CSL>
 __global__ void __launch_bounds__(kBlock, NPFEM_STEP_WAVES_PER_SIMD) step_kernel(StepArgs<Real> A) {
   extern __shared__ __align__(16) unsigned char lds[];
   double* red = reinterpret_cast<double*>(lds);
   int* sint = reinterpret_cast<int*>(lds + kRedDoubles * 8 + 32 * 8);
   Real* W = A.work + (size_t)blockIdx.x * A.slot_stride;
-  CellState* CS = A.cstate + (size_t)blockIdx.x * A.tile_cells_max;
+  CellStateT<H>* CS = CSL ? reinterpret_cast<CellStateT<H>*>(lds + A.cs_lds)
+                          : reinterpret_cast<CellStateT<H>*>(A.cstate) + (size_t)blockIdx.x * A.tile_cells_max;
   for (;;) {
     if (tid() == 0) sint[0] = atomicAdd(A.tile_counter, 1);
     __syncthreads();
@@ -1474,9 +1476,12 @@ size_t lds_bytes(int n_pad, int chunk, int stage_rows, int vec_lds) {
 
 template <typename Real>
 hipError_t set_lds_limit(size_t bytes) {
-  const void* fns[] = {reinterpret_cast<const void*>(&step_kernel<Real, 2>),
-                       reinterpret_cast<const void*>(&step_kernel<Real, 5>),
-                       reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory>),
+  const void* fns[] = {reinterpret_cast<const void*>(&step_kernel<Real, 2, false>),
+                       reinterpret_cast<const void*>(&step_kernel<Real, 5, false>),
+                       reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, false>),
+                       reinterpret_cast<const void*>(&step_kernel<Real, 2, true>),
+                       reinterpret_cast<const void*>(&step_kernel<Real, 5, true>),
+                       reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, true>),
                        reinterpret_cast<const void*>(&eval_kernel<Real>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -1487,19 +1492,24 @@ hipError_t set_lds_limit(size_t bytes) {
 
 template <typename Real>
 hipError_t occupancy(int* blocks_per_cu, size_t lds) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<Real, kMaxHistory>, kBlock, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<Real, kMaxHistory, false>, kBlock, lds);
 }
 
 template <typename Real>
 hipError_t launch_step(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s, int* counter) {
   (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
-  if (a.sol.m <= 2)
-    hipLaunchKernelGGL((step_kernel<Real, 2>), dim3(grid), dim3(kBlock), lds, s, a);
-  else if (a.sol.m <= 5)
-    hipLaunchKernelGGL((step_kernel<Real, 5>), dim3(grid), dim3(kBlock), lds, s, a);
-  else
-    hipLaunchKernelGGL((step_kernel<Real, kMaxHistory>), dim3(grid), dim3(kBlock), lds, s, a);
+  const bool csl = a.cs_lds >= 0;
+  if (a.sol.m <= 2) {
+    if (csl) hipLaunchKernelGGL((step_kernel<Real, 2, true>), dim3(grid), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((step_kernel<Real, 2, false>), dim3(grid), dim3(kBlock), lds, s, a);
+  } else if (a.sol.m <= 5) {
+    if (csl) hipLaunchKernelGGL((step_kernel<Real, 5, true>), dim3(grid), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((step_kernel<Real, 5, false>), dim3(grid), dim3(kBlock), lds, s, a);
+  } else {
+    if (csl) hipLaunchKernelGGL((step_kernel<Real, kMaxHistory, true>), dim3(grid), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((step_kernel<Real, kMaxHistory, false>), dim3(grid), dim3(kBlock), lds, s, a);
+  }
   return hipGetLastError();
 }
 
