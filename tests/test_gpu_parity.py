@@ -199,6 +199,27 @@ def test_step_tile_size_and_repeat_bitwise():
             np.testing.assert_array_equal(st["iterations"], ref[2])
 
 
+@pytest.mark.parametrize("lbfgs_m", [2, 8])
+def test_cell_state_placement_is_bitwise_neutral(lbfgs_m):
+    """A tile's per-cell L-BFGS state lives in LDS when that costs no workgroups per CU
+    and in the workspace otherwise; at the 642-vertex mesh one tile (LDS) and 5 or 16
+    cells per tile (the workspace, for history 8 or 2) must give identical bits."""
+    b = workloads.shear(n_cells=23, seed=6)
+    X, Tr = b.meshes[642]
+    x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
+    f = rounded(workloads.drag_forces(b, x, v), "fp32")
+    ref = None
+    for tcells in (1, 5, 16):
+        plan = make([(X, Tr)], "fp32", cells_per_tile=tcells, lbfgs_m=lbfgs_m)
+        xo, vo, st, _ = run_step(plan, np.zeros(23, np.int32), x, v, f)
+        if ref is None:
+            ref = (xo, vo, st["iterations"])
+        else:
+            np.testing.assert_array_equal(xo, ref[0])
+            np.testing.assert_array_equal(vo, ref[1])
+            np.testing.assert_array_equal(st["iterations"], ref[2])
+
+
 def test_step_fp64_stretch_trajectory():
     """The optical-tweezers load on one 258-vertex cell, FP64, ramped to 200 pN over
     20 steps; each side follows its own trajectory; positions within 1e-10 D."""
