@@ -21,6 +21,10 @@ using namespace npfem;
 
 namespace {
 
+// LDS a step workgroup may use (the CU's 160 KB less the kernel's static arrays and a
+// margin).
+constexpr size_t kStepLdsCap = 160 * 1024 - 1024;
+
 thread_local std::string g_err;
 
 npfem_status fail(npfem_status s, const std::string& msg) {
@@ -544,7 +548,7 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
   p->cu_count = prop.multiProcessorCount;
   const double h = dt, kmat = mat->k_mat < 0 ? mat->B : mat->k_mat;
   const bool fp64 = prm->precision == NPFEM_FP64;
-  const size_t lds_cap = 160 * 1024 - 1024;
+  const size_t lds_cap = kStepLdsCap;
   p->meshes.resize(n_meshes);
   for (int mi = 0; mi < n_meshes; ++mi) {
     const npfem_mesh* m = meshes[mi];
@@ -751,16 +755,21 @@ npfem_status batch_schedule(npfem_batch* b, int T, int m) {
       lds = std::max(lds, lds_bytes<Real>(p->meshes[mi].n_pad, p->meshes[mi].chunk, stage_rows,
                                           p->meshes[mi].vec_lds));
   b->stage_k = stage_cols(lds, stage_rows, b->n_pad_max);   // the staging stays below the cell states
-  // the tile's cell states go to LDS (after everything else) when that costs no
-  // workgroups per CU
+  // the tile's cell states go to LDS (after everything else) when they fit the LDS a
+  // workgroup may have and cost no workgroups per CU
   {
     const size_t base = (lds + 15) / 16 * 16, with_cs = base + (size_t)T * cell_state_bytes(m);
-    HIP_TRY(set_lds_limit<Real>(with_cs));
-    int per_base = 0, per_cs = 0;
-    HIP_TRY(occupancy<Real>(&per_base, lds));
-    HIP_TRY(occupancy<Real>(&per_cs, with_cs));
-    b->cs_lds = (per_cs >= per_base && per_cs > 0 && with_cs < ((size_t)1 << 31)) ? (int)base : -1;
-    if (b->cs_lds >= 0) lds = with_cs;
+    b->cs_lds = -1;
+    if (with_cs <= kStepLdsCap) {
+      HIP_TRY(set_lds_limit<Real>(with_cs));
+      int per_base = 0, per_cs = 0;
+      HIP_TRY(occupancy<Real>(&per_base, lds));
+      HIP_TRY(occupancy<Real>(&per_cs, with_cs));
+      if (per_cs >= per_base && per_cs > 0) {
+        b->cs_lds = (int)base;
+        lds = with_cs;
+      }
+    }
   }
   b->lds = lds;
   HIP_TRY(set_lds_limit<Real>(lds));

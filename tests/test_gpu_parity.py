@@ -220,6 +220,27 @@ def test_cell_state_placement_is_bitwise_neutral(lbfgs_m):
             np.testing.assert_array_equal(st["iterations"], ref[2])
 
 
+def test_large_mesh_tiles_build_and_agree():
+    """2562-vertex cells use nearly all of a CU's LDS, so the cell states must fall back
+    to the workspace where they do not fit (a batch of 16-cell tiles used to fail to
+    build); 1- and 16-cell tiles converge and agree bit for bit."""
+    from paper_1903_06479_amd import CONVERGED
+    b = workloads.shear(n_cells=16, n_verts=2562, seed=7)
+    X, Tr = b.meshes[2562]
+    x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
+    f = rounded(workloads.drag_forces(b, x, v), "fp32")
+    ref = None
+    for tcells in (16, 1):
+        plan = make([(X, Tr)], "fp32", cells_per_tile=tcells, lbfgs_m=2)
+        xo, vo, st, _ = run_step(plan, np.zeros(16, np.int32), x, v, f)
+        assert np.all(st["status"] & CONVERGED), st["status"]
+        if ref is None:
+            ref = (xo, vo)
+        else:
+            np.testing.assert_array_equal(xo, ref[0])
+            np.testing.assert_array_equal(vo, ref[1])
+
+
 def test_step_fp64_stretch_trajectory():
     """The optical-tweezers load on one 258-vertex cell, FP64, ramped to 200 pN over
     20 steps; each side follows its own trajectory; positions within 1e-10 D."""
