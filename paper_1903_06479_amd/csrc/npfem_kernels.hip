@@ -354,15 +354,30 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
   for (int i = tid(); i < n; i += kBlock) {
     Real gx = 0, gy = 0, gz = 0;
     const Real rix = work[i], riy = work[np + i], riz = work[2 * np + i];
-#pragma unroll 6
-    for (int q = 0; q < M.nb_deg; ++q) {
-      const int j = gld(M.nb_ell, q * np + i);
-      const Real w = gld(M.nbw_ell, q * np + i);
-      gx += w * (work[j] - rix);
-      gy += w * (work[np + j] - riy);
-      gz += w * (work[2 * np + j] - riz);
+    Real mass = 0;
+    for (int q0 = 0; q0 < M.nb_deg; q0 += kEllGroup) {
+      // as in pass A: the group's neighbours and weights (and the mass) are requested
+      // before the first is used
+      int jj[kEllGroup];
+      Real ww[kEllGroup];
+#pragma unroll
+      for (int u = 0; u < kEllGroup; ++u) {
+        const bool in = q0 + u < M.nb_deg;
+        jj[u] = in ? gld(M.nb_ell, (q0 + u) * np + i) : i;
+        ww[u] = in ? gld(M.nbw_ell, (q0 + u) * np + i) : Real(0);
+      }
+      if (q0 == 0) mass = gld(M.mass, i);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kEllGroup; ++u) {
+        const int j = jj[u];
+        const Real w = ww[u];
+        gx += w * (work[j] - rix);
+        gy += w * (work[np + j] - riy);
+        gz += w * (work[2 * np + j] - riz);
+      }
     }
-    const Real mi = gld(M.mass, i) * inv_h2;
+    const Real mi = mass * inv_h2;
     const Real ux = ut[i], uy = ut[np + i], uz = ut[2 * np + i];
     const Real bx = bvec[i], by = bvec[np + i], bz = bvec[2 * np + i];
     gout[i] = kb * gx + (mi * ux - bx);
@@ -381,20 +396,31 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     const int tn = min(ch, nt - t0);
     for (int tt = tid(); tt < tn; tt += kBlock) {
       const int t = t0 + tt;
+      // The triangle's table entries are all requested before the first is used, then
+      // its corners' coordinates from LDS; scheduling barriers keep each group together.
       const int a = gld(M.tri, 3 * t), b = gld(M.tri, 3 * t + 1), c = gld(M.tri, 3 * t + 2);
       const double D00 = gld(M.dminv, 4 * t), D01 = gld(M.dminv, 4 * t + 1), D10 = gld(M.dminv, 4 * t + 2), D11 = gld(M.dminv, 4 * t + 3);
+      const double area_t = gld(M.area, t), i4a2_t = gld(M.inv4a2, t);
+      __builtin_amdgcn_sched_barrier(0);
+      const Real xa = xn[a], ya = xn[np + a], za = xn[2 * np + a];
+      const Real xb = xn[b], yb = xn[np + b], zb = xn[2 * np + b];
+      const Real xc = xn[c], yc = xn[np + c], zc = xn[2 * np + c];
+      const Real uax = ut[a], uay = ut[np + a], uaz = ut[2 * np + a];
+      const Real ubx = ut[b], uby = ut[np + b], ubz = ut[2 * np + b];
+      const Real ucx = ut[c], ucy = ut[np + c], ucz = ut[2 * np + c];
+      __builtin_amdgcn_sched_barrier(0);
       const Real d00 = Real(D00), d01 = Real(D01), d10 = Real(D10), d11 = Real(D11);
-      const Real A0 = Real(gld(M.area, t));
+      const Real A0 = Real(area_t);
       // The strain measures (sigma - 1, area ratio - 1) are small differences of O(1)
       // quantities, so the edges, F = [e1 e2] D_m^-1, F^T F and |e1 x e2|^2 are formed
       // in FP64 from the stored values (exact differences); everything after that works
       // on the small differences and keeps its relative precision in FP32.
-      const double E1x = ((double)xn[a] - (double)xn[c]) + ((double)ut[a] - (double)ut[c]);
-      const double E1y = ((double)xn[np + a] - (double)xn[np + c]) + ((double)ut[np + a] - (double)ut[np + c]);
-      const double E1z = ((double)xn[2 * np + a] - (double)xn[2 * np + c]) + ((double)ut[2 * np + a] - (double)ut[2 * np + c]);
-      const double E2x = ((double)xn[b] - (double)xn[c]) + ((double)ut[b] - (double)ut[c]);
-      const double E2y = ((double)xn[np + b] - (double)xn[np + c]) + ((double)ut[np + b] - (double)ut[np + c]);
-      const double E2z = ((double)xn[2 * np + b] - (double)xn[2 * np + c]) + ((double)ut[2 * np + b] - (double)ut[2 * np + c]);
+      const double E1x = ((double)xa - (double)xc) + ((double)uax - (double)ucx);
+      const double E1y = ((double)ya - (double)yc) + ((double)uay - (double)ucy);
+      const double E1z = ((double)za - (double)zc) + ((double)uaz - (double)ucz);
+      const double E2x = ((double)xb - (double)xc) + ((double)ubx - (double)ucx);
+      const double E2y = ((double)yb - (double)yc) + ((double)uby - (double)ucy);
+      const double E2z = ((double)zb - (double)zc) + ((double)ubz - (double)ucz);
       const double F0x = E1x * D00 + E2x * D10, F0y = E1y * D00 + E2y * D10, F0z = E1z * D00 + E2z * D10;
       const double F1x = E1x * D01 + E2x * D11, F1y = E1y * D01 + E2y * D11, F1z = E1z * D01 + E2z * D11;
       const double C00 = F0x * F0x + F0y * F0y + F0z * F0z;
@@ -403,8 +429,8 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       const double Nx = E1y * E2z - E1z * E2y, Ny = E1z * E2x - E1x * E2z, Nz = E1x * E2y - E1y * E2x;
       const double NN = Nx * Nx + Ny * Ny + Nz * Nz;
       // displacement part of F for the Rayleigh term
-      const Real eu1x = ut[a] - ut[c], eu1y = ut[np + a] - ut[np + c], eu1z = ut[2 * np + a] - ut[2 * np + c];
-      const Real eu2x = ut[b] - ut[c], eu2y = ut[np + b] - ut[np + c], eu2z = ut[2 * np + b] - ut[2 * np + c];
+      const Real eu1x = uax - ucx, eu1y = uay - ucy, eu1z = uaz - ucz;
+      const Real eu2x = ubx - ucx, eu2y = uby - ucy, eu2z = ubz - ucz;
       const Real f0x = Real(F0x), f0y = Real(F0y), f0z = Real(F0z);
       const Real f1x = Real(F1x), f1y = Real(F1y), f1z = Real(F1z);
       const Real g0x = eu1x * d00 + eu2x * d10, g0y = eu1y * d00 + eu2y * d10, g0z = eu1z * d00 + eu2z * d10;
@@ -413,7 +439,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       const Real nx = Real(Nx), ny = Real(Ny), nz = Real(Nz);
       const Real nn = sqrt_(Real(NN));
       // area ratio J = sigma1 sigma2 = |e1 x e2| / (2 A0)
-      const Real Jsq_m1 = Real(NN * gld(M.inv4a2, t) - 1.0);
+      const Real Jsq_m1 = Real(NN * i4a2_t - 1.0);
       const Real J = sqrt_(fmax(Real(1) + Jsq_m1, Real(0)));
       const Real Jm1 = Jsq_m1 * rcp_(J + Real(1));
       const Real half = Real(0.5 * (C00 - C11));
@@ -470,8 +496,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       work[8 * ch + tt] = nz;
       if (single) {
         // x_a . (x_b x x_c) = E1 . (E2 x x_c) with E1 = x_a - x_c, E2 = x_b - x_c (FP64)
-        const double cx = (double)xn[c] + (double)ut[c], cy = (double)xn[np + c] + (double)ut[np + c],
-                     cz = (double)xn[2 * np + c] + (double)ut[2 * np + c];
+        const double cx = (double)xc + (double)ucx, cy = (double)yc + (double)ucy, cz = (double)zc + (double)ucz;
         accC[4] += E1x * (E2y * cz - E2z * cy) + E1y * (E2z * cx - E2x * cz) + E1z * (E2x * cy - E2y * cx);
       }
       accC[0] += 0.5 * (double)(Cst * A0) * ((double)dA1 * dA1 + (double)dA2 * dA2);
@@ -496,10 +521,12 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       // entry, or a corner outside this chunk, reads the chunk's first triangle and adds
       // zero; corner k adds g_a, g_b or -(g_a + g_b) (the same roundings as adding each
       // case on its own).
+      Real mass = 0;
       for (int q0 = 0; q0 < M.vc_deg; q0 += kEllGroup) {
         int cc[kEllGroup];
 #pragma unroll
         for (int u = 0; u < kEllGroup; ++u) cc[u] = q0 + u < M.vc_deg ? gld(M.vc_ell, (q0 + u) * np + i) : -1;
+        if (q0 == 0 && last) mass = gld(M.mass, i);      // with the first group
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < kEllGroup; ++u) {
@@ -529,7 +556,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       gout[np + i] = gy;
       gout[2 * np + i] = gz;
       if (last) {
-        const Real mi = gld(M.mass, i) * inv_h2;
+        const Real mi = mass * inv_h2;
         const Real ux = ut[i], uy = ut[np + i], uz = ut[2 * np + i];
         const Real bx = bvec[i], by = bvec[np + i], bz = bvec[2 * np + i];
         const double mux = (double)mi * ux, muy = (double)mi * uy, muz = (double)mi * uz;
