@@ -848,10 +848,9 @@ struct Tile {
 };
 
 template <typename Real, typename CST>
-__device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, int cell, CST& cs,
+__device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, int cell, int64_t voff, CST& cs,
                               const Real* xn, const Real* U, double* red, double* bc) {
   const int n = M.n, np = M.n_pad;
-  const int64_t voff = A.cell_voff[cell];
   const double h = A.sol.h;
   Real* xo = A.x_out + 3 * voff;
   Real* vo = A.v_out + 3 * voff;
@@ -941,10 +940,20 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
                          int* sint, unsigned char* lds) {
   const TileDesc td = A.tiles[tile];
   MeshDev<Real>* Ml = reinterpret_cast<MeshDev<Real>*>(lds + kLdsMesh);
+  // the tile's cells and their vertex offsets, looked up once per tile
+  __shared__ int s_cell[kMaxTile];
+  __shared__ int64_t s_voff[kMaxTile];
   {
     constexpr int nw = sizeof(MeshDev<Real>) / 4;
+    static_assert(nw <= 128, "mesh descriptor copy");
     const int* src = reinterpret_cast<const int*>(A.meshes + td.mesh);
     if (tid() < nw) reinterpret_cast<int*>(Ml)[tid()] = src[tid()];
+    const int jt = tid() - 128;
+    if (jt >= 0 && jt < td.count) {
+      const int c = A.tile_cells[td.first + jt];
+      s_cell[jt] = c;
+      s_voff[jt] = A.cell_voff[c];
+    }
     __syncthreads();
   }
   const MeshDev<Real>& M = *Ml;
@@ -966,8 +975,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
 
   // ---- initial state: b = M v_n / h + F_ext, |grad V(x_n)|^2, first guess --------
   for (int j = 0; j < cnt; ++j) {
-    const int cell = A.tile_cells[td.first + j];
-    const int64_t voff = A.cell_voff[cell];
+    const int64_t voff = s_voff[j];
     stage_aos(xn, A.x + 3 * voff, n, np);
     const Real* vs = A.v + 3 * voff;
     const Real* fs = A.f + 3 * voff;
@@ -992,7 +1000,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
     __syncthreads();
     if (A.guess_only || A.u_delta) {
       for (int j = 0; j < cnt; ++j) {
-        const int64_t voff = A.cell_voff[A.tile_cells[td.first + j]];
+        const int64_t voff = s_voff[j];
         Real* U = tl.vec(VU, j);
         for (int e = tid(); e < len; e += kBlock) {
           const int c = e / np, i = e - c * np;
@@ -1009,8 +1017,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
 
   // ---- first evaluation ---------------------------------------------------------
   for (int j = 0; j < cnt; ++j) {
-    const int cell = A.tile_cells[td.first + j];
-    stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
+    stage_aos(xn, A.x + 3 * s_voff[j], n, np);
     vcopy(ut, tl.vec(VU, j), len);
     if (vl) vcopy(bl, tl.vec(VB, j), len);
     __syncthreads();
@@ -1066,7 +1073,6 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
     for (int j = 0; j < cnt; ++j) {
       auto& cs = CS[j];
       if (!cs.active) continue;                                  // uniform: read after a barrier
-      const int cell = A.tile_cells[td.first + j];
       Real* U = tl.vec(VU, j);
       Real* G = tl.vec(VG, j);
       Real* GT = gvec(j);                                        // trial gradient
@@ -1095,7 +1101,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
           }
         }
       }
-      stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
+      stage_aos(xn, A.x + 3 * s_voff[j], n, np);
       if (vl) vcopy(bl, tl.vec(VB, j), len);
       // second half: y_p . r for every stored pair (one pass)
       double yr[H];
@@ -1361,13 +1367,12 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
 
   // ---- velocity update and dissipation --------------------------------------------
   for (int j = 0; j < cnt; ++j) {
-    const int cell = A.tile_cells[td.first + j];
-    stage_aos(xn, A.x + 3 * A.cell_voff[cell], n, np);
+    stage_aos(xn, A.x + 3 * s_voff[j], n, np);
     vcopy(ut, tl.vec(VU, j), len);
     __syncthreads();
     double bc[1] = {s_vol[j]};
     auto cs = CS[j];
-    finalize_cell(A, M, cell, cs, xn, ut, red, bc);
+    finalize_cell(A, M, s_cell[j], s_voff[j], cs, xn, ut, red, bc);
     __syncthreads();
   }
 }
