@@ -32,7 +32,7 @@ template <typename Real> struct Eps;
 template <> struct Eps<float> { static constexpr double v = 1.1920928955078125e-07; };
 template <> struct Eps<double> { static constexpr double v = 2.220446049250313e-16; };
 
-// LDS: [red: 4 waves x 32 doubles][32 doubles][ints: 32][mesh descriptor][cell vectors ...];
+// LDS: [red: 4 waves x 32 doubles][32 doubles, spare][ints: 32][mesh descriptor][cell vectors ...];
 // during the BF16 tile product the region from the cell vectors on holds the tile's rows
 // in BF16.  The current tile's mesh descriptor is copied to LDS so that reading its table
 // pointers waits on the LDS counter only, never on global loads in flight.
@@ -40,7 +40,7 @@ constexpr int kRedStride = 32;
 constexpr int kRedDoubles = 4 * kRedStride;
 constexpr int kMeshLds = 256;
 constexpr int kLdsMesh = kRedDoubles * 8 + 32 * 8 + 32 * 4;
-constexpr int kLdsHeader = kLdsMesh + kMeshLds;   // reduction, picked sums, ints, mesh
+constexpr int kLdsHeader = kLdsMesh + kMeshLds;   // reduction, 32 spare doubles, ints, mesh
 static_assert(sizeof(MeshDev<double>) <= kMeshLds && sizeof(MeshDev<float>) <= kMeshLds, "mesh descriptor");
 static_assert(sizeof(MeshDev<double>) % 4 == 0 && sizeof(MeshDev<float>) % 4 == 0, "mesh descriptor");
 
@@ -1276,15 +1276,15 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
         }
       }
       block_sum<4 + 3 * H>(acc, red);
-      // the reduced dot products go to LDS so they can be picked by pair index below
-      double* s_acc = red + kRedDoubles;                         // 32 doubles after the reduction buffer
-      if (tid() < 4 + 3 * H) {
+      // the reduced dot products (the same in every lane) picked by pair index o < H
+      auto pick = [&](int base, int o) {
+        double v = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4 + 3 * H; ++k)
-          if (k == tid()) s_acc[k] = acc[k];
-      }
-      __syncthreads();
-      const bool store = m > 0 && s_acc[0] > 1e-12 * sqrt(s_acc[1] * s_acc[2]);
+        for (int k = 0; k < H; ++k)
+          if (k == o) v = acc[base + k];
+        return v;
+      };
+      const bool store = m > 0 && acc[0] > 1e-12 * sqrt(acc[1] * acc[2]);
       // new history (p = 0 oldest): the kept old pairs (old index p + first_kept), then the
       // new pair in slot ns if it is stored
       const int first_kept = full ? 1 : 0;
@@ -1301,13 +1301,13 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
         al_new[p] = 0.0;
         if (p < hn2) {
           const bool isnew = p >= n_kept;
-          const double rho = isnew ? 1.0 / s_acc[0] : cs.rho[slot2(p)];
-          double sg = isnew ? s_acc[3] : s_acc[4 + p + first_kept];
+          const double rho = isnew ? 1.0 / acc[0] : cs.rho[slot2(p)];
+          double sg = isnew ? acc[3] : pick(4, p + first_kept);
 #pragma unroll
           for (int q = H - 1; q >= 0; --q) {
             if (q > p && q < hn2) {
               // SY[slot p][slot q] = s_p . y_q; the new pair is the newest, so p is old here
-              const double syq = q >= n_kept ? s_acc[4 + 2 * H + p + first_kept]   // s_p . y_new
+              const double syq = q >= n_kept ? pick(4 + 2 * H, p + first_kept)   // s_p . y_new
                                              : cs.SY[slot2(p)][slot2(q)];
               sg -= al_new[q] * syq;
             }
@@ -1318,12 +1318,12 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
       __syncthreads();
       if (tid() == 0) {
         if (store) {
-          cs.rho[ns] = 1.0 / s_acc[0];
-          cs.SY[ns][ns] = s_acc[0];
+          cs.rho[ns] = 1.0 / acc[0];
+          cs.SY[ns][ns] = acc[0];
           for (int p = 0; p < n_kept; ++p) {
             const int sp = slot2(p), o = p + first_kept;
-            cs.SY[ns][sp] = s_acc[4 + H + o];       // s_new . y_p
-            cs.SY[sp][ns] = s_acc[4 + 2 * H + o];   // s_p . y_new
+            cs.SY[ns][sp] = pick(4 + H, o);         // s_new . y_p
+            cs.SY[sp][ns] = pick(4 + 2 * H, o);     // s_p . y_new
           }
         }
 #pragma unroll
