@@ -33,7 +33,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-VALU_FP32_PEAK_TFLOPS = 157.3  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+# FP32 vector peak without packed instructions (the library is built with packed FP32
+# disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s; the
+# published 157.3 TFLOP/s counts packed FP32.
+VALU_FP32_PEAK_TFLOPS = 78.6
 N_CU = 256
 
 # Algorithmic arithmetic of one objective + gradient evaluation, counted operation by
@@ -99,30 +102,71 @@ def make_inputs(n_cells: int):
     return b
 
 
-def cpu_baseline(b, n_sample: int, tol: float):
-    """The FP64 oracle, as it stands, on the first n_sample cells for one step."""
+def _cpu_worker(args):
+    """One host process of the CPU baseline: oracle steps of its share of the sampled
+    cells (first step of the throughput workload) until the deadline."""
+    cells, tol, deadline_s = args
     from threadpoolctl import threadpool_limits
     from rbc_inputs import workloads
     import oracle.model as om
     import oracle.step as ostep
-    X, T = b.meshes[642]
-    model = om.Model(X, T, om.Material(), workloads.DT_US)
-    sl = slice(0, int(b.offsets[n_sample]))
-    f = workloads.drag_forces(b, b.x, b.v)
     with threadpool_limits(limits=1):
+        sub = workloads.throughput(n_cells=100000, cells=cells)
+        X, T = sub.meshes[642]
+        model = om.Model(X, T, om.Material(), workloads.DT_US)
         model.solve_Ht(np.zeros((642, 3)))
         model.solve_Mt(np.zeros((642, 3)))
+        f = workloads.drag_forces(sub, sub.x, sub.v)
         t0 = time.perf_counter()
-        iters = []
-        for c in range(n_sample):
-            s = b.cell_slice(c)
-            _, _, info = ostep.step(model, b.x[s], b.v[s], f[s], ostep.Params(tol=tol))
-            iters.append(info.iterations)
-        dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sample} cells of the 100,000-cell throughput workload, first step, "
-                      f"FP64 NumPy/SciPy oracle, residual <= {tol:g}, one thread "
-                      f"({dt:.1f}s, mean {np.mean(iters):.1f} iterations)"}
+        done, iters = 0, 0
+        for c in range(sub.n_cells):
+            s = sub.cell_slice(c)
+            _, _, info = ostep.step(model, sub.x[s], sub.v[s], f[s], ostep.Params(tol=tol))
+            done += 1
+            iters += info.iterations
+            if time.perf_counter() - t0 >= deadline_s:
+                break
+        return done, iters, time.perf_counter() - t0
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline(tol: float, seconds: float, max_workers: int = 16):
+    """The FP64 oracle as it stands, one process per usable host core (at most
+    max_workers), each stepping its own cells of the throughput workload's first step
+    for about `seconds`; cells are independent, so the rate is the sum over processes.
+    Runs before the GPU is initialised (the worker processes never touch it)."""
+    import multiprocessing as mp
+    model, n_cpu, usable = host_cpu()
+    workers = max(1, min(usable, max_workers))
+    per = 4000                                    # more cells than any worker finishes
+    jobs = [(np.arange(w, workers * per, workers), tol, seconds) for w in range(workers)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_cpu_worker, jobs)
+    wall = time.perf_counter() - t0
+    done = sum(r[0] for r in res)
+    rate = sum(r[0] / r[2] for r in res)
+    iters = sum(r[1] for r in res) / max(done, 1)
+    return {"value": rate, "unit": "cell-steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"{done} cells of the 100,000-cell throughput workload's first step, FP64 NumPy/SciPy "
+                      f"oracle (residual <= {tol:g}, mean {iters:.1f} iterations), one single-threaded process "
+                      f"per core for about {seconds:.0f} s each ({wall:.1f} s wall); host: {model}, "
+                      f"{n_cpu} logical CPUs, {usable} usable"}
 
 
 # ---------------------------------------------------------------------------------
@@ -211,7 +255,8 @@ def config_c2(args):
     x, v = x0.clone(), v0.clone()
     xo_, vo_ = torch.empty_like(x), torch.empty_like(v)
     f = torch.empty_like(x)
-    stats = [torch.empty(b.n_cells * 40, dtype=torch.uint8, device=dev) for _ in range(args.steps)]
+    from paper_1903_06479_amd import CELL_STATS_DTYPE
+    stats = [torch.empty(b.n_cells * CELL_STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -297,6 +342,23 @@ def config_c3(args):
             "schedule": b32.schedule()}
 
 
+def oracle_error(b, cells, xin, vin, fin, xout):
+    """max |x - x_oracle| / D over the sampled cells: the oracle's stationary point (FP64,
+    residual 1e-12) from the same (FP32) inputs the GPU step read."""
+    from rbc_inputs import workloads
+    import oracle.model as om
+    import oracle.step as ostep
+    X, T = b.meshes[642]
+    model = om.Model(X, T, om.Material(), workloads.DT_US)
+    D = float(np.ptp(X[:, 0]))
+    err = 0.0
+    for c in cells:
+        sl = b.cell_slice(int(c))
+        xr, _, _ = ostep.step(model, xin[sl], vin[sl], fin[sl], ostep.Params(tol=1e-12, polish=True))
+        err = max(err, float(np.abs(xout[sl] - xr).max() / D))
+    return err
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,15 +379,16 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1903_06479_amd", "data", "warmstart_642.npy"),
                     help="trained warm-start network (FP32 parameters); empty string: plain form only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=320)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline time per host process")
+    ap.add_argument("--oracle-cells", type=int, default=3, help="sampled cells checked against the oracle")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the cells are independent, "
               "so a multi-GPU run would shard them without any per-step exchange", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     if args.copy_check:
+        import torch
         a = torch.ones(args.copy_check // 4, dtype=torch.float32, device="cuda:0")
         c = torch.empty_like(a)
         for _ in range(5):
@@ -339,12 +402,24 @@ def main():
             args.steps = 100
         print(json.dumps(cfg(args)), flush=True)
         return
-    from rbc_inputs import workloads
-    from paper_1903_06479_amd import Batch, Mesh, Plan, default_params, CONVERGED
 
     b = make_inputs(args.cells)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the host processes are forked before anything initialises the GPU
+        t0 = time.time()
+        cpu = cpu_baseline(args.tol, args.cpu_seconds)
+        log(f"[bench] cpu baseline {time.time() - t0:.1f}s -> {cpu['value']:.1f} cell-steps/s on {cpu['cores']} cores")
+
+    import torch
+    from rbc_inputs import workloads
+    from paper_1903_06479_amd import Batch, Mesh, Plan, StatsTotal, default_params, CELL_STATS_DTYPE
+
     X, T = b.meshes[642]
     dev = torch.device("cuda:0")
+    # a stream of the default priority: the step is captured into a HIP graph on it (the
+    # NULL stream cannot be captured) and replayed on every later step
+    stream = torch.cuda.Stream(device=dev)
     params = default_params(tol=args.tol, cells_per_tile=args.cells_per_tile,
                             inverse_bf16=0 if args.fp32_products else 1)
     t0 = time.time()
@@ -352,70 +427,119 @@ def main():
     plan = Plan([mesh], workloads.DT_US, params=params)
     batch = Batch(plan, np.zeros(b.n_cells, np.int32))
     log(f"[bench] plan + batch in {time.time() - t0:.1f}s")
-    x0 = torch.tensor(b.x, dtype=torch.float32, device=dev)
-    v0 = torch.zeros_like(x0)
-    zeta = torch.full((b.n_cells,), workloads.drag_coefficient(642), dtype=torch.float64, device=dev)
-    rate = torch.tensor(b.shear_rate, dtype=torch.float64, device=dev)
-    origin = torch.tensor(b.origin, dtype=torch.float64, device=dev)
-    p = b.poiseuille
-    x, v, f = x0.clone(), v0.clone(), torch.empty_like(x0)
-    tuned = None
-    if not args.no_autotune:
-        batch.drag_forces(x, v, zeta, rate, origin, p["umax"], p["radius"], p["axis_y"], p["axis_z"], out=f)
-        t0 = time.time()
-        tuned = batch.autotune(x, v, f, max_lbfgs_m=5)
-        log(f"[bench] autotune {time.time() - t0:.1f}s -> {tuned}")
-    elif args.cells_per_tile or args.lbfgs_m:
-        batch.schedule(cells_per_tile=args.cells_per_tile or None, lbfgs_m=args.lbfgs_m or None)
-    if not args.no_graph:
-        batch.set_graph(True)
-    xo, vo = torch.empty_like(x0), torch.empty_like(x0)
-    st = torch.empty(b.n_cells * 40, dtype=torch.uint8, device=dev)
+    with torch.cuda.stream(stream):
+        x0 = torch.tensor(b.x, dtype=torch.float32, device=dev)
+        v0 = torch.zeros_like(x0)
+        zeta = torch.full((b.n_cells,), workloads.drag_coefficient(642), dtype=torch.float64, device=dev)
+        rate = torch.tensor(b.shear_rate, dtype=torch.float64, device=dev)
+        origin = torch.tensor(b.origin, dtype=torch.float64, device=dev)
+        p = b.poiseuille
+        x, v, f = x0.clone(), v0.clone(), torch.empty_like(x0)
+        tuned = None
+        if not args.no_autotune:
+            batch.drag_forces(x, v, zeta, rate, origin, p["umax"], p["radius"], p["axis_y"], p["axis_z"], out=f)
+            t0 = time.time()
+            tuned = batch.autotune(x, v, f, max_lbfgs_m=5)
+            log(f"[bench] autotune {time.time() - t0:.1f}s -> {tuned}")
+        elif args.cells_per_tile or args.lbfgs_m:
+            batch.schedule(cells_per_tile=args.cells_per_tile or None, lbfgs_m=args.lbfgs_m or None)
+        if not args.no_graph:
+            batch.set_graph(True)
+        xo, vo = torch.empty_like(x0), torch.empty_like(x0)
+        st = torch.empty(b.n_cells * CELL_STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
     sched = batch.schedule()
 
     def run_form(form, net=None):
         """Warm-up, reset, then K timed steps of one form; HIP events around each step call
-        (on the stream the kernels run on)."""
+        on the stream the kernels run on.  The per-cell statistics of every timed step are
+        accumulated on the GPU (outside the events) and read after the timed region."""
         nonlocal x, v, xo, vo
+        total = StatsTotal(dev, stream=stream)
 
         def one_step(ev=None):
             nonlocal x, v, xo, vo
             batch.drag_forces(x, v, zeta, rate, origin, p["umax"], p["radius"], p["axis_y"], p["axis_z"], out=f)
             if ev is not None:
-                ev[0].record()
+                ev[0].record(stream)
             if net is None:
-                batch.step(x, v, f, x_out=xo, v_out=vo, stats=st)
+                batch.step(x, v, f, x_out=xo, v_out=vo, stats=st, stream=stream)
             else:
-                batch.step_learned(net, x, v, f, x_out=xo, v_out=vo, stats=st)
+                batch.step_learned(net, x, v, f, x_out=xo, v_out=vo, stats=st, stream=stream)
             if ev is not None:
-                ev[1].record()
+                ev[1].record(stream)
+                total.add(st, b.n_cells, stream=stream)
             x, xo = xo, x
             v, vo = vo, v
 
-        x.copy_(x0)
-        v.copy_(v0)
-        for _ in range(args.warmup):
-            one_step()
+        with torch.cuda.stream(stream):
+            x.copy_(x0)
+            v.copy_(v0)
+            for _ in range(args.warmup):
+                one_step()
+            x.copy_(x0)
+            v.copy_(v0)
         torch.cuda.synchronize()
-        x.copy_(x0)
-        v.copy_(v0)
-        torch.cuda.synchronize()
+        g0 = batch.graph_counts()
         events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                   for _ in range(args.steps)]
         t_start = time.perf_counter()
-        for k in range(args.steps):
-            one_step(events[k])
+        with torch.cuda.stream(stream):
+            for k in range(args.steps):
+                one_step(events[k])
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
+        g1 = batch.graph_counts()
         kernel_ms = [a.elapsed_time(e) for a, e in events]
-        s = Batch.stats_to_numpy(st)                    # last step (read after timing)
-        res = {"value": b.n_cells * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+        tot = total.read()
+        cs = tot["cell_steps"]
+        assert cs == b.n_cells * args.steps, tot
+        res = {"value": cs / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
                "step_call_ms": float(np.mean(kernel_ms)),
-               "iterations_mean": float(np.mean(s["iterations"])), "iterations_max": int(np.max(s["iterations"])),
-               "evaluations_mean": float(np.mean(s["evaluations"])),
-               "converged_fraction": float(np.mean((s["status"] & CONVERGED) != 0))}
+               "iterations_mean": tot["iterations"] / cs, "iterations_max": tot["max_iterations"],
+               "evaluations_mean": tot["evaluations"] / cs, "halvings_mean": tot["halvings"] / cs,
+               "converged_fraction": 1.0 - tot["not_converged"] / cs,
+               "not_converged_cell_steps": tot["not_converged"],
+               "status_counts": dict(zip(("maxiter", "ls_fail", "nonfinite", "degenerate_tri"), tot["status_count"])),
+               "max_residual": tot["max_residual"],
+               "stats_over": f"all {args.steps} timed steps ({cs} cell-steps)",
+               "graph_captures_timed": g1["captures"] - g0["captures"],
+               "graph_replays_timed": g1["replays"] - g0["replays"]}
+        # the last timed step against the oracle on sampled cells: its inputs are (xo, vo, f)
+        # after the final swap, its output x
+        if args.oracle_cells > 0:
+            ids = np.linspace(0, b.n_cells - 1, args.oracle_cells).round().astype(int)
+            xin, vin, fin, xg = (a.cpu().numpy().astype(np.float64) for a in (xo, vo, f, x))
+            res["max_dx_over_D_vs_oracle"] = oracle_error(b, ids, xin, vin, fin, xg)
+            res["oracle_cells"] = ids.tolist()
         log(f"[bench] {form}: {res}")
         return res
+
+    def eval_roofline():
+        """The standalone objective-and-gradient kernel (one evaluation of every cell at
+        x_n + u, u a small random displacement), timed alone: algorithmic bytes 48 n per
+        cell (x_n, u and b in, the gradient out) plus 24 n for v and F_ext, from which b
+        is formed."""
+        with torch.cuda.stream(stream):
+            u = 1e-3 * torch.randn_like(x0)
+            batch.drag_forces(x0, v0, zeta, rate, origin, p["umax"], p["radius"], p["axis_y"], p["axis_z"], out=f)
+            batch.eval(x0, v0, f, u, stream=stream)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+            for a, e in ev:
+                a.record(stream)
+                batch.eval(x0, v0, f, u, stream=stream)
+                e.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(e) for a, e in ev]))
+        n = 642
+        by = b.n_cells * (48.0 + 24.0) * n
+        e32, e64 = eval_flops(n, mesh.nt, mesh.ne)
+        fl = b.n_cells * (e32 + 2.0 * e64)
+        return {"kernel": "eval_kernel (one objective + gradient evaluation of every cell)", "ms": ms,
+                "hbm": {"achieved": by / ms / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": by / ms / 1e6 / HBM_PEAK_GBS, "bytes_per_cell": 72.0 * n},
+                "alu": {"achieved": fl / ms / 1e9, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": fl / ms / 1e9 / VALU_FP32_PEAK_TFLOPS}}
 
     forms = {"plain": run_form("plain")}
     if args.weights:
@@ -423,12 +547,13 @@ def main():
         net = Net(plan, np.load(args.weights))
         forms["learned"] = run_form("learned", net)
         # the network's own time (inference alone, same inputs)
-        d = torch.empty_like(x0)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
-        for a, e in ev:
-            a.record()
-            net.infer(batch, x0, v0, f, out=d)
-            e.record()
+        with torch.cuda.stream(stream):
+            d = torch.empty_like(x0)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+            for a, e in ev:
+                a.record(stream)
+                net.infer(batch, x0, v0, f, out=d, stream=stream)
+                e.record(stream)
         torch.cuda.synchronize()
         forms["learned"]["net_infer_ms"] = float(np.mean([a.elapsed_time(e) for a, e in ev[1:]]))
         forms["learned"]["weights"] = os.path.relpath(args.weights, ROOT)
@@ -465,19 +590,21 @@ def main():
                                "dt=1e-7 s, FP32 bulk + FP64 reductions", "cells": b.n_cells, "mesh_vertices": n,
                    "form": chosen, "tol": args.tol, "schedule": sched,
                    "inverse_products": "fp32" if args.fp32_products else "bf16 off-diagonal + fp32 diagonal",
-                   "hip_graph": not args.no_graph},
+                   "hip_graph": (not args.no_graph) and ch["graph_replays_timed"] == args.steps},
+        "max_dx_over_D_vs_oracle": ch.get("max_dx_over_D_vs_oracle"),
         "forms": forms,
         "roofline": roof,
         "roofline_kernel": "step kernel, plain form",
         "roofline_alu": roof_alu,
+        "roofline_eval": eval_roofline(),
         "algorithmic_bytes_per_cell_step": cell_bytes,
         "work_per_cell_step": {"valu_fp32_flops": f32, "valu_fp64_flops": f64, "mfma_flops": mfma,
                                "state_bytes": 60.0 * n},
         "mfma_TFLOPs": b.n_cells * mfma / mean_kernel_s / 1e12,
         "io_GBs": io_bytes / mean_kernel_s / 1e9,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(b, args.cpu_sample, args.tol)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

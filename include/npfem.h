@@ -61,6 +61,9 @@ typedef enum { NPFEM_FP32 = 0, NPFEM_FP64 = 1 } npfem_precision;
 #define NPFEM_MAXITER 2u     /* max_iter reached */
 #define NPFEM_LS_FAIL 4u     /* line search failed even with the plain preconditioned gradient */
 #define NPFEM_NONFINITE 8u   /* non-finite objective or gradient at the first guess; x, v unchanged */
+#define NPFEM_DEGENERATE_TRI 16u  /* a triangle of x_{n+1} is collapsed (area below 1e-6 of its rest
+                                     area): its in-plane direction normal to the collapse is
+                                     undefined and carries no force */
 
 typedef struct npfem_mesh npfem_mesh;
 typedef struct npfem_plan npfem_plan;
@@ -106,6 +109,21 @@ typedef struct {
   double objective;     /* final g (up to the constant dropped from the inertial term) */
   double volume;        /* enclosed volume at x_{n+1} (FP64 reduction) */
 } npfem_cell_stats;
+
+/* Totals of per-cell results over one or more steps (device struct, see
+ * npfem_stats_accumulate).  status_count[k] counts cells with status bit 1 << (k + 1)
+ * set: MAXITER, LS_FAIL, NONFINITE, DEGENERATE_TRI. */
+typedef struct {
+  int64_t cell_steps;       /* cells counted */
+  int64_t iterations;       /* sum of iterations */
+  int64_t evaluations;      /* sum of evaluations */
+  int64_t halvings;         /* sum of line-search halvings */
+  int64_t not_converged;    /* cells without NPFEM_CONVERGED */
+  int64_t status_count[4];
+  int32_t max_iterations;
+  int32_t reserved;
+  double max_residual;
+} npfem_stats_total;
 
 const char *npfem_status_string(npfem_status s);
 const char *npfem_last_error(void);
@@ -190,12 +208,19 @@ npfem_status npfem_batch_autotune(npfem_batch *batch, const void *x, const void 
                                   double *best_ms);
 
 /*
- * use_graph = 1: npfem_step captures its launches into a HIP graph on the first call
- * with a given set of buffers and stream and replays the graph on later calls with the
- * same arguments (a different argument set is captured anew).  Not used on the NULL
- * stream.  use_graph = 0 (default): launches directly.
+ * use_graph = 1: npfem_step and npfem_step_learned capture their launches into a HIP
+ * graph on the first call with a given set of buffers, stream and network, and replay
+ * that graph on later calls with the same arguments.  Up to four argument sets are kept
+ * (the least recently used is dropped), so a caller alternating between two buffer
+ * sets replays both.  The NULL stream cannot be captured: calls on it launch directly.
+ * use_graph = 0 (default): launches directly, and the kept graphs are released.
+ * Rescheduling the batch releases them too.
  */
 npfem_status npfem_batch_set_graph(npfem_batch *batch, int32_t use_graph);
+
+/* Number of graph captures and graph replays performed by the batch's steps so far
+ * (host outputs, each may be NULL).  For tests and measurement. */
+npfem_status npfem_batch_graph_counts(const npfem_batch *batch, int64_t *captures, int64_t *replays);
 
 /*
  * One time step of every cell of the batch (Algorithm 1), asynchronous on `stream`
@@ -213,6 +238,17 @@ npfem_status npfem_batch_set_graph(npfem_batch *batch, int32_t use_graph);
 npfem_status npfem_step(npfem_batch *batch, const void *x, const void *v, const void *f_ext,
                         void *x_out, void *v_out, const void *u_guess, npfem_cell_stats *stats,
                         void *stream);
+
+/*
+ * Adds the per-cell results `stats` (device [n_cells], as written by npfem_step) to the
+ * device totals `total`, asynchronously on `stream`, so that a caller can count every
+ * step of a run without copying per-cell results to the host.  npfem_stats_reset
+ * zeroes `total` with a kernel (no memset node, so both may be captured in a graph).
+ * NPFEM_E_INVALID for NULL pointers or n_cells < 0.
+ */
+npfem_status npfem_stats_accumulate(const npfem_cell_stats *stats, int64_t n_cells, npfem_stats_total *total,
+                                    void *stream);
+npfem_status npfem_stats_reset(npfem_stats_total *total, void *stream);
 
 /*
  * Objective and gradient of every cell at x = x_n + u (section 2.1.1,

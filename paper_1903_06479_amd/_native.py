@@ -33,8 +33,12 @@ CELL_STATS_DTYPE = np.dtype([("iterations", np.int32), ("evaluations", np.int32)
                              ("status", np.uint32), ("halvings", np.int32), ("residual", np.float64),
                              ("objective", np.float64), ("volume", np.float64)])
 
+STATS_TOTAL_DTYPE = np.dtype([("cell_steps", np.int64), ("iterations", np.int64), ("evaluations", np.int64),
+                              ("halvings", np.int64), ("not_converged", np.int64), ("status_count", np.int64, (4,)),
+                              ("max_iterations", np.int32), ("reserved", np.int32), ("max_residual", np.float64)])
+
 FP32, FP64 = 0, 1
-CONVERGED, MAXITER, LS_FAIL, NONFINITE = 1, 2, 4, 8
+CONVERGED, MAXITER, LS_FAIL, NONFINITE, DEGENERATE_TRI = 1, 2, 4, 8, 16
 N_TERMS = 8
 
 _P = c_void_p
@@ -57,8 +61,11 @@ _SIGNATURES = {
     "npfem_batch_get_schedule": (c_int32, [c_void_p, _P, _P, _P, _P]),
     "npfem_batch_autotune": (c_int32, [c_void_p, _P, _P, _P, _P, _P, c_int32, _P, _P]),
     "npfem_batch_set_graph": (c_int32, [c_void_p, c_int32]),
+    "npfem_batch_graph_counts": (c_int32, [c_void_p, _P, _P]),
     "npfem_step": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P, _P]),
     "npfem_eval": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P]),
+    "npfem_stats_accumulate": (c_int32, [_P, c_int64, _P, _P]),
+    "npfem_stats_reset": (c_int32, [_P, _P]),
     "npfem_apply_inverse": (c_int32, [c_void_p, c_int32, c_int32, _P, _P, c_int32, _P, _P]),
     "npfem_drag_forces": (c_int32, [c_void_p, _P, _P, _P, _P, _P, c_double, c_double, c_double,
                                     c_double, _P, _P]),

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -671,19 +672,29 @@ struct npfem_batch {
   int* counter = nullptr;
   void* work = nullptr;
   CellState* cstate = nullptr;
-  // captured step (hipGraph), keyed by the buffers it was captured with
+  // captured steps (hipGraph), each keyed by the buffers, stream and network it was
+  // captured with; a few are kept so that callers alternating between buffer sets (the
+  // usual ping-pong of x and x_out) replay instead of capturing again
+  static constexpr int kGraphCache = 4;
+  struct GraphEntry {
+    const void* key[9];
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+  };
   int use_graph = 0;
-  hipGraphExec_t graph_exec = nullptr;
-  hipGraph_t graph = nullptr;
-  const void* graph_key[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  int64_t graph_captures = 0, graph_replays = 0;
   // learned warm start: the predicted correction of every vertex (allocated on first use)
   DeviceBuffers dbuf;
   void* delta = nullptr;
   void drop_graph() {
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    graph_exec = nullptr;
-    graph = nullptr;
+    for (auto& g : graphs) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    graphs.clear();
   }
   ~npfem_batch() { drop_graph(); }
 };
@@ -893,15 +904,27 @@ npfem_status launch_step_now(npfem_batch* b, const void* x, const void* v, const
   return NPFEM_OK;
 }
 
-// Run `launch` on stream s, directly or through the batch's captured graph: the graph
-// is (re)captured when the key (buffers, stream, network) differs from the captured one.
+// Run `launch` on stream s, directly or through one of the batch's captured graphs: a
+// graph is captured for a key (buffers, stream, network generation) not seen before,
+// replacing the least recently used one when the cache is full, and replayed otherwise.
+// The NULL stream cannot be captured, so launches on it are always direct.
 template <typename F>
 npfem_status run_maybe_graph(npfem_batch* b, const void* const (&key)[9], hipStream_t s, F launch) {
   if (!b->use_graph || s == nullptr) return launch();
-  bool same = b->graph_exec != nullptr;
-  for (int k = 0; k < 9; ++k) same = same && key[k] == b->graph_key[k];
-  if (!same) {
-    b->drop_graph();
+  npfem_batch::GraphEntry* hit = nullptr;
+  for (auto& g : b->graphs) {
+    bool same = true;
+    for (int k = 0; k < 9; ++k) same = same && key[k] == g.key[k];
+    if (same) hit = &g;
+  }
+  if (!hit) {
+    if ((int)b->graphs.size() >= npfem_batch::kGraphCache) {
+      auto lru = std::min_element(b->graphs.begin(), b->graphs.end(),
+                                  [](const auto& a, const auto& c) { return a.last_use < c.last_use; });
+      (void)hipGraphExecDestroy(lru->exec);
+      (void)hipGraphDestroy(lru->graph);
+      b->graphs.erase(lru);
+    }
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     npfem_status st = launch();
     hipGraph_t g = nullptr;
@@ -911,11 +934,22 @@ npfem_status run_maybe_graph(npfem_batch* b, const void* const (&key)[9], hipStr
       return st;
     }
     HIP_TRY(e);
-    b->graph = g;
-    HIP_TRY(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
-    for (int k = 0; k < 9; ++k) b->graph_key[k] = key[k];
+    npfem_batch::GraphEntry ent;
+    ent.graph = g;
+    const hipError_t ei = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      HIP_TRY(ei);
+    }
+    for (int k = 0; k < 9; ++k) ent.key[k] = key[k];
+    b->graphs.push_back(ent);
+    hit = &b->graphs.back();
+    b->graph_captures += 1;
+  } else {
+    b->graph_replays += 1;
   }
-  HIP_TRY(hipGraphLaunch(b->graph_exec, s));
+  hit->last_use = ++b->graph_clock;
+  HIP_TRY(hipGraphLaunch(hit->exec, s));
   return NPFEM_OK;
 }
 
@@ -943,6 +977,13 @@ npfem_status npfem_batch_set_graph(npfem_batch* b, int32_t use_graph) {
   if (!b) return fail(NPFEM_E_INVALID, "batch_set_graph: NULL batch");
   b->use_graph = use_graph ? 1 : 0;
   if (!b->use_graph) b->drop_graph();
+  return NPFEM_OK;
+}
+
+npfem_status npfem_batch_graph_counts(const npfem_batch* b, int64_t* captures, int64_t* replays) {
+  if (!b) return fail(NPFEM_E_INVALID, "batch_graph_counts: NULL batch");
+  if (captures) *captures = b->graph_captures;
+  if (replays) *replays = b->graph_replays;
   return NPFEM_OK;
 }
 
@@ -1015,6 +1056,19 @@ npfem_status npfem_batch_autotune(npfem_batch* b, const void* x, const void* v, 
   }
   if (best_ms) *best_ms = best;
   return schedule(b, bT, bm);
+}
+
+npfem_status npfem_stats_accumulate(const npfem_cell_stats* st, int64_t n, npfem_stats_total* tot, void* stream) {
+  if (!st || !tot || n < 0) return fail(NPFEM_E_INVALID, "stats_accumulate: NULL pointer or negative count");
+  if (n == 0) return NPFEM_OK;
+  HIP_TRY(launch_stats_accumulate(st, n, tot, static_cast<hipStream_t>(stream)));
+  return NPFEM_OK;
+}
+
+npfem_status npfem_stats_reset(npfem_stats_total* tot, void* stream) {
+  if (!tot) return fail(NPFEM_E_INVALID, "stats_reset: NULL pointer");
+  HIP_TRY(launch_stats_reset(tot, static_cast<hipStream_t>(stream)));
+  return NPFEM_OK;
 }
 
 npfem_status npfem_eval(npfem_batch* b, const void* x, const void* v, const void* f, const void* u,
@@ -1101,6 +1155,7 @@ npfem_status npfem_drag_forces(npfem_batch* b, const void* x, const void* v, con
 
 struct npfem_net {
   npfem_plan* plan = nullptr;
+  uint64_t generation = 0;                  // unique per network created (keys captured graphs)
   NetLayout lay{};
   double force_floor = 1.0, shape_scale = 0.1;
   DeviceBuffers buf;                        // parameters, optimiser state, BF16 weights, meshes
@@ -1256,6 +1311,25 @@ template <typename Real>
 npfem_status net_loss_grad_now(npfem_net* net, npfem_batch* b, const int32_t* cells, int n_cells,
                                const void* x, const void* v, const void* f, const void* x_next, const void* u0,
                                double* loss_out, float* grad_out, hipStream_t s) {
+  // The listed cells are copied to the host and range-checked before any kernel reads
+  // them; their vertex count gives the mean.
+  int64_t nodes = 0;
+  if (cells) {
+    std::vector<int32_t> hc(n_cells);
+    HIP_TRY(hipMemcpyAsync(hc.data(), cells, n_cells * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < n_cells; ++k) {
+      if (hc[k] < 0 || hc[k] >= b->n_cells) return fail(NPFEM_E_INVALID, "net_loss_grad: cell index out of range");
+    }
+    std::vector<int> cm(b->n_cells);
+    for (size_t mi = 0; mi < b->by_mesh.size(); ++mi)
+      for (int c : b->by_mesh[mi]) cm[c] = (int)mi;
+    for (int k = 0; k < n_cells; ++k) nodes += b->plan->meshes[cm[hc[k]]].mesh->n;
+  } else {
+    for (size_t mi = 0; mi < b->by_mesh.size(); ++mi)
+      for (int c : b->by_mesh[mi])
+        if (c < n_cells) nodes += b->plan->meshes[mi].mesh->n;
+  }
   auto a = net_fwd_args<Real>(net, b, x, v, f);
   a.S.feat = net->tfeat;
   a.S.H = net->tH;
@@ -1266,24 +1340,6 @@ npfem_status net_loss_grad_now(npfem_net* net, npfem_batch* b, const int32_t* ce
   a.cells = cells;
   a.n_cells = n_cells;
   HIP_TRY(launch_net_forward<Real>(a, net_fwd_grid(net, n_cells), net->fwd_lds, s));
-  // nodes of the listed cells (for the mean)
-  int64_t nodes = 0;
-  if (cells) {
-    std::vector<int32_t> hc(n_cells);
-    HIP_TRY(hipMemcpyAsync(hc.data(), cells, n_cells * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    std::vector<int> cm(b->n_cells);
-    for (int k = 0; k < n_cells; ++k) {
-      if (hc[k] < 0 || hc[k] >= b->n_cells) return fail(NPFEM_E_INVALID, "net_loss_grad: cell index out of range");
-    }
-    for (size_t mi = 0; mi < b->by_mesh.size(); ++mi)
-      for (int c : b->by_mesh[mi]) cm[c] = (int)mi;
-    for (int k = 0; k < n_cells; ++k) nodes += b->plan->meshes[cm[hc[k]]].mesh->n;
-  } else {
-    for (size_t mi = 0; mi < b->by_mesh.size(); ++mi)
-      for (int c : b->by_mesh[mi])
-        if (c < n_cells) nodes += b->plan->meshes[mi].mesh->n;
-  }
   NetLossArgs<Real> la{};
   la.S = a.S;
   la.meshes = net->d_meshes;
@@ -1349,6 +1405,8 @@ npfem_status npfem_net_create(npfem_plan* p, const npfem_net_config* cfg, const 
   HIP_TRY(hipSetDevice(p->device));
   auto net = std::make_unique<npfem_net>();
   net->plan = p;
+  static std::atomic<uint64_t> next_generation{1};
+  net->generation = next_generation.fetch_add(1);
   net->lay = net_layout(cfg->layers);
   net->force_floor = cfg->force_floor;
   net->shape_scale = cfg->shape_scale;
@@ -1457,7 +1515,10 @@ npfem_status npfem_step_learned(npfem_batch* b, npfem_net* net, const void* x, c
     if ((s = b->dbuf.alloc(bytes, &b->delta))) return s;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const void* const key[9] = {x, v, f, x_out, v_out, b->delta, stats, stream, net};
+  // the network enters the key by its generation, never by its address (a new network may
+  // be allocated where a destroyed one was)
+  const void* const key[9] = {x, v, f, x_out, v_out, b->delta, stats, stream,
+                              reinterpret_cast<const void*>(static_cast<uintptr_t>(net->generation))};
   return run_maybe_graph(b, key, st, [&]() -> npfem_status {
     npfem_status r;
     if ((r = net_infer_any(net, b, x, v, f, b->delta, st))) return r;

@@ -129,6 +129,8 @@ hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, c
                        const int* mesh_n, int n_cells, const double* zeta, const double* rate,
                        const double* origin, double umax, double radius, double ay, double az,
                        Real* f, hipStream_t s);
+hipError_t launch_stats_accumulate(const npfem_cell_stats* st, int64_t n, npfem_stats_total* tot, hipStream_t s);
+hipError_t launch_stats_reset(npfem_stats_total* tot, hipStream_t s);
 // LDS of the step kernel; stage_rows > 0: rows of the BF16 tile product staged in LDS;
 // vec_lds: the gradient and b of the current cell are kept in LDS too.
 template <typename Real>

@@ -14,6 +14,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <type_traits>
@@ -1079,7 +1080,9 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
       Real* D = tl.vec(VD, j);
       Real* Q = tl.vec(VQ, j);
       const int hn = cs.hist_n, head = cs.hist_head;
-      auto slot = [&](int p) { return (head - hn + p + m) % m; };   // p = 0 oldest .. hn-1 newest
+      // ring slot of stored pair p (0 oldest .. hn-1 newest); with no history (m = 0)
+      // nothing is stored and no slot is ever read
+      auto slot = [&](int p) { return m > 0 ? (head - hn + p + m) % m : 0; };
       constexpr int W = Vec16<Real>::W;
       typedef typename Vec16<Real>::type V;
       // When a vector takes at most two 16-byte slots per thread, r and the stored y_p are
@@ -1179,7 +1182,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
       } else {
 #pragma unroll 2
         for (int e = W * tid(); e < len; e += W * kBlock)
-          d_slot(e, vload(D, e), vload(G, e), vload(U, e), [&](int p) { return vload(tl.vec(VS0 + slot(p), j), e); });
+          d_slot(e, vload(D, e), vload(G, e), vload(U, e), [&](int p) { return hn > 0 ? vload(tl.vec(VS0 + slot(p), j), e) : zero; });
       }
       block_sum<1>(gdv, red);
       const double gd = gdv[0];
@@ -1291,7 +1294,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
       const int n_kept = hn - first_kept;
       const int hn2 = n_kept + (store ? 1 : 0);
       const int head2 = store ? (head + 1) % m : head;
-      auto slot2 = [&](int p) { return p < n_kept ? (head - hn + first_kept + p + m) % m : ns; };
+      auto slot2 = [&](int p) { return p < n_kept && m > 0 ? (head - hn + first_kept + p + m) % m : ns; };
       const bool conv = r.resid <= A.sol.tol;
       const bool out_of_iters = cs.iter + 1 >= A.sol.max_iter;
       // first half of the next recursion: alpha_p, newest first
@@ -1482,7 +1485,84 @@ __global__ void drag_kernel(const Real* x, const Real* v, const int64_t* cell_vo
   }
 }
 
+// Totals of per-cell step results: per-thread sums over a strided range of cells, a
+// workgroup reduction through LDS, then one set of device-scope atomics per workgroup
+// (integer sums, so the result does not depend on the order).
+__global__ void __launch_bounds__(kBlock) stats_accumulate_kernel(const npfem_cell_stats* st, int64_t n,
+                                                                  npfem_stats_total* tot) {
+  __shared__ long long s_sum[kBlock / 64][9];
+  __shared__ int s_max[kBlock / 64];
+  __shared__ double s_res[kBlock / 64];
+  long long v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // cells, iterations, evaluations, halvings, not converged, 4 status bits
+  int mx = 0;
+  double rmax = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * kBlock + tid(); c < n; c += (int64_t)gridDim.x * kBlock) {
+    const npfem_cell_stats a = st[c];
+    v[0] += 1;
+    v[1] += a.iterations;
+    v[2] += a.evaluations;
+    v[3] += a.halvings;
+    v[4] += (a.status & NPFEM_CONVERGED) ? 0 : 1;
+    v[5] += (a.status & NPFEM_MAXITER) ? 1 : 0;
+    v[6] += (a.status & NPFEM_LS_FAIL) ? 1 : 0;
+    v[7] += (a.status & NPFEM_NONFINITE) ? 1 : 0;
+    v[8] += (a.status & NPFEM_DEGENERATE_TRI) ? 1 : 0;
+    mx = max(mx, a.iterations);
+    rmax = fmax(rmax, a.residual);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] += __shfl_xor(v[k], off);
+    mx = max(mx, __shfl_xor(mx, off));
+    rmax = fmax(rmax, __shfl_xor(rmax, off));
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) s_sum[wave][k] = v[k];
+    s_max[wave] = mx;
+    s_res[wave] = rmax;
+  }
+  __syncthreads();
+  if (tid() == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v[k] += s_sum[w][k];
+      mx = max(mx, s_max[w]);
+      rmax = fmax(rmax, s_res[w]);
+    }
+    unsigned long long* t = reinterpret_cast<unsigned long long*>(tot);
+    atomicAdd(&t[0], (unsigned long long)v[0]);
+    atomicAdd(&t[1], (unsigned long long)v[1]);
+    atomicAdd(&t[2], (unsigned long long)v[2]);
+    atomicAdd(&t[3], (unsigned long long)v[3]);
+    atomicAdd(&t[4], (unsigned long long)v[4]);
+    for (int k = 0; k < 4; ++k) atomicAdd(&t[5 + k], (unsigned long long)v[5 + k]);
+    atomicMax(&tot->max_iterations, mx);
+    // residuals are >= 0 (or +inf / NaN), so their bit patterns order like the values
+    atomicMax(reinterpret_cast<unsigned long long*>(&tot->max_residual), (unsigned long long)__double_as_longlong(rmax));
+  }
+}
+
+__global__ void stats_reset_kernel(npfem_stats_total* tot) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *tot = npfem_stats_total{};
+}
+
 }  // namespace
+
+hipError_t launch_stats_accumulate(const npfem_cell_stats* st, int64_t n, npfem_stats_total* tot, hipStream_t s) {
+  (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
+  const int64_t want = (n + kBlock - 1) / kBlock;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, 512));
+  hipLaunchKernelGGL(stats_accumulate_kernel, dim3(grid), dim3(kBlock), 0, s, st, n, tot);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_reset(npfem_stats_total* tot, hipStream_t s) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(stats_reset_kernel, dim3(1), dim3(64), 0, s, tot);
+  return hipGetLastError();
+}
 
 // k columns of the BF16 tile product staged per chunk: what the LDS region of `lds`
 // bytes holds for stage_rows rows (a multiple of 32, capped at n_pad; 0: not staged).

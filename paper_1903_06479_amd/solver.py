@@ -173,6 +173,12 @@ class Batch:
     def set_graph(self, use_graph: bool) -> None:
         N.check(N.lib().npfem_batch_set_graph(self._h, 1 if use_graph else 0), "npfem_batch_set_graph")
 
+    def graph_counts(self) -> dict:
+        """Graph captures and replays performed by this batch's steps."""
+        c, r = c_int64(), c_int64()
+        N.check(N.lib().npfem_batch_graph_counts(self._h, byref(c), byref(r)), "npfem_batch_graph_counts")
+        return {"captures": c.value, "replays": r.value}
+
     def _vec(self, t, name):
         if t.shape != (self.n_vertices, 3):
             raise ValueError(f"{name} must have shape ({self.n_vertices}, 3)")
@@ -261,6 +267,28 @@ class Batch:
         h, self._h = getattr(self, "_h", None), None
         if h and N is not None and N._lib is not None:
             N._lib.npfem_batch_destroy(h)
+
+
+class StatsTotal:
+    """Device totals of per-cell step results over any number of steps
+    (npfem_stats_accumulate): no host synchronisation until read."""
+
+    def __init__(self, device="cuda:0", stream=None):
+        import torch
+        self.buf = torch.empty(N.STATS_TOTAL_DTYPE.itemsize, dtype=torch.uint8, device=device)
+        self.reset(stream)
+
+    def reset(self, stream=None) -> None:
+        N.check(N.lib().npfem_stats_reset(_dptr(self.buf), _stream(stream)), "npfem_stats_reset")
+
+    def add(self, stats, n_cells: int, stream=None) -> None:
+        N.check(N.lib().npfem_stats_accumulate(_dptr(stats), int(n_cells), _dptr(self.buf), _stream(stream)),
+                "npfem_stats_accumulate")
+
+    def read(self) -> dict:
+        a = self.buf.cpu().numpy().view(N.STATS_TOTAL_DTYPE)[0]
+        return {k: (a[k].tolist() if a[k].shape else a[k].item()) for k in N.STATS_TOTAL_DTYPE.names
+                if k != "reserved"}
 
 
 def default_net_config(**overrides) -> N.NetConfig:

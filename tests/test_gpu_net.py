@@ -259,3 +259,26 @@ def test_trained_network_cuts_iterations_on_held_out_cells():
     assert r["all_converged"]
     assert r["iterations_learned"] <= r["iterations_plain"] - 0.3, r
     assert r["max_dx_over_D"] <= 1e-5, r
+
+
+def test_loss_grad_rejects_a_bad_cell_index_before_any_launch():
+    """An out-of-range index in the training cell list is refused with
+    NPFEM_E_INVALID, and no kernel has run: the gradient buffer is untouched."""
+    from paper_1903_06479_amd import Batch, Net
+    from paper_1903_06479_amd import _native as N
+    b = workloads.shear(n_cells=4, seed=51)
+    X, Tr = b.meshes[642]
+    plan = make([(X, Tr)])
+    batch = Batch(plan, np.zeros(4, np.int32))
+    net = Net(plan, mp.init_params(mp.NetConfig(), 3).astype(np.float32))
+    x, v = T(b.x), T(b.v)
+    grad = torch.full((net.n_params,), 7.0, dtype=torch.float32, device=dev())
+    for bad in ([0, 4], [-1], [1, 2, 100000]):
+        cells = torch.tensor(bad, dtype=torch.int32, device=dev())
+        with pytest.raises(N.NpfemError, match="invalid argument"):
+            net.loss_grad(batch, x, v, v, x, v, cells=cells, grad=grad)
+    torch.cuda.synchronize()
+    assert torch.all(grad == 7.0)
+    cells = torch.tensor([3, 0], dtype=torch.int32, device=dev())
+    loss, g = net.loss_grad(batch, x, v, v, x, v, cells=cells, grad=grad)
+    assert np.isfinite(loss) and torch.isfinite(g).all()

@@ -388,29 +388,45 @@ def test_drag_forces_kernel_matches_inputs_module():
 
 
 def test_graph_replay_matches_eager_launch():
-    """The step captured in a HIP graph and replayed gives the eager result bit for bit,
-    on every replay, with unrelated eager work and synchronisations in between."""
-    from paper_1903_06479_amd import Batch
+    """The step captured in a HIP graph on a (non-NULL) stream and replayed gives the
+    eager result bit for bit, on every replay, with unrelated eager work and
+    synchronisations in between; a caller alternating between two buffer sets (x -> x',
+    then x' -> x) captures each set once and replays it afterwards."""
+    from paper_1903_06479_amd import Batch, CELL_STATS_DTYPE
     b = workloads.shear(n_cells=12, seed=21)
     X, Tr = b.meshes[642]
     x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
     f = rounded(workloads.drag_forces(b, x, v), "fp32")
     plan = make([(X, Tr)], "fp32", inverse_bf16=1)
     ref = Batch(plan, np.zeros(12, np.int32))
-    xe, ve, _ = ref.step(T(x, torch.float32), T(v, torch.float32), T(f, torch.float32))
+    xi, vi, fi = T(x, torch.float32), T(v, torch.float32), T(f, torch.float32)
+    xe, ve, _ = ref.step(xi, vi, fi)
+    xe2, ve2, _ = ref.step(xe, ve, fi)
     torch.cuda.synchronize()
+    side = torch.cuda.Stream()
     g = Batch(plan, np.zeros(12, np.int32))
     g.set_graph(True)
-    xi, vi, fi = T(x, torch.float32), T(v, torch.float32), T(f, torch.float32)
-    xo, vo = torch.empty_like(xi), torch.empty_like(vi)
-    st = torch.empty(12 * 40, dtype=torch.uint8, device=dev())
-    for rep in range(4):
-        xo.fill_(0.0)
-        g.step(xi, vi, fi, x_out=xo, v_out=vo, stats=st)
-        junk = (xi * 2.0).sum()                       # eager work between replays
-        torch.cuda.synchronize()
-        assert torch.equal(xo, xe) and torch.equal(vo, ve), rep
-        assert float(junk) == float(junk)
+    with torch.cuda.stream(side):
+        xa, va = xi.clone(), vi.clone()
+        xb, vb = torch.empty_like(xi), torch.empty_like(vi)
+        st = torch.empty(12 * CELL_STATS_DTYPE.itemsize, dtype=torch.uint8, device=dev())
+        for rep in range(4):
+            xa.copy_(xi)
+            va.copy_(vi)
+            xb.fill_(0.0)
+            g.step(xa, va, fi, x_out=xb, v_out=vb, stats=st, stream=side)      # set 1
+            junk = (xi * 2.0).sum()                                            # eager work in between
+            side.synchronize()
+            assert torch.equal(xb, xe) and torch.equal(vb, ve), rep
+            g.step(xb, vb, fi, x_out=xa, v_out=va, stats=st, stream=side)      # set 2
+            side.synchronize()
+            assert torch.equal(xa, xe2) and torch.equal(va, ve2), rep
+            assert float(junk) == float(junk)
+    counts = g.graph_counts()
+    assert counts == {"captures": 2, "replays": 6}, counts
+    # the NULL stream cannot be captured: those calls launch directly
+    g.step(xi, vi, fi)
+    assert g.graph_counts() == counts
 
 
 def test_autotuner_keeps_the_solution():
@@ -495,3 +511,51 @@ def test_throughput_full_size_sampled_cells():
         sl = b.cell_slice(c)
         xr, _, _ = oracle_step(m, xi[sl], vi[sl], fi[sl])
         assert np.abs(xg[sl] - xr).max() <= 1e-5 * D, c
+
+
+def test_no_history_fp64_matches_oracle():
+    """History length 0 (the preconditioned gradient H~^-1 grad g every iteration) on
+    FP64 642-vertex plans, whose vector passes take the unfused path: no stored pair is
+    ever read, and the step reaches the oracle's stationary point (computed with m = 0
+    too) within 1e-10 D."""
+    import oracle.step as ostep
+    from paper_1903_06479_amd import CONVERGED
+    b = workloads.shear(n_cells=3, seed=41)
+    X, Tr = b.meshes[642]
+    m = oracle_model(642)
+    f = workloads.drag_forces(b, b.x, b.v)
+    plan = make([(X, Tr)], "fp64", tol=1e-10, lbfgs_m=0, noise_factor=64.0, cells_per_tile=2)
+    xo, vo, st, _ = run_step(plan, np.zeros(3, np.int32), b.x, b.v, f)
+    assert np.all(st["status"] == CONVERGED), st
+    D = np.ptp(X[:, 0])
+    for c in range(3):
+        s = b.cell_slice(c)
+        xr, vr, _ = ostep.step(m, b.x[s], b.v[s], f[s], ostep.Params(tol=1e-12, m=0, polish=True))
+        assert np.abs(xo[s] - xr).max() <= 1e-10 * D, c
+
+
+def test_stats_totals_match_per_cell_results():
+    """The device totals of npfem_stats_accumulate over several steps equal the sums and
+    maxima of the per-cell results read back after each step."""
+    from paper_1903_06479_amd import Batch, StatsTotal, CONVERGED, MAXITER
+    b = workloads.shear(n_cells=37, seed=61)
+    X, Tr = b.meshes[642]
+    plan = make([(X, Tr)], "fp32", max_iter=4)              # some cells stop at MAXITER
+    batch = Batch(plan, np.zeros(37, np.int32))
+    x, v = T(b.x, torch.float32), T(b.v, torch.float32)
+    total = StatsTotal()
+    per = []
+    for k in range(3):
+        f = T(workloads.drag_forces(b, x.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64)),
+              torch.float32)
+        x, v, st = batch.step(x, v, f)
+        total.add(st, 37)
+        per.append(batch.stats_to_numpy(st))
+    tot = total.read()
+    s = np.concatenate(per)
+    assert tot["cell_steps"] == 3 * 37
+    assert tot["iterations"] == s["iterations"].sum() and tot["evaluations"] == s["evaluations"].sum()
+    assert tot["halvings"] == s["halvings"].sum() and tot["max_iterations"] == s["iterations"].max()
+    assert tot["not_converged"] == np.sum((s["status"] & CONVERGED) == 0)
+    assert tot["status_count"][0] == np.sum((s["status"] & MAXITER) != 0) > 0
+    assert tot["max_residual"] == s["residual"].max()

@@ -158,3 +158,154 @@ def test_step_momentum_balance():
     mm = m.mass[:, None]
     expect = (mm * vn).sum(0) + m.h * f.sum(0)
     np.testing.assert_allclose((mm * v).sum(0), expect, atol=1e-8 * np.abs(mm * vn).sum())
+
+
+# ---- L-BFGS two-loop recursion -------------------------------------------------------
+
+def test_lbfgs_direction_equals_dense_bfgs_inverse_update():
+    """The two-loop recursion is a fast way to apply H_k, the inverse-Hessian
+    approximation obtained by the BFGS inverse update (Nocedal & Wright eq. 6.17)
+        H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T,  rho = 1 / (y . s),
+    applied to H_0 once per stored pair, oldest first.  Here H_0 is an SPD matrix
+    applied to each of the three coordinate columns (as H~^-1 is), built densely on the
+    flattened 3n vector, and the direction must be -H_k g.  The secant condition
+    H_k y_newest = s_newest holds as well.  A reversed loop, a wrong rho or a swapped
+    s/y would break either check."""
+    rng = np.random.default_rng(11)
+    n, k = 7, 4
+    A = rng.standard_normal((n, n))
+    H0 = A @ A.T + n * np.eye(n)                      # SPD, applied per coordinate
+    H0_inv = np.linalg.inv(H0)
+    solve = lambda q: H0_inv @ q                      # q is [n, 3]
+    Bq = rng.standard_normal((3 * n, 3 * n))
+    Hess = Bq @ Bq.T + np.eye(3 * n)                  # a curvature model for the pairs
+    S = [rng.standard_normal((n, 3)) for _ in range(k)]
+    Y = [(Hess @ s.ravel()).reshape(n, 3) for s in S]
+    rho = [1.0 / np.sum(s * y) for s, y in zip(S, Y)]
+    g = rng.standard_normal((n, 3))
+    # dense H_k on the row-major flattening (index 3 i + c): H_0 = H0_inv (x) I_3
+    H = np.kron(H0_inv, np.eye(3))
+    I = np.eye(3 * n)
+    for s, y in zip(S, Y):
+        s_, y_ = s.ravel(), y.ravel()
+        r = 1.0 / (y_ @ s_)
+        H = (I - r * np.outer(s_, y_)) @ H @ (I - r * np.outer(y_, s_)) + r * np.outer(s_, s_)
+    d = step.lbfgs_direction(g, S, Y, rho, solve)
+    np.testing.assert_allclose(d.ravel(), -H @ g.ravel(), rtol=1e-10, atol=1e-12 * np.abs(H @ g.ravel()).max())
+    np.testing.assert_allclose(H @ Y[-1].ravel(), S[-1].ravel(), rtol=1e-10, atol=1e-12)
+    # no pairs: the preconditioned gradient
+    np.testing.assert_allclose(step.lbfgs_direction(g, [], [], [], solve), -H0_inv @ g, rtol=1e-14)
+
+
+# ---- residual ---------------------------------------------------------------------------
+
+def _tetrahedron():
+    X = np.array([[1.0, 1.0, 1.0], [1.0, -1.0, -1.0], [-1.0, 1.0, -1.0], [-1.0, -1.0, 1.0]])
+    T = np.array([[0, 1, 2], [0, 3, 1], [0, 2, 3], [1, 3, 2]])
+    return X, T
+
+
+def test_residual_hand_computed_tetrahedron():
+    """Regular tetrahedron with edge 2 sqrt(2): faces of area 2 sqrt(3), total area
+    8 sqrt(3), volume 8/3.  With density 3 the mass is 8, i.e. 2 per vertex; with
+    h = 0.5, m/h^2 = 8.  Inputs: u = (1/8, 0, 0) on vertex 0 (so M u/h^2 = (1, 0, 0)),
+    v = 0, F_ext = (0, 3, 4) on vertex 1 (|b| = 5), and a gradient (0, 9, 12) on
+    vertex 3 (|grad| = 15).  Then grad - M u/h^2 + b has entries (-1, 0, 0), (0, 3, 4),
+    (0, 9, 12): norm sqrt(251), and
+        r = 15 / (1 + 5 + sqrt(251) + B sqrt(8 sqrt(3))).
+    """
+    X, T = _tetrahedron()
+    m = Model(X, T, Material(density=3.0), 0.5)
+    assert np.isclose(m.V0, 8.0 / 3.0) and np.allclose(m.mass, 2.0)
+    u = np.zeros((4, 3))
+    u[0, 0] = 1.0 / 8.0
+    f = np.zeros((4, 3))
+    f[1] = [0.0, 3.0, 4.0]
+    grad = np.zeros((4, 3))
+    grad[3] = [0.0, 9.0, 12.0]
+    obj = step.Objective(m, X, np.zeros((4, 3)), f)
+    expect = 15.0 / (1.0 + 5.0 + np.sqrt(251.0) + m.mat.B * np.sqrt(8.0 * np.sqrt(3.0)))
+    assert obj.residual(X + u, grad) == pytest.approx(expect, rel=1e-14)
+    assert obj.residual(X + u, np.zeros((4, 3))) == 0.0
+
+
+def test_residual_and_step_invariant_under_change_of_units():
+    """The residual is a ratio of forces, so it must not depend on the units.  Lengths
+    scaled by L, masses by Mu and times by Tau: forces scale by Mu L / Tau^2, the
+    moduli B, C, D, k_volume (force per length) by Mu / Tau^2, k_bend (energy) by
+    Mu L^2 / Tau^2, the density by Mu / L^3; beta is in units of the time step.  The
+    residual of the same physical state, and the converged step, must map onto each
+    other."""
+    m1 = oracle_model(258)
+    xn, vn, f = random_inputs(m1, 21, pert=0.04, vel=0.02, force=3.0)
+    Lf, Mu, Tau = 1e3, 1e-3, 1e3           # nm, ag (1e-21 kg), ns
+    Ff = Mu * Lf / Tau ** 2
+    mat = m1.mat
+    mat2 = Material(B=mat.B * Mu / Tau ** 2, C=mat.C * Mu / Tau ** 2, D=mat.D * Mu / Tau ** 2,
+                    k_bend=mat.k_bend * Mu * Lf ** 2 / Tau ** 2, k_volume=mat.k_volume * Mu / Tau ** 2,
+                    beta=mat.beta, kappa=mat.kappa, density=mat.density * Mu / Lf ** 3)
+    m2 = Model(m1.X * Lf, m1.tris, mat2, m1.h * Tau)
+    np.testing.assert_allclose(m2.mass, m1.mass * Mu, rtol=1e-12)
+    o1 = step.Objective(m1, xn, vn, f)
+    o2 = step.Objective(m2, xn * Lf, vn * Lf / Tau, f * Ff)
+    x = o1.y + 0.01 * np.random.default_rng(3).standard_normal(xn.shape)
+    _, g1, _ = o1(x)
+    _, g2, _ = o2(x * Lf)
+    np.testing.assert_allclose(g2, g1 * Ff, rtol=1e-7, atol=1e-9 * np.abs(g1).max() * Ff)
+    assert o2.residual(x * Lf, g2) == pytest.approx(o1.residual(x, g1), rel=1e-7)
+    x1, _, _ = step.step(m1, xn, vn, f, step.Params(tol=1e-12, polish=True))
+    x2, _, _ = step.step(m2, xn * Lf, vn * Lf / Tau, f * Ff, step.Params(tol=1e-12, polish=True))
+    assert np.abs(x2 / Lf - x1).max() <= 1e-10 * np.ptp(m1.X)
+
+
+# ---- the stationary point (parity reference) ------------------------------------------
+
+def test_polish_reaches_the_stationary_point_of_a_stretched_cell():
+    """Under a large stretching load the Armijo test on g stops resolving progress well
+    above residual 1e-12 (g's FP64 rounding exceeds its decrease); the residual-decrease
+    continuation then reaches 1e-12, and the point it reaches is the brute-force Newton
+    solution of grad g = 0 (66-vertex mesh)."""
+    X, T = meshes.rbc_mesh(66)
+    m = Model(X, T, Material(), 0.1)
+    from rbc_inputs import workloads
+    n_end = int(np.ceil(0.05 * len(X)))
+    f = np.zeros_like(X)
+    order = np.argsort(X[:, 0])
+    f[order[-n_end:], 0] = 400.0 / n_end
+    f[order[:n_end], 0] = -400.0 / n_end
+    xa, _, plain = step.step(m, X, np.zeros_like(X), f, step.Params(tol=1e-12))
+    xb, _, info = step.step(m, X, np.zeros_like(X), f, step.Params(tol=1e-12, polish=True))
+    assert info.status == step.CONVERGED and info.residual <= 1e-12
+    xn, ok = newton.newton_solve(step.Objective(m, X, np.zeros_like(X), f), xb + 1e-4, tol=1e-12)
+    assert ok
+    assert np.abs(xb - xn).max() <= 1e-11 * np.ptp(X)
+    if plain.status != step.CONVERGED:          # the plain run stopped early: polish moved it
+        assert plain.residual > 1e-12
+
+
+def test_mixed_voronoi_areas_partition_the_surface():
+    """Meyer's mixed areas split every triangle among its corners, so they sum to the
+    total area, on the RBC meshes, which have obtuse triangles (the branch that gives
+    the obtuse corner half the area and the others a quarter).  Single triangles fix
+    the values: equilateral 1/3 each; right isosceles 1/2 at the right angle and 1/4 at
+    the others (the circumcentre lies on the hypotenuse, so both branches must agree
+    there); an obtuse triangle 1/2, 1/4, 1/4."""
+    from oracle.model import mixed_voronoi_areas
+    for n in (258, 642):
+        mm = oracle_model(n)
+        P = mm.X[mm.tris]
+        cosang = []
+        for k in range(3):
+            u, v = P[:, (k + 1) % 3] - P[:, k], P[:, (k + 2) % 3] - P[:, k]
+            cosang.append(np.einsum("ij,ij->i", u, v))
+        n_obtuse = int(np.sum(np.min(cosang, axis=0) < 0))
+        assert n_obtuse > 0, n
+        assert mm.vor_area.sum() == pytest.approx(mm.tri_area.sum(), rel=1e-12)
+        assert np.all(mm.vor_area > 0)
+    tri = np.array([[0, 1, 2]])
+    eq = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0], [1.0, np.sqrt(3.0), 0.0]])
+    np.testing.assert_allclose(mixed_voronoi_areas(eq, tri), np.full(3, np.sqrt(3.0) / 3), rtol=1e-13)
+    right = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0], [0.0, 2.0, 0.0]])      # area 2
+    np.testing.assert_allclose(mixed_voronoi_areas(right, tri), [1.0, 0.5, 0.5], rtol=1e-12)
+    obtuse = np.array([[0.0, 0.0, 0.0], [4.0, 0.0, 0.0], [-1.0, 1.0, 0.0]])     # area 2, obtuse at 0
+    np.testing.assert_allclose(mixed_voronoi_areas(obtuse, tri), [1.0, 0.5, 0.5], rtol=1e-13)
