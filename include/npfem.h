@@ -251,6 +251,24 @@ npfem_status npfem_stats_accumulate(const npfem_cell_stats *stats, int64_t n_cel
 npfem_status npfem_stats_reset(npfem_stats_total *total, void *stream);
 
 /*
+ * npfem_step without any allocation, for callers that cannot allocate device memory
+ * while they run: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and per-cell statistics as npfem_step
+ * (bit for bit), launched directly on `stream` (never through the batch's graphs).
+ * The tile counter, the cell states and the persistent workgroups' workspace live in a
+ * static device array of 64 MiB per GPU, allocated when the library's code is loaded on
+ * that GPU and held until the process ends; its address is looked up when the first
+ * plan on the GPU is created.  The persistent grid is reduced to the workgroups whose
+ * workspace fits the array (a 642-vertex FP32 batch at 5 cells per tile and history 2
+ * keeps about 180 workgroups).  NPFEM_E_UNSUPPORTED if a single workgroup's workspace
+ * exceeds 64 MiB.  Every call on a GPU shares that GPU's array: calls that overlap on
+ * one GPU (on different streams, or from several threads) race and must not be issued.
+ */
+npfem_status npfem_step_noalloc(npfem_batch *batch, const void *x, const void *v, const void *f_ext,
+                                void *x_out, void *v_out, const void *u_guess, npfem_cell_stats *stats,
+                                void *stream);
+
+/*
  * Objective and gradient of every cell at x = x_n + u (section 2.1.1,
  * eq. GeneralizedObjectiveFunctionDerivative), without iterating: the kernel that
  * evaluates the trial points of the line search, exposed for testing and measurement.

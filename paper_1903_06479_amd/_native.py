@@ -63,6 +63,7 @@ _SIGNATURES = {
     "npfem_batch_set_graph": (c_int32, [c_void_p, c_int32]),
     "npfem_batch_graph_counts": (c_int32, [c_void_p, _P, _P]),
     "npfem_step": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "npfem_step_noalloc": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P, _P]),
     "npfem_eval": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P]),
     "npfem_stats_accumulate": (c_int32, [_P, c_int64, _P, _P]),
     "npfem_stats_reset": (c_int32, [_P, _P]),

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -113,6 +114,28 @@ std::vector<double> spd_inverse(const std::vector<double>& L, int n) {
 }
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Per-device address of the allocation-free step's scratch array, looked up once per
+// device (with that device current) when the first plan on it is created.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+npfem_status init_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(NPFEM_E_UNSUPPORTED, "scratch: device index too large");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return NPFEM_OK;
+  void* ptr = nullptr;
+  HIP_TRY(scratch_address(&ptr));
+  if (!ptr) return fail(NPFEM_E_HIP, "scratch: hipGetSymbolAddress returned NULL");
+  g_scratch_ptr[device] = ptr;
+  return NPFEM_OK;
+}
+
+void* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
 
 // FP32 -> BF16 bits, round to nearest even (finite inputs).
 uint16_t to_bf16(float f) {
@@ -538,6 +561,7 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
   HIP_TRY(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(NPFEM_E_INVALID, "plan_create: no such HIP device");
   HIP_TRY(hipSetDevice(device));
+  if (npfem_status se = init_scratch(device)) return se;
   auto p = std::make_unique<npfem_plan>();
   p->device = device;
   p->precision = prm->precision;
@@ -964,6 +988,56 @@ npfem_status npfem_step(npfem_batch* b, const void* x, const void* v, const void
   hipStream_t s = static_cast<hipStream_t>(stream);
   const void* const key[9] = {x, v, f, x_out, v_out, u_guess, stats, stream, nullptr};
   return run_maybe_graph(b, key, s, [&] { return launch_step_now(b, x, v, f, x_out, v_out, u_guess, stats, s); });
+}
+
+npfem_status npfem_step_noalloc(npfem_batch* b, const void* x, const void* v, const void* f, void* x_out,
+                                void* v_out, const void* u_guess, npfem_cell_stats* stats, void* stream) {
+  if (!b || !x || !v || !f || !x_out || !v_out) return fail(NPFEM_E_INVALID, "step_noalloc: NULL pointer");
+  HIP_TRY(hipSetDevice(b->plan->device));
+  unsigned char* base = static_cast<unsigned char*>(scratch_of(b->plan->device));
+  if (!base) return fail(NPFEM_E_HIP, "step_noalloc: no scratch address for this device");
+  // layout: [tile counter: 256 B][cell states of the grid, 256-aligned][workspace slots]
+  const size_t rs = b->plan->precision == NPFEM_FP64 ? sizeof(double) : sizeof(float);
+  const size_t slot_bytes = (size_t)b->slot_stride * rs;
+  const size_t cs_bytes = (size_t)b->T * sizeof(CellState);
+  auto need = [&](int g) { return (size_t)256 + ((size_t)g * cs_bytes + 255) / 256 * 256 + (size_t)g * slot_bytes; };
+  int grid = b->grid;
+  while (grid > 0 && need(grid) > kScratchBytes) --grid;
+  if (grid < 1)
+    return fail(NPFEM_E_UNSUPPORTED, "step_noalloc: one workgroup's workspace (" + std::to_string(need(1)) +
+                                         " B) exceeds the " + std::to_string(kScratchBytes) + " B scratch");
+  int* counter = reinterpret_cast<int*>(base);
+  CellState* cstate = reinterpret_cast<CellState*>(base + 256);
+  unsigned char* work = base + 256 + ((size_t)grid * cs_bytes + 255) / 256 * 256;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (b->plan->precision == NPFEM_FP64) {
+    auto a = make_args<double>(b);
+    a.tile_counter = counter;
+    a.cstate = cstate;
+    a.work = reinterpret_cast<double*>(work);
+    a.x = static_cast<const double*>(x);
+    a.v = static_cast<const double*>(v);
+    a.f = static_cast<const double*>(f);
+    a.u_guess = static_cast<const double*>(u_guess);
+    a.x_out = static_cast<double*>(x_out);
+    a.v_out = static_cast<double*>(v_out);
+    a.stats = stats;
+    HIP_TRY(launch_step<double>(a, grid, b->lds, s, counter));
+  } else {
+    auto a = make_args<float>(b);
+    a.tile_counter = counter;
+    a.cstate = cstate;
+    a.work = reinterpret_cast<float*>(work);
+    a.x = static_cast<const float*>(x);
+    a.v = static_cast<const float*>(v);
+    a.f = static_cast<const float*>(f);
+    a.u_guess = static_cast<const float*>(u_guess);
+    a.x_out = static_cast<float*>(x_out);
+    a.v_out = static_cast<float*>(v_out);
+    a.stats = stats;
+    HIP_TRY(launch_step<float>(a, grid, b->lds, s, counter));
+  }
+  return NPFEM_OK;
 }
 
 npfem_status npfem_first_guess(npfem_batch* b, const void* x, const void* v, const void* f, void* u_out,

@@ -129,6 +129,10 @@ hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, c
                        const int* mesh_n, int n_cells, const double* zeta, const double* rate,
                        const double* origin, double umax, double radius, double ay, double az,
                        Real* f, hipStream_t s);
+// Allocation-free step: size of the per-device scratch array and its device address
+// (the address must be looked up with the device current).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_address(void** ptr);
 hipError_t launch_stats_accumulate(const npfem_cell_stats* st, int64_t n, npfem_stats_total* tot, hipStream_t s);
 hipError_t launch_stats_reset(npfem_stats_total* tot, hipStream_t s);
 // LDS of the step kernel; stage_rows > 0: rows of the BF16 tile product staged in LDS;

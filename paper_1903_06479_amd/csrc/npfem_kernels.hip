@@ -1550,6 +1550,14 @@ __global__ void stats_reset_kernel(npfem_stats_total* tot) {
 
 }  // namespace
 
+// Device scratch of the allocation-free step (npfem_step_noalloc): the tile counter,
+// the cell states and the workspace of the persistent workgroups.  One copy per device,
+// held until the process ends.  Host code never uses this name as an address: it takes
+// the per-device address from scratch_address() and passes that to the kernels.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
+
 hipError_t launch_stats_accumulate(const npfem_cell_stats* st, int64_t n, npfem_stats_total* tot, hipStream_t s) {
   (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
   const int64_t want = (n + kBlock - 1) / kBlock;

@@ -204,6 +204,17 @@ class Batch:
                                    _dptr(u_guess), _dptr(st), _stream(stream)), "npfem_step")
         return x_out, v_out, st
 
+    def step_noalloc(self, x, v, f, x_out, v_out, stats=None, u_guess=None, stream=None):
+        """npfem_step with every buffer supplied by the caller and the workspace in the
+        library's static device scratch: allocates nothing."""
+        for t, nm in ((x, "x"), (v, "v"), (f, "f"), (x_out, "x_out"), (v_out, "v_out")):
+            self._vec(t, nm)
+        if u_guess is not None:
+            self._vec(u_guess, "u_guess")
+        N.check(N.lib().npfem_step_noalloc(self._h, _dptr(x), _dptr(v), _dptr(f), _dptr(x_out), _dptr(v_out),
+                                           _dptr(u_guess), _dptr(stats), _stream(stream)), "npfem_step_noalloc")
+        return x_out, v_out, stats
+
     @staticmethod
     def stats_to_numpy(st) -> np.ndarray:
         return st.cpu().numpy().view(N.CELL_STATS_DTYPE)
