@@ -179,7 +179,7 @@ def _oracle_step(n_verts, x, v, f, tol=1e-12):
     import oracle.step as ostep
     X, T = meshes.rbc_mesh(n_verts)
     model = om.Model(X, T, om.Material(), workloads.DT_US)
-    xr, vr, info = ostep.step(model, x, v, f, ostep.Params(tol=tol))
+    xr, vr, info = ostep.step(model, x, v, f, ostep.Params(tol=tol, polish=True))
     return xr, info
 
 
