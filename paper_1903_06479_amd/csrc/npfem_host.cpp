@@ -394,7 +394,7 @@ struct DeviceBuffers {
 
 struct MeshPlan {
   const npfem_mesh* mesh;
-  int n_pad, chunk, vec_lds = 1;
+  int n_pad, chunk, vec_lds = 1, xu_lds = 1;
   std::vector<double> mass;
   double floor_force;
   MeshDev<float> dev32;
@@ -434,6 +434,7 @@ npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>&
   d.n_pad = np;
   d.chunk = mp.chunk;
   d.vec_lds = mp.vec_lds;
+  d.xu_lds = mp.xu_lds;
   npfem_status s;
   if ((s = p->buf.upload(m->tri.data(), m->tri.size(), &d.tri))) return s;
   auto w = conv(m->nb_w), va = conv(m->vor_area), e0 = conv(m->ell0), ms = conv(mp.mass);
@@ -503,31 +504,35 @@ npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>&
 
 // Largest triangle chunk for which the step's LDS fits the budget.
 template <typename Real>
-int choose_chunk(int np, int nt, size_t budget, int vec_lds) {
-  if (lds_bytes<Real>(np, nt, 0, vec_lds) <= budget) return nt;
+int choose_chunk(int np, int nt, size_t budget, int vec_lds, int xu_lds) {
+  if (lds_bytes<Real>(np, nt, 0, vec_lds, xu_lds) <= budget) return nt;
   int lo = 0;
   for (int ch = nt; ch >= 64; ch -= 64)
-    if (lds_bytes<Real>(np, ch, 0, vec_lds) <= budget) { lo = ch; break; }
+    if (lds_bytes<Real>(np, ch, 0, vec_lds, xu_lds) <= budget) { lo = ch; break; }
   return lo;
 }
 
 // LDS layout of a mesh: the first fit of (gradient and b in LDS, whole triangle list in
 // one chunk, two workgroups per CU), (in the workspace, one chunk, two per CU), (in LDS,
-// one chunk, one per CU), (in the workspace, largest chunk, one per CU).
+// one chunk, one per CU), (in the workspace, largest chunk, one per CU), and finally
+// (x_n and u in the workspace too, the LDS holding only the largest triangle chunk).
 template <typename Real>
-void choose_layout(int np, int nt, size_t half, size_t cap, int* chunk, int* vec_lds) {
-  const size_t budgets[4] = {half, half, cap, cap};
-  const int vls[4] = {1, 0, 1, 0};
-  for (int k = 0; k < 4; ++k) {
-    const int ch = choose_chunk<Real>(np, nt, budgets[k], vls[k]);
-    if (ch == nt || (k == 3 && ch > 0)) {
+void choose_layout(int np, int nt, size_t half, size_t cap, int* chunk, int* vec_lds, int* xu_lds) {
+  const size_t budgets[5] = {half, half, cap, cap, cap};
+  const int vls[5] = {1, 0, 1, 0, 0};
+  const int xus[5] = {1, 1, 1, 1, 0};
+  for (int k = 0; k < 5; ++k) {
+    const int ch = choose_chunk<Real>(np, nt, budgets[k], vls[k], xus[k]);
+    if (ch == nt || (k >= 3 && ch > 0)) {
       *chunk = ch;
       *vec_lds = vls[k];
+      *xu_lds = xus[k];
       return;
     }
   }
   *chunk = 0;
   *vec_lds = 0;
+  *xu_lds = 0;
 }
 
 }  // namespace
@@ -584,9 +589,9 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
     // two workgroups per CU when the whole triangle list fits in half the LDS
     const size_t half = 80 * 1024 - 512;
     if (fp64)
-      choose_layout<double>(mp.n_pad, m->nt, half, lds_cap, &mp.chunk, &mp.vec_lds);
+      choose_layout<double>(mp.n_pad, m->nt, half, lds_cap, &mp.chunk, &mp.vec_lds, &mp.xu_lds);
     else
-      choose_layout<float>(mp.n_pad, m->nt, half, lds_cap, &mp.chunk, &mp.vec_lds);
+      choose_layout<float>(mp.n_pad, m->nt, half, lds_cap, &mp.chunk, &mp.vec_lds, &mp.xu_lds);
     if (mp.chunk <= 0)
       return fail(NPFEM_E_UNSUPPORTED, "plan_create: mesh too large for the LDS in this precision");
     // lumped mass by barycentric area (section 2.1)
@@ -788,7 +793,7 @@ npfem_status batch_schedule(npfem_batch* b, int T, int m) {
   for (int mi = 0; mi < nm; ++mi)
     if (!b->by_mesh[mi].empty())
       lds = std::max(lds, lds_bytes<Real>(p->meshes[mi].n_pad, p->meshes[mi].chunk, stage_rows,
-                                          p->meshes[mi].vec_lds));
+                                          p->meshes[mi].vec_lds, p->meshes[mi].xu_lds));
   b->stage_k = stage_cols(lds, stage_rows, b->n_pad_max);   // the staging stays below the cell states
   // the tile's cell states go to LDS (after everything else) when they fit the LDS a
   // workgroup may have and cost no workgroups per CU
@@ -815,11 +820,15 @@ npfem_status batch_schedule(npfem_batch* b, int T, int m) {
   b->grid = p->prm.grid_blocks > 0 ? p->prm.grid_blocks : slots;
   b->grid = std::max(1, std::min(b->grid, b->n_tiles));
   // b, u, grad, d, q, the history, and a trial gradient if some mesh keeps it out of LDS
-  bool any_global = false;
-  for (int mi = 0; mi < nm; ++mi)
+  bool any_global = false, any_xu_global = false;
+  for (int mi = 0; mi < nm; ++mi) {
     if (!b->by_mesh[mi].empty() && !p->meshes[mi].vec_lds) any_global = true;
+    if (!b->by_mesh[mi].empty() && !p->meshes[mi].xu_lds) any_xu_global = true;
+  }
   b->n_vec = 5 + 2 * m + (any_global ? 1 : 0);
-  b->slot_stride = (int64_t)b->n_vec * T * 3 * b->n_pad_max;
+  // per slot: the tile's vectors, then (if some mesh keeps them out of LDS) the current
+  // cell's x_n and trial u
+  b->slot_stride = ((int64_t)b->n_vec * T + (any_xu_global ? 2 : 0)) * 3 * b->n_pad_max;
   const size_t wbytes = (size_t)b->grid * b->slot_stride * sizeof(Real);
   if ((s = b->sched.alloc(wbytes, &b->work))) return s;
   HIP_TRY(hipMemset(b->work, 0, wbytes));
@@ -1153,7 +1162,7 @@ npfem_status npfem_eval(npfem_batch* b, const void* x, const void* v, const void
   const bool fp64 = b->plan->precision == NPFEM_FP64;
   const size_t rs = fp64 ? 8 : 4;
   if (!b->eval_scratch) {
-    npfem_status st = b->buf.alloc((size_t)b->n_cells * 6 * b->n_pad_max * rs, &b->eval_scratch);
+    npfem_status st = b->buf.alloc((size_t)b->n_cells * 12 * b->n_pad_max * rs, &b->eval_scratch);
     if (st) return st;
   }
   if (fp64) {

@@ -18,6 +18,8 @@ struct MeshDev {
   int n, nt, n_pad;            // vertices, triangles, n rounded up to 32
   int chunk;                   // triangles per LDS corner chunk
   int vec_lds;                 // 1: the current cell's gradient and b live in LDS (else in the workspace)
+  int xu_lds;                  // 1: the current cell's x_n and trial u live in LDS (else in the
+                               //    workspace, after the per-cell vectors; implies vec_lds = 0)
   const int* tri;              // [nt][3]
   const double* dminv;         // [nt][4] D_m^-1 row-major (FP64 in every precision: the
   const double* area;          // [nt] rest area            triangle geometry is formed in FP64)
@@ -136,9 +138,10 @@ hipError_t scratch_address(void** ptr);
 hipError_t launch_stats_accumulate(const npfem_cell_stats* st, int64_t n, npfem_stats_total* tot, hipStream_t s);
 hipError_t launch_stats_reset(npfem_stats_total* tot, hipStream_t s);
 // LDS of the step kernel; stage_rows > 0: rows of the BF16 tile product staged in LDS;
-// vec_lds: the gradient and b of the current cell are kept in LDS too.
+// xu_lds: x_n and the trial u of the current cell are kept in LDS; vec_lds: so are its
+// gradient and b.
 template <typename Real>
-size_t lds_bytes(int n_pad, int chunk, int stage_rows, int vec_lds);
+size_t lds_bytes(int n_pad, int chunk, int stage_rows, int vec_lds, int xu_lds);
 int stage_cols(size_t lds, int stage_rows, int n_pad);
 template <typename Real>
 hipError_t set_lds_limit(size_t bytes);

@@ -960,12 +960,16 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
   const MeshDev<Real>& M = *Ml;
   const int n = M.n, np = M.n_pad, cnt = td.count, len = 3 * np;
   Tile<Real> tl{W, np, A.tile_cells_max};
-  Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);   // the current cell's x_n, trial u
-  Real* ut = xn + 3 * np;                                    // (and gradient and b) in LDS
-  const bool vl = M.vec_lds != 0;
+  // the current cell's x_n and trial u (and gradient and b) in LDS, then the corner
+  // chunks; for meshes too large for that, x_n and u follow the tile's vectors in the
+  // workspace and the LDS holds the corner chunks only
+  const bool vl = M.vec_lds != 0, xl = M.xu_lds != 0;
+  unsigned char* stage = lds + kLdsHeader;                   // BF16 staging of the tile product
+  Real* xn = xl ? reinterpret_cast<Real*>(lds + kLdsHeader) : W + (size_t)A.n_vec_slot * A.tile_cells_max * 3 * np;
+  Real* ut = xn + 3 * np;
   Real* gl = ut + 3 * np;
   Real* bl = gl + 3 * np;
-  Real* work = xn + (vl ? 12 : 6) * np;
+  Real* work = reinterpret_cast<Real*>(lds + kLdsHeader) + (xl ? (vl ? 12 : 6) * np : 0);
   const double h = A.sol.h;
   const int m = A.sol.m;
   const double eps = Eps<Real>::v;
@@ -996,8 +1000,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
     __syncthreads();
   }
   if (!A.u_guess) {
-    tile_product(M, A.sol, 1, tl.mat(VB), tl.mat(VU), 3 * cnt, reinterpret_cast<unsigned char*>(xn),
-                 A.stage_k);                                              // u = h^2 M~^-1 b
+    tile_product(M, A.sol, 1, tl.mat(VB), tl.mat(VU), 3 * cnt, stage, A.stage_k);                                              // u = h^2 M~^-1 b
     __syncthreads();
     if (A.guess_only || A.u_delta) {
       for (int j = 0; j < cnt; ++j) {
@@ -1068,8 +1071,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
     }
     __syncthreads();
     if (sint[1] == 0) break;
-    tile_product(M, A.sol, 0, tl.mat(VQ), tl.mat(VD), 3 * cnt, reinterpret_cast<unsigned char*>(xn),
-                 A.stage_k);                                              // r = H~^-1 q
+    tile_product(M, A.sol, 0, tl.mat(VQ), tl.mat(VD), 3 * cnt, stage, A.stage_k);                                              // r = H~^-1 q
     __syncthreads();
     for (int j = 0; j < cnt; ++j) {
       auto& cs = CS[j];
@@ -1418,12 +1420,14 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
   const MeshDev<Real>& M = A.meshes[A.cell_mesh[cell]];
   const int n = M.n, np = M.n_pad, len = 3 * np;
   const int64_t voff = A.cell_voff[cell];
-  Real* xn = reinterpret_cast<Real*>(lds + kLdsHeader);
-  Real* ut = xn + 3 * np;
-  const bool vl = M.vec_lds != 0;
-  Real* G = vl ? ut + 3 * np : scratch + (size_t)cell * 2 * 3 * A.n_pad_max;
-  Real* B = vl ? G + 3 * np : G + 3 * A.n_pad_max;
-  Real* work = xn + (vl ? 12 : 6) * np;
+  // per cell in the scratch: gradient, b, x_n, u (3 n_pad_max each), where not in LDS
+  const bool vl = M.vec_lds != 0, xl = M.xu_lds != 0;
+  Real* cs = scratch + (size_t)cell * 4 * 3 * A.n_pad_max;
+  Real* xn = xl ? reinterpret_cast<Real*>(lds + kLdsHeader) : cs + 2 * 3 * A.n_pad_max;
+  Real* ut = xl ? xn + 3 * np : cs + 3 * 3 * A.n_pad_max;
+  Real* G = vl ? ut + 3 * np : cs;
+  Real* B = vl ? G + 3 * np : cs + 3 * A.n_pad_max;
+  Real* work = reinterpret_cast<Real*>(lds + kLdsHeader) + (xl ? (vl ? 12 : 6) * np : 0);
   stage_aos(xn, A.x + 3 * voff, n, np);
   const Real* vs = A.v + 3 * voff;
   const Real* fs = A.f + 3 * voff;
@@ -1582,11 +1586,13 @@ int stage_cols(size_t lds, int stage_rows, int n_pad) {
 }
 
 template <typename Real>
-size_t lds_bytes(int n_pad, int chunk, int stage_rows, int vec_lds) {
-  // x_n, trial u (and, with vec_lds, the gradient and b), 3 n_pad each, then the corner
-  // chunks (9 per triangle, at least 3 n_pad: the bending pass keeps its residuals there)
+size_t lds_bytes(int n_pad, int chunk, int stage_rows, int vec_lds, int xu_lds) {
+  // x_n, trial u (and, with vec_lds, the gradient and b), 3 n_pad each, unless they live
+  // in the workspace, then the corner chunks (9 per triangle, at least 3 n_pad: the
+  // bending pass keeps its residuals there)
   const size_t work = (size_t)(3 * n_pad > 9 * chunk ? 3 * n_pad : 9 * chunk);
-  size_t region = sizeof(Real) * ((vec_lds ? 12 : 6) * (size_t)n_pad + work);
+  const size_t vecs = xu_lds ? (vec_lds ? 12 : 6) * (size_t)n_pad : 0;
+  size_t region = sizeof(Real) * (vecs + work);
   if (stage_rows > 0 && n_pad <= kStageMaxPad) {
     const size_t st = (size_t)stage_rows * (n_pad + 8) * 2;
     region = region > st ? region : st;
@@ -1670,7 +1676,7 @@ hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, c
 }
 
 #define NPFEM_INSTANTIATE(R)                                                                       \
-  template size_t lds_bytes<R>(int, int, int, int);                                                     \
+  template size_t lds_bytes<R>(int, int, int, int, int);                                                     \
   template hipError_t set_lds_limit<R>(size_t);                                                    \
   template hipError_t occupancy<R>(int*, size_t);                                                  \
   template hipError_t launch_step<R>(const StepArgs<R>&, int, size_t, hipStream_t, int*);          \
