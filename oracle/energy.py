@@ -16,13 +16,21 @@ Readings (paper silent or ambiguous; see the design notes):
   * Volume: the projection p = x - C grad C / |grad C|^2 (section 2.1.2) is used with
     the normaliser |grad C|^2 frozen at x_n for the whole step, making the energy
     (k/2) C(x)^2 / G_n and its gradient k C(x) grad C(x) / G_n consistent.  At x = x_n
-    this is exactly the paper's PD gradient k (x - p(x)).
+    this is exactly the paper's PD gradient k (x - p(x)).  The paper's own form, with
+    the normaliser taken at the current x (energy (k/2) C^2 / |grad C(x)|^2 and force
+    k (x - p(x))), is kept as the `literal` option; its force is not the derivative of
+    its energy once C != 0.
+  * Global area (optional, off by default): the same construction with the total area
+    A(x) in place of the volume, E = (k_A/2) (A - A0)^2 / G_A, G_A = |grad A(x_n)|^2.
+  * Collapsed triangles (deformed area below 1e-6 of the rest area) have no second
+    in-plane direction (see model.py): the in-plane forces of such a triangle act only
+    along its remaining edge direction.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .model import Model, triangle_frames, volume, volume_gradient
+from .model import Model, area_gradient, surface_area, triangle_frames, volume, volume_gradient
 
 
 def sl2_projection(s1: np.ndarray, s2: np.ndarray) -> np.ndarray:
@@ -46,9 +54,19 @@ def sl2_projection(s1: np.ndarray, s2: np.ndarray) -> np.ndarray:
     return t
 
 
+COLLAPSE_RATIO = 1e-6
+
+
+def collapsed_triangles(x: np.ndarray, m: Model) -> np.ndarray:
+    """Triangles whose deformed area is below COLLAPSE_RATIO of their rest area."""
+    a, b, c = x[m.tris[:, 0]], x[m.tris[:, 1]], x[m.tris[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(a - c, b - c), axis=1)
+    return area < COLLAPSE_RATIO * m.tri_area
+
+
 def _deformation(x: np.ndarray, m: Model):
     """F = D_s D_m^-1 in the deformed triangle's own 2D frame (Appendix B) and its SVD."""
-    Ds, basis, _ = triangle_frames(x, m.tris)
+    Ds, basis, _ = triangle_frames(x, m.tris, collapsed_triangles(x, m))
     F = Ds @ m.Dm_inv
     U, s, Vt = np.linalg.svd(F)
     return F, U, s, Vt, basis
@@ -113,20 +131,37 @@ def bending_energy(x: np.ndarray, m: Model):
     return E, m.G_bend.T @ (w[:, None] * r)
 
 
-def volume_energy(x: np.ndarray, m: Model, Gn: float):
+def volume_energy(x: np.ndarray, m: Model, Gn: float | None):
     """Global volume (section 2.1.2): E = (k / 2) C(x)^2 / G_n, C = V - V0,
-    gradient k C grad C / G_n with grad C = nbar / 3."""
+    gradient k C grad C / G_n with grad C = nbar / 3.  Gn = None: the paper's literal
+    form, normaliser |grad C(x)|^2 at the current x and force k C grad C / |grad C(x)|^2
+    (= k (x - p(x)), not the derivative of that energy once C != 0)."""
     C = volume(x, m.tris) - m.V0
     gC = volume_gradient(x, m.tris)
-    return 0.5 * m.mat.k_volume * C * C / Gn, m.mat.k_volume * C / Gn * gC
+    G = float(np.sum(gC ** 2)) if Gn is None else Gn
+    return 0.5 * m.mat.k_volume * C * C / G, m.mat.k_volume * C / G * gC
 
 
 def volume_normaliser(x: np.ndarray, m: Model) -> float:
     return float(np.sum(volume_gradient(x, m.tris) ** 2))
 
 
-def elastic_energy(x: np.ndarray, m: Model, Gn: float):
-    """Sum of the four membrane energies and of their gradients, plus the list of
-    the individual energies (for the line search's rounding-noise estimate)."""
+def area_normaliser(x: np.ndarray, m: Model) -> float:
+    return float(np.sum(area_gradient(x, m.tris) ** 2))
+
+
+def global_area_energy(x: np.ndarray, m: Model, GA: float):
+    """Global area (optional; section 2.1.2 notes it could be built like the volume
+    term): E = (k_A / 2) (A - A0)^2 / G_A, gradient k_A (A - A0) grad A / G_A."""
+    C = surface_area(x, m.tris) - m.A0
+    return 0.5 * m.mat.k_area_global * C * C / GA, m.mat.k_area_global * C / GA * area_gradient(x, m.tris)
+
+
+def elastic_energy(x: np.ndarray, m: Model, Gn: float | None, GA: float | None = None):
+    """Sum of the membrane energies and of their gradients, plus the list of the
+    individual energies (for the line search's rounding-noise estimate).  The global
+    area term enters when k_area_global > 0 (GA its frozen normaliser)."""
     parts = [area_energy(x, m), skalak_energy(x, m), bending_energy(x, m), volume_energy(x, m, Gn)]
+    if m.mat.k_area_global > 0:
+        parts.append(global_area_energy(x, m, GA))
     return sum(p[0] for p in parts), sum(p[1] for p in parts), [p[0] for p in parts]

@@ -9,8 +9,13 @@ Readings of the paper taken here (each is listed with its reason in the design n
   * Mass: the body's total mass rho * V0 is lumped on the vertices in proportion to
     their barycentric area (section 2.1, "weighting based on the area per vertex").
   * L = sum_i w_i G_i^T G_i (eq. fullyDeveloped_g) over the projective-dynamics
-    elements: area triangles (w = A_t C), bending vertices (w = A_i k_b) and the
-    volume element (G = I, w = k_volume).
+    elements: area triangles (w = A_t C), bending vertices (w = A_i k_b), the volume
+    element (G = I, w = k_volume) and, when it is switched on, the global-area element
+    (G = I, w = k_area_global), built like the volume one (section 2.1.2 says global
+    area conservation could be imposed by the same approach; off by default).
+  * A triangle whose deformed area is below 1e-6 of its rest area is taken as
+    collapsed: its frame has no second in-plane direction (the direction normal to the
+    collapse is undefined), so that direction carries no force.
   * Rayleigh damping C = beta_D L' with alpha_D = 0 (section 2.1.4), where L' is L
     without the volume identity so that rigid translations are not damped, and
     beta_D = beta * h (beta given in units of the time step).  Hence
@@ -41,26 +46,32 @@ class Material:
     kappa: float = 0.6       # post-convergence dissipation
     density: float = 1100.0  # fg / um^3
     k_mat: float | None = None  # material stiffness added to H~ (None -> B)
+    k_area_global: float = 0.0  # global-area PD weight (pN/um); 0 = off, as in the paper
 
     @property
     def k_mat_value(self) -> float:
         return self.B if self.k_mat is None else self.k_mat
 
 
-def triangle_frames(x: np.ndarray, tris: np.ndarray):
+def triangle_frames(x: np.ndarray, tris: np.ndarray, collapsed=None):
     """Each triangle (a, b, c) isometrically embedded in its own 2D frame.
 
     Returns (D [nt,2,2], basis [nt,3,2], area [nt]) with D = [x_a - x_c, x_b - x_c]
     expressed in the orthonormal frame basis = [e1, e2], e1 along x_a - x_c and
     e2 = n x e1 in the triangle's plane (n the unit normal), so det D = 2 * area >= 0.
+    Triangles flagged in `collapsed` get e2 = 0 (no second in-plane direction).
     """
     e1v = x[tris[:, 0]] - x[tris[:, 2]]
     e2v = x[tris[:, 1]] - x[tris[:, 2]]
     cr = np.cross(e1v, e2v)
-    area = 0.5 * np.linalg.norm(cr, axis=1)
-    t1 = e1v / np.linalg.norm(e1v, axis=1, keepdims=True)
-    nrm = cr / np.linalg.norm(cr, axis=1, keepdims=True)
+    crn = np.linalg.norm(cr, axis=1, keepdims=True)
+    area = 0.5 * crn[:, 0]
+    l1 = np.linalg.norm(e1v, axis=1, keepdims=True)
+    t1 = e1v / np.where(l1 > 0, l1, 1.0)
+    nrm = cr / np.where(crn > 0, crn, 1.0)
     t2 = np.cross(nrm, t1)
+    if collapsed is not None:
+        t2[collapsed] = 0.0
     basis = np.stack([t1, t2], axis=2)                      # [nt, 3, 2]
     D = np.einsum("tik,tij->tkj", basis, np.stack([e1v, e2v], axis=2))
     return D, basis, area
@@ -120,6 +131,25 @@ def volume(x: np.ndarray, tris: np.ndarray) -> float:
     return float(np.sum(np.einsum("ij,ij->i", a + b + c, an)) / 9.0)
 
 
+def surface_area(x: np.ndarray, tris: np.ndarray) -> float:
+    a, b, c = x[tris[:, 0]], x[tris[:, 1]], x[tris[:, 2]]
+    return float(0.5 * np.sum(np.linalg.norm(np.cross(b - a, c - a), axis=1)))
+
+
+def area_gradient(x: np.ndarray, tris: np.ndarray) -> np.ndarray:
+    """grad of the total area: a triangle's area A_t = |(x_b - x_a) x (x_c - x_a)| / 2
+    has dA_t/dx_a = n x (x_c - x_b) / 2 (n its unit normal), and cyclically for b, c."""
+    a, b, c = x[tris[:, 0]], x[tris[:, 1]], x[tris[:, 2]]
+    cr = np.cross(b - a, c - a)
+    nn = np.linalg.norm(cr, axis=1, keepdims=True)
+    n = cr / np.where(nn > 0, nn, 1.0)
+    g = np.zeros_like(x)
+    np.add.at(g, tris[:, 0], 0.5 * np.cross(n, c - b))
+    np.add.at(g, tris[:, 1], 0.5 * np.cross(n, a - c))
+    np.add.at(g, tris[:, 2], 0.5 * np.cross(n, b - a))
+    return g
+
+
 def volume_gradient(x: np.ndarray, tris: np.ndarray) -> np.ndarray:
     """grad V = nbar / 3, nbar_k = sum of A_t n_t over the triangles containing k
     (section 2.1.2; exact for a closed mesh)."""
@@ -158,6 +188,7 @@ class Model:
 
         # lumped mass, area weighted (section 2.1)
         self.V0 = volume(self.X, self.tris)
+        self.A0 = surface_area(self.X, self.tris)
         bary = np.zeros(n)
         for k in range(3):
             np.add.at(bary, self.tris[:, k], self.tri_area / 3.0)
@@ -175,7 +206,7 @@ class Model:
         np.add.at(L, (rows, cols), ((self.tri_area * mat.C)[:, None, None] * GtG).ravel())
         L += (Gb.T * (mat.k_bend * self.vor_area)) @ Gb
         self.L_damp = L.copy()                               # L' (no volume identity)
-        L += mat.k_volume * np.eye(n)
+        L += (mat.k_volume + mat.k_area_global) * np.eye(n)
         self.L = L
         self.K_mat = np.zeros((n, n))
         np.add.at(self.K_mat, (rows, cols), ((self.tri_area * mat.k_mat_value)[:, None, None] * GtG).ravel())

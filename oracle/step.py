@@ -39,9 +39,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .model import Model
-from .energy import elastic_energy, volume_normaliser
+from .energy import area_normaliser, collapsed_triangles, elastic_energy, volume_normaliser
 
-CONVERGED, MAXITER, LS_FAIL = 1, 2, 4
+CONVERGED, MAXITER, LS_FAIL, NONFINITE, DEGENERATE_TRI = 1, 2, 4, 8, 16
 
 
 @dataclass
@@ -68,15 +68,17 @@ class StepInfo:
 
 
 class Objective:
-    """g, grad g and the residual of one step (fixed x_n, v_n, F_ext)."""
+    """g, grad g and the residual of one step (fixed x_n, v_n, F_ext).  literal: the
+    volume term with the paper's normaliser at the current x instead of at x_n."""
 
-    def __init__(self, m: Model, x_n, v_n, f_ext):
+    def __init__(self, m: Model, x_n, v_n, f_ext, literal: bool = False):
         self.m, self.x_n = m, np.asarray(x_n, np.float64)
         h = m.h
         self.b = m.mass[:, None] * np.asarray(v_n, np.float64) / h + np.asarray(f_ext, np.float64)
         # y_n = x_n + h M~^-1 M v_n + h^2 M~^-1 F_ext = x_n + h^2 M~^-1 b
         self.y = self.x_n + h * h * m.solve_Mt(self.b)
-        self.Gn = volume_normaliser(self.x_n, m)
+        self.Gn = None if literal else volume_normaliser(self.x_n, m)
+        self.GA = area_normaliser(self.x_n, m) if m.mat.k_area_global > 0 else None
         self.evaluations = 0
 
     def __call__(self, x):
@@ -86,7 +88,7 @@ class Objective:
         dx = x - self.y
         Mdx = m.Mt @ dx
         inertia = 0.5 * np.sum(dx * Mdx) / h ** 2
-        E, gE, parts = elastic_energy(x, m, self.Gn)
+        E, gE, parts = elastic_energy(x, m, self.Gn, self.GA)
         grad = Mdx / h ** 2 + gE
         noise = abs(inertia) + sum(abs(p) for p in parts)
         return inertia + E, grad, noise
@@ -154,6 +156,8 @@ def minimise(obj: Objective, x0, p: Params):
         x, g = _polish(obj, x, g, grad, p, info)
     if not info.status:
         info.status = MAXITER
+    if np.any(collapsed_triangles(x, obj.m)):
+        info.status |= DEGENERATE_TRI
     info.evaluations = obj.evaluations
     info.objective = g
     return x, info
@@ -221,9 +225,9 @@ def dissipate(x, v, mass, kappa):
     return v + kappa * dv
 
 
-def step(m: Model, x_n, v_n, f_ext, p: Params = Params(), x_start=None):
+def step(m: Model, x_n, v_n, f_ext, p: Params = Params(), x_start=None, literal: bool = False):
     """One npFEM step of one cell: returns (x_{n+1}, v_{n+1}, info)."""
-    obj = Objective(m, x_n, v_n, f_ext)
+    obj = Objective(m, x_n, v_n, f_ext, literal)
     x0 = obj.y if x_start is None else np.asarray(x_start, np.float64)
     x, info = minimise(obj, x0, p)
     v = (x - obj.x_n) / m.h

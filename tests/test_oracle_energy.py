@@ -236,3 +236,131 @@ def test_L_matches_quadratic_part_of_pd_energies():
         ell[j] += m.G_bend[j, i] * (u[i] - u[j])
     bend = np.sum(m.mat.k_bend * m.vor_area * np.sum(ell * ell, axis=1))
     assert np.isclose(np.sum(u * (m.L_damp @ u)), tri + bend, rtol=1e-10)
+
+
+# ---- global area (optional term) -------------------------------------------------------
+
+def test_area_gradient_euler_relation_and_invariances():
+    """The total area is homogeneous of degree 2 in the positions (and the volume of
+    degree 3), so Euler's relation fixes sum_k x_k . grad A_k = 2 A (and = 3 V for the
+    volume), independently of how the gradients are formed; translation and rotation
+    invariance give sum grad A = 0 and sum x x grad A = 0."""
+    from oracle.model import area_gradient, surface_area
+    m = oracle_model(642)
+    x = deformed(m, 0.08, 12) + [2.0, -1.0, 0.5]
+    gA, gV = area_gradient(x, m.tris), volume_gradient(x, m.tris)
+    assert np.sum(x * gA) == pytest.approx(2.0 * surface_area(x, m.tris), rel=1e-12)
+    assert np.sum(x * gV) == pytest.approx(3.0 * volume(x, m.tris), rel=1e-12)
+    assert np.abs(gA.sum(axis=0)).max() < 1e-12 * np.abs(gA).sum()
+    assert np.abs(np.cross(x, gA).sum(axis=0)).max() < 1e-12 * np.abs(x[:, None] * gA[:, :, None]).sum()
+    h = 1e-6
+    for i, k in [(0, 0), (100, 1), (641, 2)]:
+        xp, xm = x.copy(), x.copy()
+        xp[i, k] += h
+        xm[i, k] -= h
+        fd = (surface_area(xp, m.tris) - surface_area(xm, m.tris)) / (2 * h)
+        assert fd == pytest.approx(gA[i, k], rel=1e-6, abs=1e-9)
+
+
+def test_global_area_energy_pins():
+    """(k_A/2)(A - A0)^2 / G_A: zero with zero force at rest, its gradient against
+    finite differences (G_A frozen), invariant under rigid motions, and a uniform
+    scaling by s gives exactly (k_A/2)(s^2 - 1)^2 A0^2 / G_A."""
+    m = oracle_model(258, k_area_global=40.0)
+    GA = energy.area_normaliser(deformed(m, 0.03, 3), m)
+    E0, g0 = energy.global_area_energy(m.X, m, GA)
+    assert abs(E0) < 1e-12 * m.A0 ** 2 and np.abs(g0).max() < 1e-10
+    s = 1.03
+    Es, _ = energy.global_area_energy(s * m.X, m, GA)
+    assert Es == pytest.approx(0.5 * 40.0 * (s * s - 1) ** 2 * m.A0 ** 2 / GA, rel=1e-10)
+    x = deformed(m, 0.05, 4)
+    E, g = energy.global_area_energy(x, m, GA)
+    h = 1e-6
+    for i, k in [(3, 0), (77, 1), (250, 2)]:
+        xp, xm = x.copy(), x.copy()
+        xp[i, k] += h
+        xm[i, k] -= h
+        fd = (energy.global_area_energy(xp, m, GA)[0] - energy.global_area_energy(xm, m, GA)[0]) / (2 * h)
+        assert fd == pytest.approx(g[i, k], rel=1e-5, abs=1e-7 * np.abs(g).max())
+    R = random_rotation(5)
+    E2, g2 = energy.global_area_energy(x @ R.T - 3.0, m, GA)
+    assert E2 == pytest.approx(E, rel=1e-10)
+    np.testing.assert_allclose(g2, g @ R.T, atol=1e-10 * np.abs(g).max())
+    # the global-area element adds k_A I to L (G = I, like the volume element)
+    assert np.allclose(m.L @ np.ones(m.n), m.mat.k_volume + 40.0, atol=1e-8)
+
+
+def test_step_with_global_area_matches_brute_force_newton():
+    from oracle import newton, step
+    from oracle.model import Model, Material
+    X, T = meshes.sphere_mesh(42, 3.0)
+    mm = Model(X, T, Material(k_area_global=80.0), 0.1)
+    rng = np.random.default_rng(13)
+    xn = X + 0.1 * rng.standard_normal(X.shape)
+    vn, f = 0.01 * rng.standard_normal(X.shape), 5.0 * rng.standard_normal(X.shape)
+    xa, _, info = step.step(mm, xn, vn, f, step.Params(tol=1e-13, polish=True))
+    assert info.status & step.CONVERGED
+    xb, ok = newton.newton_solve(step.Objective(mm, xn, vn, f), xn + 0.01)
+    assert ok and np.abs(xa - xb).max() <= 1e-10 * np.ptp(X)
+
+
+# ---- the paper's literal volume normaliser ---------------------------------------------
+
+def test_literal_volume_normaliser():
+    """The literal form takes |grad C|^2 at the current x: at x = x_n it coincides with
+    the frozen form; its force equals the paper's PD force k (x - p(x)) with the
+    projection p(x) = x - C grad C / |grad C|^2 assembled explicitly; once C != 0 that
+    force differs from the derivative of its own energy (which the frozen form avoids)."""
+    m = oracle_model(258)
+    xn = deformed(m, 0.04, 6)
+    x = xn + 0.03 * np.random.default_rng(2).standard_normal(xn.shape)
+    Gn = energy.volume_normaliser(xn, m)
+    Ef, gf = energy.volume_energy(xn, m, Gn)
+    El, gl = energy.volume_energy(xn, m, None)
+    assert El == Ef and np.array_equal(gl, gf)
+    C = volume(x, m.tris) - m.V0
+    gC = volume_gradient(x, m.tris)
+    p = x - C * gC / np.sum(gC * gC)
+    _, gl = energy.volume_energy(x, m, None)
+    np.testing.assert_allclose(gl, m.mat.k_volume * (x - p), rtol=0, atol=1e-9 * np.abs(gl).max())
+    i, k, h = 10, 2, 1e-6
+    xp, xm = x.copy(), x.copy()
+    xp[i, k] += h
+    xm[i, k] -= h
+    fd = (energy.volume_energy(xp, m, None)[0] - energy.volume_energy(xm, m, None)[0]) / (2 * h)
+    assert abs(C) > 1e-3 and abs(fd - gl[i, k]) > 1e-6 * abs(gl[i, k])
+
+
+# ---- collapsed triangles --------------------------------------------------------------
+
+def test_collapsed_triangle_reading():
+    """A triangle squeezed to a segment (one vertex on the opposite edge) has no second
+    in-plane direction: every term stays finite, its in-plane forces act along the
+    segment only, and the step reports DEGENERATE_TRI when the final positions still
+    hold a collapsed triangle."""
+    from oracle import step
+    m = oracle_model(66)
+    x = m.X.copy()
+    a, b, c = m.tris[5]
+    x[c] = 0.5 * (x[a] + x[b])                       # triangle 5 collapses onto edge ab
+    assert energy.collapsed_triangles(x, m)[5] and energy.collapsed_triangles(x, m).sum() >= 1
+    for name in ("area", "skalak"):
+        E, g = term(name, x, m, energy.volume_normaliser(x, m))
+        assert np.isfinite(E) and np.all(np.isfinite(g))
+    # the in-plane terms of triangle 5 alone: forces parallel to the segment a-b
+    from oracle.model import Model
+    single = Model.__new__(Model)
+    single.__dict__.update(m.__dict__)
+    single.tris = m.tris[5:6]
+    single.Dm_inv, single.tri_area = m.Dm_inv[5:6], m.tri_area[5:6]
+    for fn in (energy.area_energy, energy.skalak_energy):
+        _, g = fn(x, single)
+        d = (x[b] - x[a]) / np.linalg.norm(x[b] - x[a])
+        for v in (a, b, c):
+            assert np.linalg.norm(np.cross(g[v], d)) <= 1e-9 * max(1.0, np.linalg.norm(g[v]))
+    # a step that cannot undo the collapse (vertices pinned by huge masses is not an
+    # option here), so check the flag on the status of a minimisation that starts and
+    # stops there: max_iter 0 iterations of work, the first guess kept
+    obj = step.Objective(m, x, np.zeros_like(x), np.zeros_like(x))
+    _, info = step.minimise(obj, x, step.Params(max_iter=0))
+    assert info.status & step.DEGENERATE_TRI
