@@ -80,7 +80,20 @@ typedef struct {
   double kappa;     /* post-convergence dissipation factor in [0, 1] (section 2.1.4) */
   double density;   /* total mass = density * rest volume, lumped by vertex area (section 2.1) */
   double k_mat;     /* material stiffness added to H~ only (section 2.1.1); < 0 means B */
+  double k_area_global;  /* weight of the optional global-area PD term (section 2.1.2: the
+                            paper notes it could be built like the volume term and does not
+                            use it): E = (k/2)(A - A0)^2 / |grad A(x_n)|^2, and k I in L and
+                            H~; 0 (default) = off */
 } npfem_material;
+
+/* Normaliser of the global-volume term (section 2.1.2). */
+#define NPFEM_VOLUME_STEP_FROZEN 0    /* |grad V|^2 taken at x_n for the whole step: the energy
+                                         (k/2) C^2 / G_n and its gradient k C grad V / G_n agree,
+                                         and the gradient equals the paper's PD force at x_n */
+#define NPFEM_VOLUME_PAPER_LITERAL 1  /* |grad V(x)|^2 at the current x, force k (x - p(x)) as
+                                         printed; that force is not the derivative of the
+                                         energy once C != 0, so near convergence the line
+                                         search may stop on it (LS_FAIL) */
 
 /* Solver controls.  The paper fixes none of these (section 2.1.5). */
 typedef struct {
@@ -97,6 +110,7 @@ typedef struct {
                                diagonal plus a BF16 off-diagonal part on the matrix cores
                                (they only precondition and start the iteration, so the
                                solution is unchanged); 0 = FP32 matrix cores */
+  int32_t volume_normaliser;  /* NPFEM_VOLUME_STEP_FROZEN (default) or NPFEM_VOLUME_PAPER_LITERAL */
 } npfem_solver_params;
 
 /* Per-cell result of a step (device array filled by npfem_step). */
@@ -108,6 +122,7 @@ typedef struct {
   double residual;      /* final residual */
   double objective;     /* final g (up to the constant dropped from the inertial term) */
   double volume;        /* enclosed volume at x_{n+1} (FP64 reduction) */
+  double area;          /* total membrane area at x_{n+1} (FP64 reduction) */
 } npfem_cell_stats;
 
 /* Totals of per-cell results over one or more steps (device struct, see
@@ -273,10 +288,11 @@ npfem_status npfem_step_noalloc(npfem_batch *batch, const void *x, const void *v
  * eq. GeneralizedObjectiveFunctionDerivative), without iterating: the kernel that
  * evaluates the trial points of the line search, exposed for testing and measurement.
  *   x, v, f_ext, u: device [V_total][3]; grad_out: device [V_total][3]
- *   terms_out     : device double [n_cells][8] = { g, inertial part, area PD, Skalak,
+ *   terms_out     : device double [n_cells][11] = { g, inertial part, area PD, Skalak,
  *                   bending (incl. its Rayleigh part), volume PD, triangle Rayleigh
- *                   part, residual }
- * The volume normaliser |grad V|^2 is taken at x_n.
+ *                   part, residual, global-area PD, total area, collapsed triangles }
+ * The volume normaliser |grad V|^2 is taken at x_n (at x_n + u with
+ * NPFEM_VOLUME_PAPER_LITERAL), the global-area one at x_n.
  */
 npfem_status npfem_eval(npfem_batch *batch, const void *x, const void *v, const void *f_ext,
                         const void *u, void *grad_out, double *terms_out, void *stream);

@@ -24,7 +24,8 @@ Readings (paper silent or ambiguous; see the design notes):
     A(x) in place of the volume, E = (k_A/2) (A - A0)^2 / G_A, G_A = |grad A(x_n)|^2.
   * Collapsed triangles (deformed area below 1e-6 of the rest area) have no second
     in-plane direction (see model.py): the in-plane forces of such a triangle act only
-    along its remaining edge direction.
+    along its remaining edge direction, and it adds nothing to the area gradient (its
+    normal, and the derivative of its area, are undefined).
 """
 from __future__ import annotations
 
@@ -147,14 +148,15 @@ def volume_normaliser(x: np.ndarray, m: Model) -> float:
 
 
 def area_normaliser(x: np.ndarray, m: Model) -> float:
-    return float(np.sum(area_gradient(x, m.tris) ** 2))
+    return float(np.sum(area_gradient(x, m.tris, collapsed_triangles(x, m)) ** 2))
 
 
 def global_area_energy(x: np.ndarray, m: Model, GA: float):
     """Global area (optional; section 2.1.2 notes it could be built like the volume
     term): E = (k_A / 2) (A - A0)^2 / G_A, gradient k_A (A - A0) grad A / G_A."""
     C = surface_area(x, m.tris) - m.A0
-    return 0.5 * m.mat.k_area_global * C * C / GA, m.mat.k_area_global * C / GA * area_gradient(x, m.tris)
+    gA = area_gradient(x, m.tris, collapsed_triangles(x, m))
+    return 0.5 * m.mat.k_area_global * C * C / GA, m.mat.k_area_global * C / GA * gA
 
 
 def elastic_energy(x: np.ndarray, m: Model, Gn: float | None, GA: float | None = None):

@@ -136,13 +136,17 @@ def surface_area(x: np.ndarray, tris: np.ndarray) -> float:
     return float(0.5 * np.sum(np.linalg.norm(np.cross(b - a, c - a), axis=1)))
 
 
-def area_gradient(x: np.ndarray, tris: np.ndarray) -> np.ndarray:
+def area_gradient(x: np.ndarray, tris: np.ndarray, collapsed=None) -> np.ndarray:
     """grad of the total area: a triangle's area A_t = |(x_b - x_a) x (x_c - x_a)| / 2
-    has dA_t/dx_a = n x (x_c - x_b) / 2 (n its unit normal), and cyclically for b, c."""
+    has dA_t/dx_a = n x (x_c - x_b) / 2 (n its unit normal), and cyclically for b, c.
+    A collapsed triangle (flagged in `collapsed`) has no normal, and |n| no derivative:
+    it contributes nothing."""
     a, b, c = x[tris[:, 0]], x[tris[:, 1]], x[tris[:, 2]]
     cr = np.cross(b - a, c - a)
     nn = np.linalg.norm(cr, axis=1, keepdims=True)
     n = cr / np.where(nn > 0, nn, 1.0)
+    if collapsed is not None:
+        n[collapsed] = 0.0
     g = np.zeros_like(x)
     np.add.at(g, tris[:, 0], 0.5 * np.cross(n, c - b))
     np.add.at(g, tris[:, 1], 0.5 * np.cross(n, a - c))

@@ -15,14 +15,14 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnpfem.so
 
 class Material(ctypes.Structure):
     _fields_ = [(k, c_double) for k in ("B", "C", "D", "k_bend", "k_volume", "beta", "kappa",
-                                        "density", "k_mat")]
+                                        "density", "k_mat", "k_area_global")]
 
 
 class SolverParams(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("lbfgs_m", c_int32), ("max_iter", c_int32),
                 ("max_halvings", c_int32), ("tol", c_double), ("c1", c_double),
                 ("noise_factor", c_double), ("cells_per_tile", c_int32), ("grid_blocks", c_int32),
-                ("inverse_bf16", c_int32)]
+                ("inverse_bf16", c_int32), ("volume_normaliser", c_int32)]
 
 
 class NetConfig(ctypes.Structure):
@@ -31,7 +31,7 @@ class NetConfig(ctypes.Structure):
 
 CELL_STATS_DTYPE = np.dtype([("iterations", np.int32), ("evaluations", np.int32),
                              ("status", np.uint32), ("halvings", np.int32), ("residual", np.float64),
-                             ("objective", np.float64), ("volume", np.float64)])
+                             ("objective", np.float64), ("volume", np.float64), ("area", np.float64)])
 
 STATS_TOTAL_DTYPE = np.dtype([("cell_steps", np.int64), ("iterations", np.int64), ("evaluations", np.int64),
                               ("halvings", np.int64), ("not_converged", np.int64), ("status_count", np.int64, (4,)),
@@ -39,7 +39,8 @@ STATS_TOTAL_DTYPE = np.dtype([("cell_steps", np.int64), ("iterations", np.int64)
 
 FP32, FP64 = 0, 1
 CONVERGED, MAXITER, LS_FAIL, NONFINITE, DEGENERATE_TRI = 1, 2, 4, 8, 16
-N_TERMS = 8
+N_TERMS = 11
+VOLUME_STEP_FROZEN, VOLUME_PAPER_LITERAL = 0, 1
 
 _P = c_void_p
 _SIGNATURES = {

@@ -191,6 +191,7 @@ void npfem_material_default(npfem_material* m) {
   m->kappa = 0.6;
   m->density = 1100.0;
   m->k_mat = -1.0;
+  m->k_area_global = 0.0;
 }
 
 void npfem_solver_params_default(npfem_solver_params* p) {
@@ -205,6 +206,7 @@ void npfem_solver_params_default(npfem_solver_params* p) {
   p->cells_per_tile = 0;
   p->grid_blocks = 0;
   p->inverse_bf16 = 0;
+  p->volume_normaliser = NPFEM_VOLUME_STEP_FROZEN;
 }
 
 npfem_status npfem_mesh_create(int32_t n, const double* xyz, int32_t nt, const int32_t* tris,
@@ -498,6 +500,7 @@ npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>&
     }
   }
   d.V0 = m->V0;
+  d.A0 = m->A0;
   d.floor_force = mp.floor_force;
   return NPFEM_OK;
 }
@@ -554,7 +557,9 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
     return fail(NPFEM_E_INVALID, "plan_create: bad solver controls");
   if (prm->cells_per_tile < 0 || prm->cells_per_tile > kMaxTile)
     return fail(NPFEM_E_INVALID, "plan_create: cells_per_tile must be in [0, 21]");
-  const double mats[] = {mat->B, mat->C, mat->D, mat->k_bend, mat->k_volume, mat->beta, mat->density};
+  if (prm->volume_normaliser != NPFEM_VOLUME_STEP_FROZEN && prm->volume_normaliser != NPFEM_VOLUME_PAPER_LITERAL)
+    return fail(NPFEM_E_INVALID, "plan_create: unknown volume_normaliser");
+  const double mats[] = {mat->B, mat->C, mat->D, mat->k_bend, mat->k_volume, mat->beta, mat->density, mat->k_area_global};
   for (double v : mats)
     if (!(v >= 0.0) || !std::isfinite(v)) return fail(NPFEM_E_INVALID, "plan_create: material constants must be finite and >= 0");
   if (!(mat->density > 0.0)) return fail(NPFEM_E_INVALID, "plan_create: density must be positive");
@@ -627,13 +632,13 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
       for (auto& [a, ca] : row)
         for (auto& [b, cb] : row) Lp[(size_t)a * n + b] += w * ca * cb;
     }
-    // M~ = M + beta h^2 L';  H~ = M~/h^2 + L' + k_volume I + K_mat
+    // M~ = M + beta h^2 L';  H~ = M~/h^2 + L' + (k_volume + k_area_global) I + K_mat
     std::vector<double> Mt((size_t)n * n), Ht((size_t)n * n);
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) {
         const size_t k = (size_t)i * n + j;
         Mt[k] = mat->beta * h * h * Lp[k] + (i == j ? mp.mass[i] : 0.0);
-        Ht[k] = Mt[k] / (h * h) + Lp[k] + Km[k] + (i == j ? mat->k_volume : 0.0);
+        Ht[k] = Mt[k] / (h * h) + Lp[k] + Km[k] + (i == j ? mat->k_volume + mat->k_area_global : 0.0);
       }
     if (!cholesky(Mt, n)) return fail(NPFEM_E_NOT_SPD, "plan_create: M~ is not positive definite");
     if (!cholesky(Ht, n)) return fail(NPFEM_E_NOT_SPD, "plan_create: H~ is not positive definite");
@@ -735,10 +740,12 @@ StepArgs<Real> make_args(npfem_batch* b) {
   npfem_plan* p = b->plan;
   StepArgs<Real> a{};
   a.meshes = static_cast<const MeshDev<Real>*>(p->d_meshdev);
-  a.mat = {p->mat.B, p->mat.C, p->mat.D, p->mat.k_bend, p->mat.k_volume, p->mat.beta, p->mat.kappa};
+  a.mat = {p->mat.B, p->mat.C, p->mat.D, p->mat.k_bend, p->mat.k_volume, p->mat.beta, p->mat.kappa,
+           p->mat.k_area_global};
   const double eps = std::is_same<Real, float>::value ? 1.1920928955078125e-07 : 2.220446049250313e-16;
   a.sol = {p->dt, p->prm.tol, p->prm.c1, p->prm.noise_factor * eps, b->m, p->prm.max_iter,
-           p->prm.max_halvings, (p->prm.inverse_bf16 && std::is_same<Real, float>::value) ? 1 : 0};
+           p->prm.max_halvings, (p->prm.inverse_bf16 && std::is_same<Real, float>::value) ? 1 : 0,
+           p->prm.volume_normaliser == NPFEM_VOLUME_PAPER_LITERAL ? 1 : 0};
   a.tiles = b->tiles;
   a.tile_cells = b->tile_cells;
   a.cell_voff = b->cell_voff;

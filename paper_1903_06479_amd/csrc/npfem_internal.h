@@ -10,7 +10,7 @@ namespace npfem {
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxHistory = 8;     // L-BFGS pairs
 constexpr int kMaxTile = 21;       // cells per tile: 3*21 = 63 rows <= 4 MFMA row blocks
-constexpr int kTerms = 8;          // objective terms reported by npfem_eval
+constexpr int kTerms = 11;         // objective terms reported by npfem_eval
 
 // Rest data of one mesh type on the device (precision Real).
 template <typename Real>
@@ -43,17 +43,19 @@ struct MeshDev {
   const float* hinv_diag;      // [n_pad] diagonal of H~^-1
   const float* minv_diag;      // [n_pad] diagonal of h^2 M~^-1
   double V0;                   // rest volume
+  double A0;                   // rest area
   double floor_force;          // B sqrt(A0): force floor of the residual
 };
 
 struct MaterialDev {
-  double B, C, D, k_bend, k_volume, beta, kappa;
+  double B, C, D, k_bend, k_volume, beta, kappa, k_area_global;
 };
 
 struct SolverDev {
   double h, tol, c1, noise;    // noise = noise_factor * machine epsilon
   int m, max_iter, max_halvings;
   int bf16;                    // products with the inverses on the BF16 matrix cores
+  int literal;                 // volume normaliser at the current x (else frozen at x_n)
 };
 
 // Per-cell scalar state of the step for a history of at most H pairs (the arrays are
@@ -64,11 +66,13 @@ struct CellStateT {
   double E;                    // objective at the current iterate
   double noise;                // sum of |terms| of E (line-search rounding scale)
   double Gn;                   // |grad V(x_n)|^2
+  double GA;                   // |grad A(x_n)|^2 (global-area term)
   double resid;
   double rho[H];
   double alpha[H];
   double SY[H][H];             // s_i . y_j over the history slots
   int hist_n, hist_head, iter, evals, status, active, retry, halvings;
+  int degen;                   // the current iterate has a collapsed triangle
 };
 using CellState = CellStateT<kMaxHistory>;
 

@@ -168,29 +168,66 @@ __device__ inline void stage_aos(Real* dst, const Real* src, int n, int np) {
   aos_to_soa(dst, n, np, [&](int e) { return src[e]; });
 }
 
+// Reciprocal and square root of the FP32 bulk arithmetic: the hardware instructions
+// (v_rcp_f32, v_sqrt_f32, about 1 ulp) instead of the correctly rounded sequences; the
+// FP64 path keeps the exact operations.
+template <typename Real> __device__ inline Real rcp_(Real x) { return Real(1) / x; }
+template <> __device__ inline float rcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename Real> __device__ inline Real sqrt_(Real x) { return sqrt(x); }
+template <> __device__ inline float sqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // ---------------------------------------------------------------------------------
-// Volume normaliser |grad V(x_n)|^2, grad V_k = nbar_k / 3 (section 2.1.2)
+// Normalisers of the global terms (section 2.1.2): |grad V|^2 with grad V_k = nbar_k / 3,
+// and (when accA is given) |grad A|^2 with grad A = sum over the incident triangles of
+// n x (the edge opposite the vertex) / 2, at x = x_n (+ u when ut is given).  Per chunk,
+// each triangle's contributions go to `work` (9 per triangle: the volume normal / 6 and
+// the area gradients of corners a and b, corner c taking minus their sum), then every
+// vertex gathers its corners into accV (and accA).
 // ---------------------------------------------------------------------------------
 template <typename Real>
-__device__ double volume_normaliser(const MeshDev<Real>& M, const Real* xn, Real* acc, Real* work,
-                                    double* red) {
+__device__ void normalisers(const MeshDev<Real>& M, const Real* xn, const Real* ut, Real* accV, Real* accA,
+                            Real* work, double* red, double& GV, double& GA) {
   const int n = M.n, np = M.n_pad, nt = M.nt, ch = M.chunk;
-  for (int e = tid(); e < 3 * np; e += kBlock) acc[e] = Real(0);
+  const bool area = accA != nullptr;
+  for (int e = tid(); e < 3 * np; e += kBlock) {
+    accV[e] = Real(0);
+    if (area) accA[e] = Real(0);
+  }
   for (int t0 = 0; t0 < nt; t0 += ch) {
     __syncthreads();
     const int tn = min(ch, nt - t0);
     for (int tt = tid(); tt < tn; tt += kBlock) {
       const int t = t0 + tt;
       const int a = gld(M.tri, 3 * t), b = gld(M.tri, 3 * t + 1), c = gld(M.tri, 3 * t + 2);
-      const Real e1x = xn[a] - xn[c], e1y = xn[np + a] - xn[np + c], e1z = xn[2 * np + a] - xn[2 * np + c];
-      const Real e2x = xn[b] - xn[c], e2y = xn[np + b] - xn[np + c], e2z = xn[2 * np + b] - xn[2 * np + c];
-      work[tt] = (e1y * e2z - e1z * e2y) / Real(6);
-      work[ch + tt] = (e1z * e2x - e1x * e2z) / Real(6);
-      work[2 * ch + tt] = (e1x * e2y - e1y * e2x) / Real(6);
+      Real e1x = xn[a] - xn[c], e1y = xn[np + a] - xn[np + c], e1z = xn[2 * np + a] - xn[2 * np + c];
+      Real e2x = xn[b] - xn[c], e2y = xn[np + b] - xn[np + c], e2z = xn[2 * np + b] - xn[2 * np + c];
+      if (ut) {
+        e1x += ut[a] - ut[c]; e1y += ut[np + a] - ut[np + c]; e1z += ut[2 * np + a] - ut[2 * np + c];
+        e2x += ut[b] - ut[c]; e2y += ut[np + b] - ut[np + c]; e2z += ut[2 * np + b] - ut[2 * np + c];
+      }
+      const Real nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+      work[tt] = nx / Real(6);
+      work[ch + tt] = ny / Real(6);
+      work[2 * ch + tt] = nz / Real(6);
+      if (area) {
+        // a collapsed triangle (area below 1e-6 of its rest area) has no normal and adds
+        // nothing to the area gradient
+        const Real nn2 = nx * nx + ny * ny + nz * nz;
+        const bool collapsed = (double)nn2 * gld(M.inv4a2, t) < 1e-12;   // (area ratio)^2
+        const Real nn = sqrt_(nn2);
+        const Real s = nn > Real(0) && !collapsed ? Real(0.5) * rcp_(nn) : Real(0);
+        const Real hx = s * nx, hy = s * ny, hz = s * nz;       // n / 2
+        work[3 * ch + tt] = -(hy * e2z - hz * e2y);              // corner a: -(n/2) x e2
+        work[4 * ch + tt] = -(hz * e2x - hx * e2z);
+        work[5 * ch + tt] = -(hx * e2y - hy * e2x);
+        work[6 * ch + tt] = hy * e1z - hz * e1y;                 // corner b: (n/2) x e1
+        work[7 * ch + tt] = hz * e1x - hx * e1z;
+        work[8 * ch + tt] = hx * e1y - hy * e1x;
+      }
     }
     __syncthreads();
     for (int i = tid(); i < n; i += kBlock) {
-      Real gx = 0, gy = 0, gz = 0;
+      Real gx = 0, gy = 0, gz = 0, ax = 0, ay = 0, az = 0;
       // incident corners from the ELL list, a group of indices in flight together;
       // padding and corners outside this chunk add zero
       for (int q0 = 0; q0 < M.vc_deg; q0 += kEllGroup) {
@@ -201,45 +238,53 @@ __device__ double volume_normaliser(const MeshDev<Real>& M, const Real* xn, Real
 #pragma unroll
         for (int u = 0; u < kEllGroup; ++u) {
           const int cid = cc[u];
-          const int t = cid / 3 - t0;
+          const int tri = cid / 3, k = cid - 3 * tri, t = tri - t0;
           const bool ok = cid >= 0 && t >= 0 && t < tn;
           const int tc = ok ? t : 0;
-          const Real wx = work[tc], wy = work[ch + tc], wz = work[2 * ch + tc];
-          gx += ok ? wx : Real(0);
-          gy += ok ? wy : Real(0);
-          gz += ok ? wz : Real(0);
+          gx += ok ? work[tc] : Real(0);
+          gy += ok ? work[ch + tc] : Real(0);
+          gz += ok ? work[2 * ch + tc] : Real(0);
+          if (area) {
+            const Real sg = ok ? (k == 2 ? Real(-1) : Real(1)) : Real(0);
+            const Real pax = work[3 * ch + tc], pay = work[4 * ch + tc], paz = work[5 * ch + tc];
+            const Real pbx = work[6 * ch + tc], pby = work[7 * ch + tc], pbz = work[8 * ch + tc];
+            ax += sg * (k == 0 ? pax : (k == 1 ? pbx : pax + pbx));
+            ay += sg * (k == 0 ? pay : (k == 1 ? pby : pay + pby));
+            az += sg * (k == 0 ? paz : (k == 1 ? pbz : paz + pbz));
+          }
         }
       }
-      acc[i] += gx;
-      acc[np + i] += gy;
-      acc[2 * np + i] += gz;
+      accV[i] += gx;
+      accV[np + i] += gy;
+      accV[2 * np + i] += gz;
+      if (area) {
+        accA[i] += ax;
+        accA[np + i] += ay;
+        accA[2 * np + i] += az;
+      }
     }
   }
   __syncthreads();
-  double s[1] = {0.0};
-  for (int i = tid(); i < n; i += kBlock)
-    s[0] += (double)acc[i] * acc[i] + (double)acc[np + i] * acc[np + i] + (double)acc[2 * np + i] * acc[2 * np + i];
-  block_sum<1>(s, red);
-  return s[0];
+  double sm[2] = {0.0, 0.0};
+  for (int i = tid(); i < n; i += kBlock) {
+    sm[0] += (double)accV[i] * accV[i] + (double)accV[np + i] * accV[np + i] + (double)accV[2 * np + i] * accV[2 * np + i];
+    if (area)
+      sm[1] += (double)accA[i] * accA[i] + (double)accA[np + i] * accA[np + i] + (double)accA[2 * np + i] * accA[2 * np + i];
+  }
+  block_sum<2>(sm, red);
+  GV = sm[0];
+  GA = area ? sm[1] : 1.0;
 }
 
 // ---------------------------------------------------------------------------------
 // Objective and gradient at x = x_n + u (eq. GeneralizedObjectiveFunctionDerivative)
 // ---------------------------------------------------------------------------------
 struct EvalResult {
-  double E, noise, resid, vol;
-  double terms[6];   // inertial, area, Skalak, bending(+Rayleigh), volume, triangle Rayleigh
+  double E, noise, resid, vol, area, degen;
+  double terms[7];   // inertial, area, Skalak, bending(+Rayleigh), volume, triangle Rayleigh, global area
 };
 
 // SL(2) projection of the singular values (section 2.1.2): t = 1 + tau, the largest
-// Reciprocal and square root of the FP32 bulk arithmetic: the hardware instructions
-// (v_rcp_f32, v_sqrt_f32, about 1 ulp) instead of the correctly rounded sequences; the
-// FP64 path keeps the exact operations.
-template <typename Real> __device__ inline Real rcp_(Real x) { return Real(1) / x; }
-template <> __device__ inline float rcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <typename Real> __device__ inline Real sqrt_(Real x) { return sqrt(x); }
-template <> __device__ inline float sqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
-
 // root of t^4 - s1 t^3 + s2 t - 1, written in deviations s_i = 1 + a_i so that small
 // strains lose no digits:  f(tau) = (1+tau)^3 (tau - a1) + tau (1 + a2) + a2.
 // f is convex for t >= s1/2 and f(s1/2) <= 0, so Newton from any start right of the
@@ -267,29 +312,45 @@ __device__ inline Real sl2_tau(Real a1, Real a2, Real sig1, Real J) {
 }
 
 template <typename Real>
-__device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double h, double Gn,
-                         const Real* xn, const Real* ut, const Real* bvec, Real* work, Real* gout,
+__device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool literal, double h, double Gn,
+                         double GA, const Real* xn, const Real* ut, const Real* bvec, Real* work, Real* gout,
                          double* red, EvalResult& res) {
   const int n = M.n, np = M.n_pad, nt = M.nt, ch = M.chunk;
   const Real inv_h2 = Real(1.0 / (h * h));
   const Real beta = Real(mat.beta), kb = Real(mat.k_bend);
   const Real Cst = Real(mat.C), Bsk = Real(mat.B), Dsk = Real(mat.D);
 
-  // xn, ut, bvec and gout are the cell's vectors in LDS.  The corner buffer holds, per
-  // triangle, the in-plane gradient of corners a and b (6 values; corner c gets minus
-  // their sum) and the normal e1 x e2 (3 values; the volume gradient of each corner is
-  // a sixth of it).  When all triangles fit one chunk the enclosed volume is summed in
-  // the triangle pass itself; otherwise it is summed first, in a pass of its own.
+  // xn, ut, bvec and gout are the cell's vectors (in LDS unless the mesh is too large).
+  // The corner buffer holds, per triangle, the in-plane gradient of corners a and b (6
+  // values; corner c gets minus their sum; with the global-area term switched on it
+  // includes that term's gradient) and the normal e1 x e2 (3 values; the volume
+  // gradient of each corner is a sixth of it).  When all triangles fit one chunk and no
+  // global-area term needs the total area beforehand, the enclosed volume and area are
+  // summed in the triangle pass itself; otherwise first, in a pass of their own.
   const bool single = nt <= ch;
-  // ---- pass A: (volume when chunked) and bending residuals R_i -> work -------------
-  double accA[3] = {0.0, 0.0, 0.0};   // volume, bending energy, bending Rayleigh energy
-  if (!single) {
+  const bool area_on = mat.k_area_global > 0.0;
+  const bool pre = !single || area_on;
+  // ---- literal volume normaliser: |grad V|^2 at the trial point (gout as scratch) ---
+  if (literal) {
+    double gv, ga;
+    normalisers(M, xn, ut, gout, static_cast<Real*>(nullptr), work, red, gv, ga);
+    Gn = gv;
+  }
+  // ---- pass A: (volume and area when needed first) and bending residuals -> work ----
+  double accA[4] = {0.0, 0.0, 0.0, 0.0};   // 6 volume, bending energy, bending Rayleigh energy, 2 area
+  if (pre) {
     for (int t = tid(); t < nt; t += kBlock) {
       const int a = gld(M.tri, 3 * t), b = gld(M.tri, 3 * t + 1), c = gld(M.tri, 3 * t + 2);
-      const double ax = (double)xn[a] + ut[a], ay = (double)xn[np + a] + ut[np + a], az = (double)xn[2 * np + a] + ut[2 * np + a];
-      const double bx = (double)xn[b] + ut[b], by = (double)xn[np + b] + ut[np + b], bz = (double)xn[2 * np + b] + ut[2 * np + b];
+      const double E1x = ((double)xn[a] - (double)xn[c]) + ((double)ut[a] - (double)ut[c]);
+      const double E1y = ((double)xn[np + a] - (double)xn[np + c]) + ((double)ut[np + a] - (double)ut[np + c]);
+      const double E1z = ((double)xn[2 * np + a] - (double)xn[2 * np + c]) + ((double)ut[2 * np + a] - (double)ut[2 * np + c]);
+      const double E2x = ((double)xn[b] - (double)xn[c]) + ((double)ut[b] - (double)ut[c]);
+      const double E2y = ((double)xn[np + b] - (double)xn[np + c]) + ((double)ut[np + b] - (double)ut[np + c]);
+      const double E2z = ((double)xn[2 * np + b] - (double)xn[2 * np + c]) + ((double)ut[2 * np + b] - (double)ut[2 * np + c]);
       const double cx = (double)xn[c] + ut[c], cy = (double)xn[np + c] + ut[np + c], cz = (double)xn[2 * np + c] + ut[2 * np + c];
-      accA[0] += ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
+      accA[0] += E1x * (E2y * cz - E2z * cy) + E1y * (E2z * cx - E2x * cz) + E1z * (E2x * cy - E2y * cx);
+      const double Nx = E1y * E2z - E1z * E2y, Ny = E1z * E2x - E1x * E2z, Nz = E1x * E2y - E1y * E2x;
+      accA[3] += sqrt(Nx * Nx + Ny * Ny + Nz * Nz);
     }
   }
   for (int i = tid(); i < n; i += kBlock) {
@@ -338,11 +399,13 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     work[np + i] = ry + beta * uy;
     work[2 * np + i] = rz + beta * uz;
   }
-  double coefd = 0.0, vol = 0.0;
-  if (!single) {
-    block_sum<3>(accA, red);
+  double coefd = 0.0, vol = 0.0, area = 0.0, coefa = 0.0;
+  if (pre) {
+    block_sum<4>(accA, red);
     vol = accA[0] / 6.0;
+    area = 0.5 * accA[3];
     coefd = mat.k_volume * (vol - M.V0) / Gn;               // k C / G_n
+    coefa = area_on ? mat.k_area_global * (area - M.A0) / GA : 0.0;
   } else {
     double ab[2] = {accA[1], accA[2]};
     block_sum<2>(ab, red);                                   // also the barrier before pass B
@@ -391,7 +454,9 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
   __syncthreads();   // work (R) is reused for the corner chunks below
 
   // ---- passes C/D: triangle in-plane terms + volume, per chunk --------------------
-  double accC[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // area PD, Skalak, triangle Rayleigh, |u.b|, 6 volume
+  // area PD, Skalak, triangle Rayleigh, |u.b|, 6 volume, 2 area, collapsed triangles
+  double accC[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const Real ca = Real(0.5 * coefa);               // global area: k_A (A - A0) / G_A / 2
   double accD[4] = {0.0, 0.0, 0.0, 0.0};   // |grad|^2, |M u/h^2|^2, |b|^2, |F_int|^2
   for (int t0 = 0; t0 < nt; t0 += ch) {
     const int tn = min(ch, nt - t0);
@@ -439,6 +504,9 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       const Real c01 = Real(C01);
       const Real nx = Real(Nx), ny = Real(Ny), nz = Real(Nz);
       const Real nn = sqrt_(Real(NN));
+      // a collapsed triangle (area below 1e-6 of its rest area) has no second in-plane
+      // direction: u2 below is taken as zero, so that direction carries no force
+      const bool collapsed = NN * i4a2_t < 1e-12;
       // area ratio J = sigma1 sigma2 = |e1 x e2| / (2 A0)
       const Real Jsq_m1 = Real(NN * i4a2_t - 1.0);
       const Real J = sqrt_(fmax(Real(1) + Jsq_m1, Real(0)));
@@ -465,7 +533,8 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       }
       const Real u1x = (f0x * vx + f1x * vy) * inv_s1, u1y = (f0y * vx + f1y * vy) * inv_s1, u1z = (f0z * vx + f1z * vy) * inv_s1;
       const Real inv_nn = nn > Real(1e-30) ? rcp_(nn) : Real(0);
-      const Real hx = nx * inv_nn, hy = ny * inv_nn, hz = nz * inv_nn;
+      const Real hx = collapsed ? Real(0) : nx * inv_nn, hy = collapsed ? Real(0) : ny * inv_nn,
+                 hz = collapsed ? Real(0) : nz * inv_nn;
       const Real u2x = hy * u1z - hz * u1y, u2y = hz * u1x - hx * u1z, u2z = hx * u1y - hy * u1x;
       // area PD: closest SL(2) element diag(t, 1/t)
       const Real tau = sl2_tau<Real>(a1, a2, sig1, J);
@@ -484,8 +553,21 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       const Real G1z = w1 * u1z * vy + w2 * u2z * vx + wr * g1z;
       // corner gradients [g_a g_b] = dE/dF D_m^-T, g_c = -g_a - g_b, plus the volume
       // gradient k C / G_n * (e1 x e2) / 6 on each corner
-      const Real gax = G0x * d00 + G1x * d01, gay = G0y * d00 + G1y * d01, gaz = G0z * d00 + G1z * d01;
-      const Real gbx = G0x * d10 + G1x * d11, gby = G0y * d10 + G1y * d11, gbz = G0z * d10 + G1z * d11;
+      Real gax = G0x * d00 + G1x * d01, gay = G0y * d00 + G1y * d01, gaz = G0z * d00 + G1z * d01;
+      Real gbx = G0x * d10 + G1x * d11, gby = G0y * d10 + G1y * d11, gbz = G0z * d10 + G1z * d11;
+      if (area_on) {
+        // global area: k_A (A - A0) / G_A times grad A_t, which is -(n/2) x e2 at corner a
+        // and (n/2) x e1 at corner b (n the unit normal, from the raw cross product)
+        const Real e1x = Real(E1x), e1y = Real(E1y), e1z = Real(E1z);
+        const Real e2x = Real(E2x), e2y = Real(E2y), e2z = Real(E2z);
+        const Real mx = ca * hx, my = ca * hy, mz = ca * hz;      // zero for a collapsed triangle
+        gax -= my * e2z - mz * e2y;
+        gay -= mz * e2x - mx * e2z;
+        gaz -= mx * e2y - my * e2x;
+        gbx += my * e1z - mz * e1y;
+        gby += mz * e1x - mx * e1z;
+        gbz += mx * e1y - my * e1x;
+      }
       work[0 * ch + tt] = gax;
       work[1 * ch + tt] = gay;
       work[2 * ch + tt] = gaz;
@@ -495,21 +577,24 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
       work[6 * ch + tt] = nx;
       work[7 * ch + tt] = ny;
       work[8 * ch + tt] = nz;
-      if (single) {
+      if (!pre) {
         // x_a . (x_b x x_c) = E1 . (E2 x x_c) with E1 = x_a - x_c, E2 = x_b - x_c (FP64)
         const double cx = (double)xc + (double)ucx, cy = (double)yc + (double)ucy, cz = (double)zc + (double)ucz;
         accC[4] += E1x * (E2y * cz - E2z * cy) + E1y * (E2z * cx - E2x * cz) + E1z * (E2x * cy - E2y * cx);
+        accC[5] += sqrt(NN);
       }
+      accC[6] += collapsed ? 1.0 : 0.0;
       accC[0] += 0.5 * (double)(Cst * A0) * ((double)dA1 * dA1 + (double)dA2 * dA2);
       accC[1] += (double)A0 * (0.125 * (double)Bsk * ((double)s1m * s1m + (double)s2m * s2m)
                                + 0.25 * (double)Dsk * ((double)a1 * a1 * a1 * a1 + (double)a2 * a2 * a2 * a2));
       accC[2] += 0.5 * (double)wr * ((double)g0x * g0x + (double)g0y * g0y + (double)g0z * g0z
                                      + (double)g1x * g1x + (double)g1y * g1y + (double)g1z * g1z);
     }
-    if (single) {
-      double vv[1] = {accC[4]};
-      block_sum<1>(vv, red);                  // also the barrier before the gather
+    if (!pre) {
+      double vv[2] = {accC[4], accC[5]};
+      block_sum<2>(vv, red);                  // also the barrier before the gather
       vol = vv[0] / 6.0;
+      area = 0.5 * vv[1];
       coefd = mat.k_volume * (vol - M.V0) / Gn;
     } else {
       __syncthreads();
@@ -571,21 +656,25 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, double 
     }
     __syncthreads();
   }
-  const double Cv = vol - M.V0;
+  const double Cv = vol - M.V0, Ca = area - M.A0;
   const double e_vol = 0.5 * mat.k_volume * Cv * Cv / Gn;
-  double acc[9] = {accB[0], accC[0], accC[1], accC[2], accC[3], accD[0], accD[1], accD[2], accD[3]};
-  block_sum<9>(acc, red);
+  const double e_area = area_on ? 0.5 * mat.k_area_global * Ca * Ca / GA : 0.0;
+  double acc[10] = {accB[0], accC[0], accC[1], accC[2], accC[3], accD[0], accD[1], accD[2], accD[3], accC[6]};
+  block_sum<10>(acc, red);
   const double inertial = acc[0];
   res.vol = vol;
+  res.area = area;
+  res.degen = acc[9];
   res.terms[0] = inertial;
   res.terms[1] = acc[1];
   res.terms[2] = acc[2];
   res.terms[3] = accA[1] + accA[2];
   res.terms[4] = e_vol;
   res.terms[5] = acc[3];
-  res.E = inertial + acc[1] + acc[2] + accA[1] + accA[2] + e_vol + acc[3];
+  res.terms[6] = e_area;
+  res.E = inertial + acc[1] + acc[2] + accA[1] + accA[2] + e_vol + acc[3] + e_area;
   // rounding scale of E: the sum of the magnitudes of its terms
-  res.noise = fabs(inertial) + 2.0 * acc[4] + acc[1] + acc[2] + accA[1] + accA[2] + e_vol + acc[3];
+  res.noise = fabs(inertial) + 2.0 * acc[4] + acc[1] + acc[2] + accA[1] + accA[2] + e_vol + acc[3] + e_area;
   const double num = sqrt(acc[5]);
   const double den = sqrt(acc[6]) + sqrt(acc[7]) + sqrt(acc[8]) + M.floor_force;
   res.resid = num == 0.0 ? 0.0 : num / den;
@@ -927,11 +1016,12 @@ __device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, i
     npfem_cell_stats st;
     st.iterations = cs.iter;
     st.evaluations = cs.evals;
-    st.status = (uint32_t)cs.status;
+    st.status = (uint32_t)cs.status | ((cs.degen && !(cs.status & NPFEM_NONFINITE)) ? NPFEM_DEGENERATE_TRI : 0u);
     st.halvings = cs.halvings;
     st.residual = cs.resid;
     st.objective = cs.E;
     st.volume = bc[0];
+    st.area = bc[1];
     A.stats[cell] = st;
   }
 }
@@ -973,7 +1063,8 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
   const double h = A.sol.h;
   const int m = A.sol.m;
   const double eps = Eps<Real>::v;
-  __shared__ double s_vol[kMaxTile];
+  __shared__ double s_vol[kMaxTile], s_area[kMaxTile];
+  const bool area_on = A.mat.k_area_global > 0.0, literal = A.sol.literal != 0;
   // per cell: gradient and b in LDS, or (meshes too large for that) in the workspace
   auto gvec = [&](int j) { return vl ? gl : tl.vec(VS0 + 2 * m, j); };
   auto bvec = [&](int j) { return vl ? bl : tl.vec(VB, j); };
@@ -990,11 +1081,16 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
       aos_to_soa(tl.vec(VU, j), n, np, [&](int e) { return gs[e]; });
     }
     __syncthreads();
-    const double Gn = volume_normaliser(M, xn, ut, work, red);
+    // normalisers at x_n (ut and, for the area term, the cell's gradient vector are free
+    // until the first evaluation)
+    double Gn, GA;
+    normalisers(M, xn, static_cast<const Real*>(nullptr), ut, area_on ? gvec(j) : static_cast<Real*>(nullptr),
+                work, red, Gn, GA);
     if (tid() == 0) {
       auto& cs = CS[j];
       cs.Gn = Gn;
-      cs.hist_n = cs.hist_head = cs.iter = cs.evals = cs.status = cs.retry = cs.halvings = 0;
+      cs.GA = GA;
+      cs.hist_n = cs.hist_head = cs.iter = cs.evals = cs.status = cs.retry = cs.halvings = cs.degen = 0;
       cs.active = 1;
     }
     __syncthreads();
@@ -1026,7 +1122,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
     if (vl) vcopy(bl, tl.vec(VB, j), len);
     __syncthreads();
     EvalResult r;
-    evaluate(M, A.mat, h, CS[j].Gn, xn, ut, bvec(j), work, gvec(j), red, r);
+    evaluate(M, A.mat, literal, h, CS[j].Gn, CS[j].GA, xn, ut, bvec(j), work, gvec(j), red, r);
     const bool bad = !isfinite(r.E) || !isfinite(r.resid);
     const bool done = bad || r.resid <= A.sol.tol;
     vcopy(tl.vec(VG, j), gvec(j), len);
@@ -1037,7 +1133,9 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
       cs.noise = r.noise;
       cs.resid = r.resid;
       cs.evals = 1;
+      cs.degen = r.degen > 0.0;
       s_vol[j] = r.vol;
+      s_area[j] = r.area;
       if (bad) { cs.status = NPFEM_NONFINITE; cs.active = 0; }
       else if (done) { cs.status = NPFEM_CONVERGED; cs.active = 0; }
     }
@@ -1203,7 +1301,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
           }
           __syncthreads();
         }
-        evaluate(M, A.mat, h, cs.Gn, xn, ut, bvec(j), work, GT, red, r);
+        evaluate(M, A.mat, literal, h, cs.Gn, cs.GA, xn, ut, bvec(j), work, GT, red, r);
         const double slack = A.sol.noise * fmax(cs.noise, r.noise);
         accepted = isfinite(r.E) && (r.E <= cs.E + A.sol.c1 * alpha * gd + slack);
         if (accepted) break;
@@ -1342,7 +1440,9 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
         cs.iter += 1;
         cs.evals += evals_add;
         cs.halvings += hv;
+        cs.degen = r.degen > 0.0;
         s_vol[j] = r.vol;
+        s_area[j] = r.area;
         if (conv) { cs.status = NPFEM_CONVERGED; cs.active = 0; }
         else if (out_of_iters) { cs.status = NPFEM_MAXITER; cs.active = 0; }
       }
@@ -1375,7 +1475,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
     stage_aos(xn, A.x + 3 * s_voff[j], n, np);
     vcopy(ut, tl.vec(VU, j), len);
     __syncthreads();
-    double bc[1] = {s_vol[j]};
+    double bc[2] = {s_vol[j], s_area[j]};
     auto cs = CS[j];
     finalize_cell(A, M, s_cell[j], s_voff[j], cs, xn, ut, red, bc);
     __syncthreads();
@@ -1433,12 +1533,14 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
   const Real* fs = A.f + 3 * voff;
   aos_to_soa(B, n, np, [&](int e) { return gld(M.mass, e / 3) * vs[e] / Real(A.sol.h) + fs[e]; });
   __syncthreads();
-  const double Gn = volume_normaliser(M, xn, ut, work, red);
+  double Gn, GA;
+  normalisers(M, xn, static_cast<const Real*>(nullptr), ut, A.mat.k_area_global > 0.0 ? G : static_cast<Real*>(nullptr),
+              work, red, Gn, GA);
   __syncthreads();
   stage_aos(ut, u + 3 * voff, n, np);
   __syncthreads();
   EvalResult r;
-  evaluate(M, A.mat, A.sol.h, Gn, xn, ut, B, work, G, red, r);
+  evaluate(M, A.mat, A.sol.literal != 0, A.sol.h, Gn, GA, xn, ut, B, work, G, red, r);
   for (int e = tid(); e < 3 * n; e += kBlock) {
     const int i = e / 3, c = e - 3 * i;
     grad[3 * voff + e] = G[c * np + i];
@@ -1448,6 +1550,9 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
     o[0] = r.E;
     for (int k = 0; k < 6; ++k) o[1 + k] = r.terms[k];
     o[7] = r.resid;
+    o[8] = r.terms[6];
+    o[9] = r.area;
+    o[10] = r.degen;
   }
 }
 

@@ -71,3 +71,36 @@ def test_host_rest_data_matches_oracle(n):
     np.testing.assert_allclose(rd["ell0"], m.ell0_norm, rtol=1e-9, atol=1e-12)
     np.testing.assert_allclose(rd["tri_area"], m.tri_area, rtol=1e-12)
     np.testing.assert_allclose(rd["dminv"], m.Dm_inv, rtol=1e-11, atol=1e-12)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets the C
+    compiler gives the header's structs."""
+    import ctypes
+    import subprocess
+    structs = {"npfem_material": N.Material, "npfem_solver_params": N.SolverParams,
+               "npfem_net_config": N.NetConfig}
+    np_structs = {"npfem_cell_stats": N.CELL_STATS_DTYPE, "npfem_stats_total": N.STATS_TOTAL_DTYPE}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "npfem.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    for name, dt in np_structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f in dt.names:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+    for name, dt in np_structs.items():
+        assert int(got[name]) == dt.itemsize, name
+        for f in dt.names:
+            assert int(got[f"{name}.{f}"]) == dt.fields[f][1], (name, f)
