@@ -266,6 +266,34 @@ npfem_status npfem_stats_accumulate(const npfem_cell_stats *stats, int64_t n_cel
 npfem_status npfem_stats_reset(npfem_stats_total *total, void *stream);
 
 /*
+ * Collision term between cells (section 4.7: a non-PD spring energy on colliding
+ * vertices, dropped at every iteration where the vertex no longer penetrates, with no
+ * share of H~).  npfem_collisions_detect finds, from the positions at the start of the
+ * step, for every vertex the nearest vertex of another cell closer than `cutoff`
+ * (ties: the smaller batch-wide vertex index), with a uniform grid of cell size
+ * `cutoff` hashed into a table of at least twice the vertex count:
+ *   cell_origin : device double [n_cells][3], world origin of each cell's local frame
+ *   x           : device [V_total][3] cell-local positions (plan precision)
+ *   contact_q   : device [V_total][3] out: the partner's position in the searching
+ *                 vertex's cell frame (plan precision; zero without a contact)
+ *   contact_n   : device [V_total][3] out: the partner's unit area-weighted vertex
+ *                 normal (zero without a contact)
+ *   n_contacts  : host, may be NULL: number of vertices with a contact (the call then
+ *                 synchronises the stream)
+ * The grid's buffers are allocated by the batch on the first call.
+ * npfem_step_contacts is npfem_step with the collision energy
+ *   (w_col/2) sum_i min((x_i - q_i) . n_i, 0)^2
+ * added to g, so that a vertex behind its partner's tangent plane is pushed out along
+ * the partner's normal (p_i = x_i - d_i n_i is its desired position) and the term
+ * vanishes once it is out.  Launched directly (not through the batch's graphs).
+ */
+npfem_status npfem_collisions_detect(npfem_batch *batch, const double *cell_origin, const void *x, double cutoff,
+                                     void *contact_q, void *contact_n, int64_t *n_contacts, void *stream);
+npfem_status npfem_step_contacts(npfem_batch *batch, const void *x, const void *v, const void *f_ext,
+                                 const void *contact_q, const void *contact_n, double w_col, void *x_out,
+                                 void *v_out, npfem_cell_stats *stats, void *stream);
+
+/*
  * npfem_step without any allocation, for callers that cannot allocate device memory
  * while they run: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same arguments, results and per-cell statistics as npfem_step

@@ -19,6 +19,7 @@ mesoscopic and continuum modeling of red blood cells for fully resolved blood fl
              GeneralizedObjectiveFunctionDerivative), first guess, L-BFGS with H~ as
              initial Hessian and halving line search (Algorithm 1), velocity update and
              the post-convergence dissipation (section 2.1.4)
+  collision.py  contact search between cells and the collision term (section 4.7)
   newton.py  brute-force Newton with a finite-difference Jacobian (test pin)
   mpnn.py    FP64 forward/backward of the learned warm-start network
 

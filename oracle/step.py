@@ -39,6 +39,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .model import Model
+from .collision import collision_energy
 from .energy import area_normaliser, collapsed_triangles, elastic_energy, volume_normaliser
 
 CONVERGED, MAXITER, LS_FAIL, NONFINITE, DEGENERATE_TRI = 1, 2, 4, 8, 16
@@ -71,8 +72,11 @@ class Objective:
     """g, grad g and the residual of one step (fixed x_n, v_n, F_ext).  literal: the
     volume term with the paper's normaliser at the current x instead of at x_n."""
 
-    def __init__(self, m: Model, x_n, v_n, f_ext, literal: bool = False):
+    def __init__(self, m: Model, x_n, v_n, f_ext, literal: bool = False, contacts=None):
+        """contacts: None or (q, nrm, w_col), the collision term of collision.py with the
+        partner positions q and normals nrm (cell-local) found at the start of the step."""
         self.m, self.x_n = m, np.asarray(x_n, np.float64)
+        self.contacts = contacts
         h = m.h
         self.b = m.mass[:, None] * np.asarray(v_n, np.float64) / h + np.asarray(f_ext, np.float64)
         # y_n = x_n + h M~^-1 M v_n + h^2 M~^-1 F_ext = x_n + h^2 M~^-1 b
@@ -89,6 +93,9 @@ class Objective:
         Mdx = m.Mt @ dx
         inertia = 0.5 * np.sum(dx * Mdx) / h ** 2
         E, gE, parts = elastic_energy(x, m, self.Gn, self.GA)
+        if self.contacts is not None:
+            Ec, gc = collision_energy(x, *self.contacts)
+            E, gE, parts = E + Ec, gE + gc, parts + [Ec]
         grad = Mdx / h ** 2 + gE
         noise = abs(inertia) + sum(abs(p) for p in parts)
         return inertia + E, grad, noise
@@ -225,9 +232,9 @@ def dissipate(x, v, mass, kappa):
     return v + kappa * dv
 
 
-def step(m: Model, x_n, v_n, f_ext, p: Params = Params(), x_start=None, literal: bool = False):
+def step(m: Model, x_n, v_n, f_ext, p: Params = Params(), x_start=None, literal: bool = False, contacts=None):
     """One npFEM step of one cell: returns (x_{n+1}, v_{n+1}, info)."""
-    obj = Objective(m, x_n, v_n, f_ext, literal)
+    obj = Objective(m, x_n, v_n, f_ext, literal, contacts)
     x0 = obj.y if x_start is None else np.asarray(x_start, np.float64)
     x, info = minimise(obj, x0, p)
     v = (x - obj.x_n) / m.h

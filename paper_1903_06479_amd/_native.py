@@ -65,6 +65,8 @@ _SIGNATURES = {
     "npfem_batch_graph_counts": (c_int32, [c_void_p, _P, _P]),
     "npfem_step": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P, _P]),
     "npfem_step_noalloc": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "npfem_collisions_detect": (c_int32, [c_void_p, _P, _P, c_double, _P, _P, _P, _P]),
+    "npfem_step_contacts": (c_int32, [c_void_p, _P, _P, _P, _P, _P, c_double, _P, _P, _P, _P]),
     "npfem_eval": (c_int32, [c_void_p, _P, _P, _P, _P, _P, _P, _P]),
     "npfem_stats_accumulate": (c_int32, [_P, c_int64, _P, _P]),
     "npfem_stats_reset": (c_int32, [_P, _P]),

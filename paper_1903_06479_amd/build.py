@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnpfem.so")
 
-SOURCES = ["npfem_host.cpp", "npfem_kernels.hip", "npfem_net.hip"]
+SOURCES = ["npfem_host.cpp", "npfem_kernels.hip", "npfem_net.hip", "npfem_collide.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions are kept out of the device code

@@ -723,6 +723,14 @@ struct npfem_batch {
   // learned warm start: the predicted correction of every vertex (allocated on first use)
   DeviceBuffers dbuf;
   void* delta = nullptr;
+  // contact search: hashed grid buffers (allocated on first use)
+  DeviceBuffers cbuf;
+  int64_t c_table = 0;
+  unsigned *c_count = nullptr, *c_start = nullptr, *c_fill = nullptr, *c_bsum = nullptr, *c_vkey = nullptr,
+           *c_sorted = nullptr;
+  int* c_vcell = nullptr;
+  double* c_normals = nullptr;
+  unsigned long long* c_ncontacts = nullptr;
   void drop_graph() {
     for (auto& g : graphs) {
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -915,9 +923,13 @@ namespace {
 
 npfem_status launch_step_now(npfem_batch* b, const void* x, const void* v, const void* f, void* x_out,
                              void* v_out, const void* u_guess, npfem_cell_stats* stats, hipStream_t s,
-                             const void* u_delta = nullptr, int guess_only = 0) {
+                             const void* u_delta = nullptr, int guess_only = 0, const void* col_q = nullptr,
+                             const void* col_n = nullptr, double w_col = 0.0) {
   if (b->plan->precision == NPFEM_FP64) {
     auto a = make_args<double>(b);
+    a.col_q = static_cast<const double*>(col_q);
+    a.col_n = static_cast<const double*>(col_n);
+    a.w_col = w_col;
     a.x = static_cast<const double*>(x);
     a.v = static_cast<const double*>(v);
     a.f = static_cast<const double*>(f);
@@ -930,6 +942,9 @@ npfem_status launch_step_now(npfem_batch* b, const void* x, const void* v, const
     HIP_TRY(launch_step<double>(a, b->grid, b->lds, s, b->counter));
   } else {
     auto a = make_args<float>(b);
+    a.col_q = static_cast<const float*>(col_q);
+    a.col_n = static_cast<const float*>(col_n);
+    a.w_col = w_col;
     a.x = static_cast<const float*>(x);
     a.v = static_cast<const float*>(v);
     a.f = static_cast<const float*>(f);
@@ -1004,6 +1019,98 @@ npfem_status npfem_step(npfem_batch* b, const void* x, const void* v, const void
   hipStream_t s = static_cast<hipStream_t>(stream);
   const void* const key[9] = {x, v, f, x_out, v_out, u_guess, stats, stream, nullptr};
   return run_maybe_graph(b, key, s, [&] { return launch_step_now(b, x, v, f, x_out, v_out, u_guess, stats, s); });
+}
+
+npfem_status npfem_step_contacts(npfem_batch* b, const void* x, const void* v, const void* f,
+                                 const void* contact_q, const void* contact_n, double w_col, void* x_out,
+                                 void* v_out, npfem_cell_stats* stats, void* stream) {
+  if (!b || !x || !v || !f || !contact_q || !contact_n || !x_out || !v_out)
+    return fail(NPFEM_E_INVALID, "step_contacts: NULL pointer");
+  if (!(w_col >= 0.0) || !std::isfinite(w_col)) return fail(NPFEM_E_INVALID, "step_contacts: w_col must be >= 0");
+  HIP_TRY(hipSetDevice(b->plan->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return launch_step_now(b, x, v, f, x_out, v_out, nullptr, stats, s, nullptr, 0, contact_q, contact_n, w_col);
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename Real>
+npfem_status collide_now(npfem_batch* b, const double* origin, const void* x, double cutoff, void* q, void* n,
+                         hipStream_t s) {
+  CollideArgs<Real> a{};
+  a.meshes = static_cast<const MeshDev<Real>*>(b->plan->d_meshdev);
+  a.cell_voff = b->cell_voff;
+  a.cell_mesh = b->cell_mesh;
+  a.mesh_n = b->mesh_n;
+  a.origin = origin;
+  a.x = static_cast<const Real*>(x);
+  a.cutoff = cutoff;
+  a.inv_h = 1.0 / cutoff;
+  a.mask = (unsigned)(b->c_table - 1);
+  a.count = b->c_count;
+  a.start = b->c_start;
+  a.fill = b->c_fill;
+  a.bsum = b->c_bsum;
+  a.vkey = b->c_vkey;
+  a.vcell = b->c_vcell;
+  a.sorted = b->c_sorted;
+  a.normals = b->c_normals;
+  a.q = static_cast<Real*>(q);
+  a.n = static_cast<Real*>(n);
+  a.n_contacts = b->c_ncontacts;
+  HIP_TRY(launch_collide<Real>(a, (int)b->n_cells, b->n_vert, s));
+  return NPFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+npfem_status npfem_collisions_detect(npfem_batch* b, const double* cell_origin, const void* x, double cutoff,
+                                     void* contact_q, void* contact_n, int64_t* n_contacts, void* stream) {
+  if (!b || !cell_origin || !x || !contact_q || !contact_n) return fail(NPFEM_E_INVALID, "collisions_detect: NULL pointer");
+  if (!(cutoff > 0.0) || !std::isfinite(cutoff)) return fail(NPFEM_E_INVALID, "collisions_detect: cutoff must be > 0");
+  if (b->n_vert > (int64_t)1 << 31) return fail(NPFEM_E_UNSUPPORTED, "collisions_detect: more than 2^31 vertices");
+  HIP_TRY(hipSetDevice(b->plan->device));
+  if (!b->c_count) {
+    int64_t table = 1024;
+    while (table < 2 * b->n_vert) table *= 2;
+    const int nb = collide_scan_blocks(table);
+    void* p;
+    npfem_status st;
+    if ((st = b->cbuf.alloc(table * sizeof(unsigned), &p))) return st;
+    b->c_count = static_cast<unsigned*>(p);
+    if ((st = b->cbuf.alloc(table * sizeof(unsigned), &p))) return st;
+    b->c_start = static_cast<unsigned*>(p);
+    if ((st = b->cbuf.alloc(table * sizeof(unsigned), &p))) return st;
+    b->c_fill = static_cast<unsigned*>(p);
+    if ((st = b->cbuf.alloc((size_t)nb * sizeof(unsigned), &p))) return st;
+    b->c_bsum = static_cast<unsigned*>(p);
+    if ((st = b->cbuf.alloc(b->n_vert * sizeof(unsigned), &p))) return st;
+    b->c_vkey = static_cast<unsigned*>(p);
+    if ((st = b->cbuf.alloc(b->n_vert * sizeof(unsigned), &p))) return st;
+    b->c_sorted = static_cast<unsigned*>(p);
+    if ((st = b->cbuf.alloc(b->n_vert * sizeof(int), &p))) return st;
+    b->c_vcell = static_cast<int*>(p);
+    if ((st = b->cbuf.alloc(b->n_vert * 3 * sizeof(double), &p))) return st;
+    b->c_normals = static_cast<double*>(p);
+    if ((st = b->cbuf.alloc(sizeof(unsigned long long), &p))) return st;
+    b->c_ncontacts = static_cast<unsigned long long*>(p);
+    b->c_table = table;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  npfem_status st = b->plan->precision == NPFEM_FP64 ? collide_now<double>(b, cell_origin, x, cutoff, contact_q, contact_n, s)
+                                                     : collide_now<float>(b, cell_origin, x, cutoff, contact_q, contact_n, s);
+  if (st) return st;
+  if (n_contacts) {
+    unsigned long long c = 0;
+    HIP_TRY(hipMemcpyAsync(&c, b->c_ncontacts, sizeof(c), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_contacts = (int64_t)c;
+  }
+  return NPFEM_OK;
 }
 
 npfem_status npfem_step_noalloc(npfem_batch* b, const void* x, const void* v, const void* f, void* x_out,

@@ -113,11 +113,41 @@ struct StepArgs {
   const Real* f;
   const Real* u_guess;         // nullable: start from x_n + u_guess instead of the first guess
   const Real* u_delta;         // nullable: start from the first guess + u_delta (learned correction)
+  const Real* col_q;           // nullable: [V][3] contact partner of each vertex (cell frame)
+  const Real* col_n;           //           [V][3] its normal (zero: no contact)
+  double w_col;                //           weight of the collision term
   int guess_only;              // write the first guess y_n - x_n to x_out and stop
   Real* x_out;
   Real* v_out;
   npfem_cell_stats* stats;     // nullable
 };
+
+// Contact search between cells (npfem_collide.hip).
+template <typename Real>
+struct CollideArgs {
+  const MeshDev<Real>* meshes;
+  const int64_t* cell_voff;
+  const int* cell_mesh;
+  const int* mesh_n;
+  const double* origin;        // [n_cells][3] world origin of each cell
+  const Real* x;               // [V][3] cell-local positions
+  double cutoff, inv_h;        // contact distance; 1 / grid cell size (= 1 / cutoff)
+  unsigned mask;               // hash table size - 1 (a power of two)
+  unsigned* count;             // [table] vertices per bucket
+  unsigned* start;             // [table] first slot of each bucket
+  unsigned* fill;              // [table] slots filled so far
+  unsigned* bsum;              // [scan blocks] block sums of the scan
+  unsigned* vkey;              // [V] bucket of each vertex
+  int* vcell;                  // [V] cell of each vertex
+  unsigned* sorted;            // [V] vertices ordered by bucket
+  double* normals;             // [V][3] unit area-weighted vertex normals
+  Real* q;                     // [V][3] out: partner position in the vertex's cell frame
+  Real* n;                     // [V][3] out: partner normal (zero: no contact)
+  unsigned long long* n_contacts;  // out: number of vertices with a contact
+};
+template <typename Real>
+hipError_t launch_collide(const CollideArgs<Real>& a, int n_cells, int64_t n_vert, hipStream_t s);
+int collide_scan_blocks(int64_t table);
 
 // Launch wrappers (npfem_kernels.hip).
 template <typename Real>

@@ -281,7 +281,16 @@ __device__ void normalisers(const MeshDev<Real>& M, const Real* xn, const Real* 
 // ---------------------------------------------------------------------------------
 struct EvalResult {
   double E, noise, resid, vol, area, degen;
-  double terms[7];   // inertial, area, Skalak, bending(+Rayleigh), volume, triangle Rayleigh, global area
+  double terms[8];   // inertial, area, Skalak, bending(+Rayleigh), volume, triangle Rayleigh, global area, collision
+};
+
+// Collision term of one cell (section 4.7): per vertex the partner q and its normal n
+// found at the start of the step (AoS [n][3], global; n = 0 where there is none), weight w.
+template <typename Real>
+struct Contacts {
+  const Real* q;
+  const Real* n;
+  double w;
 };
 
 // SL(2) projection of the singular values (section 2.1.2): t = 1 + tau, the largest
@@ -313,8 +322,8 @@ __device__ inline Real sl2_tau(Real a1, Real a2, Real sig1, Real J) {
 
 template <typename Real>
 __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool literal, double h, double Gn,
-                         double GA, const Real* xn, const Real* ut, const Real* bvec, Real* work, Real* gout,
-                         double* red, EvalResult& res) {
+                         double GA, const Contacts<Real>& col, const Real* xn, const Real* ut, const Real* bvec,
+                         Real* work, Real* gout, double* red, EvalResult& res) {
   const int n = M.n, np = M.n_pad, nt = M.nt, ch = M.chunk;
   const Real inv_h2 = Real(1.0 / (h * h));
   const Real beta = Real(mat.beta), kb = Real(mat.k_bend);
@@ -413,8 +422,11 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool li
     accA[2] = ab[1];
   }
 
-  // ---- pass B: bending gradient + inertia - b -> gout ----------------------------
-  double accB[1] = {0.0};
+  // ---- pass B: bending gradient + inertia - b (+ collision) -> gout -----------------
+  // collision: (w/2) min(d, 0)^2 per vertex with d = (x - q) . n, gradient w min(d, 0) n;
+  // the term drops out wherever the vertex no longer penetrates
+  double accB[2] = {0.0, 0.0};
+  const Real wc = Real(col.w);
   for (int i = tid(); i < n; i += kBlock) {
     Real gx = 0, gy = 0, gz = 0;
     const Real rix = work[i], riy = work[np + i], riz = work[2 * np + i];
@@ -444,9 +456,20 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool li
     const Real mi = mass * inv_h2;
     const Real ux = ut[i], uy = ut[np + i], uz = ut[2 * np + i];
     const Real bx = bvec[i], by = bvec[np + i], bz = bvec[2 * np + i];
-    gout[i] = kb * gx + (mi * ux - bx);
-    gout[np + i] = kb * gy + (mi * uy - by);
-    gout[2 * np + i] = kb * gz + (mi * uz - bz);
+    Real ox = kb * gx + (mi * ux - bx), oy = kb * gy + (mi * uy - by), oz = kb * gz + (mi * uz - bz);
+    if (col.n) {
+      const Real cnx = gld(col.n, 3 * i), cny = gld(col.n, 3 * i + 1), cnz = gld(col.n, 3 * i + 2);
+      const Real cqx = gld(col.q, 3 * i), cqy = gld(col.q, 3 * i + 1), cqz = gld(col.q, 3 * i + 2);
+      const Real dd = ((xn[i] - cqx) + ux) * cnx + ((xn[np + i] - cqy) + uy) * cny + ((xn[2 * np + i] - cqz) + uz) * cnz;
+      const Real dm = dd < Real(0) ? dd : Real(0);
+      ox += wc * dm * cnx;
+      oy += wc * dm * cny;
+      oz += wc * dm * cnz;
+      accB[1] += 0.5 * col.w * (double)dm * dm;
+    }
+    gout[i] = ox;
+    gout[np + i] = oy;
+    gout[2 * np + i] = oz;
     accB[0] += 0.5 * (double)mi * ((double)ux * ux + (double)uy * uy + (double)uz * uz)
                - ((double)ux * bx + (double)uy * by + (double)uz * bz);
   }
@@ -659,8 +682,9 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool li
   const double Cv = vol - M.V0, Ca = area - M.A0;
   const double e_vol = 0.5 * mat.k_volume * Cv * Cv / Gn;
   const double e_area = area_on ? 0.5 * mat.k_area_global * Ca * Ca / GA : 0.0;
-  double acc[10] = {accB[0], accC[0], accC[1], accC[2], accC[3], accD[0], accD[1], accD[2], accD[3], accC[6]};
-  block_sum<10>(acc, red);
+  double acc[11] = {accB[0], accC[0], accC[1], accC[2], accC[3], accD[0], accD[1], accD[2], accD[3], accC[6], accB[1]};
+  block_sum<11>(acc, red);
+  const double e_col = acc[10];
   const double inertial = acc[0];
   res.vol = vol;
   res.area = area;
@@ -672,9 +696,10 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool li
   res.terms[4] = e_vol;
   res.terms[5] = acc[3];
   res.terms[6] = e_area;
-  res.E = inertial + acc[1] + acc[2] + accA[1] + accA[2] + e_vol + acc[3] + e_area;
+  res.terms[7] = e_col;
+  res.E = inertial + acc[1] + acc[2] + accA[1] + accA[2] + e_vol + acc[3] + e_area + e_col;
   // rounding scale of E: the sum of the magnitudes of its terms
-  res.noise = fabs(inertial) + 2.0 * acc[4] + acc[1] + acc[2] + accA[1] + accA[2] + e_vol + acc[3] + e_area;
+  res.noise = fabs(inertial) + 2.0 * acc[4] + acc[1] + acc[2] + accA[1] + accA[2] + e_vol + acc[3] + e_area + e_col;
   const double num = sqrt(acc[5]);
   const double den = sqrt(acc[6]) + sqrt(acc[7]) + sqrt(acc[8]) + M.floor_force;
   res.resid = num == 0.0 ? 0.0 : num / den;
@@ -1065,6 +1090,10 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
   const double eps = Eps<Real>::v;
   __shared__ double s_vol[kMaxTile], s_area[kMaxTile];
   const bool area_on = A.mat.k_area_global > 0.0, literal = A.sol.literal != 0;
+  auto contacts = [&](int j) {
+    return A.col_n ? Contacts<Real>{A.col_q + 3 * s_voff[j], A.col_n + 3 * s_voff[j], A.w_col}
+                   : Contacts<Real>{nullptr, nullptr, 0.0};
+  };
   // per cell: gradient and b in LDS, or (meshes too large for that) in the workspace
   auto gvec = [&](int j) { return vl ? gl : tl.vec(VS0 + 2 * m, j); };
   auto bvec = [&](int j) { return vl ? bl : tl.vec(VB, j); };
@@ -1122,7 +1151,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
     if (vl) vcopy(bl, tl.vec(VB, j), len);
     __syncthreads();
     EvalResult r;
-    evaluate(M, A.mat, literal, h, CS[j].Gn, CS[j].GA, xn, ut, bvec(j), work, gvec(j), red, r);
+    evaluate(M, A.mat, literal, h, CS[j].Gn, CS[j].GA, contacts(j), xn, ut, bvec(j), work, gvec(j), red, r);
     const bool bad = !isfinite(r.E) || !isfinite(r.resid);
     const bool done = bad || r.resid <= A.sol.tol;
     vcopy(tl.vec(VG, j), gvec(j), len);
@@ -1301,7 +1330,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
           }
           __syncthreads();
         }
-        evaluate(M, A.mat, literal, h, cs.Gn, cs.GA, xn, ut, bvec(j), work, GT, red, r);
+        evaluate(M, A.mat, literal, h, cs.Gn, cs.GA, contacts(j), xn, ut, bvec(j), work, GT, red, r);
         const double slack = A.sol.noise * fmax(cs.noise, r.noise);
         accepted = isfinite(r.E) && (r.E <= cs.E + A.sol.c1 * alpha * gd + slack);
         if (accepted) break;
@@ -1540,7 +1569,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
   stage_aos(ut, u + 3 * voff, n, np);
   __syncthreads();
   EvalResult r;
-  evaluate(M, A.mat, A.sol.literal != 0, A.sol.h, Gn, GA, xn, ut, B, work, G, red, r);
+  evaluate(M, A.mat, A.sol.literal != 0, A.sol.h, Gn, GA, Contacts<Real>{nullptr, nullptr, 0.0}, xn, ut, B, work, G,
+           red, r);
   for (int e = tid(); e < 3 * n; e += kBlock) {
     const int i = e / 3, c = e - 3 * i;
     grad[3 * voff + e] = G[c * np + i];

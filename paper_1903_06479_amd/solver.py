@@ -204,6 +204,38 @@ class Batch:
                                    _dptr(u_guess), _dptr(st), _stream(stream)), "npfem_step")
         return x_out, v_out, st
 
+    def detect_contacts(self, origin, x, cutoff, q=None, n=None, count=False, stream=None):
+        """Nearest vertex of another cell within `cutoff` for every vertex: (q, n) in the
+        plan's precision, and the number of vertices with a contact when count=True."""
+        import torch
+        self._vec(x, "x")
+        if origin.dtype != torch.float64 or not origin.is_cuda or origin.shape != (self.n_cells, 3):
+            raise ValueError("origin must be a float64 CUDA tensor of shape (n_cells, 3)")
+        q = torch.empty_like(x) if q is None else q
+        n = torch.empty_like(x) if n is None else n
+        nc = c_int64(-1)
+        N.check(N.lib().npfem_collisions_detect(self._h, _dptr(origin), _dptr(x), float(cutoff), _dptr(q), _dptr(n),
+                                                byref(nc) if count else None, _stream(stream)),
+                "npfem_collisions_detect")
+        return (q, n, nc.value) if count else (q, n)
+
+    def step_contacts(self, x, v, f, q, n, w_col, x_out=None, v_out=None, stats=True, stream=None):
+        """One step with the collision term of the contacts (q, n) and weight w_col."""
+        import torch
+        for t, nm in ((x, "x"), (v, "v"), (f, "f"), (q, "q"), (n, "n")):
+            self._vec(t, nm)
+        x_out = torch.empty_like(x) if x_out is None else x_out
+        v_out = torch.empty_like(v) if v_out is None else v_out
+        st = None
+        if stats is True:
+            st = torch.empty(self.n_cells * N.CELL_STATS_DTYPE.itemsize, dtype=torch.uint8, device=x.device)
+        elif stats is not None and stats is not False:
+            st = stats
+        N.check(N.lib().npfem_step_contacts(self._h, _dptr(x), _dptr(v), _dptr(f), _dptr(q), _dptr(n), float(w_col),
+                                            _dptr(x_out), _dptr(v_out), _dptr(st), _stream(stream)),
+                "npfem_step_contacts")
+        return x_out, v_out, st
+
     def step_noalloc(self, x, v, f, x_out, v_out, stats=None, u_guess=None, stream=None):
         """npfem_step with every buffer supplied by the caller and the workspace in the
         library's static device scratch: allocates nothing."""

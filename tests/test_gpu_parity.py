@@ -794,3 +794,137 @@ def test_line_search_and_iteration_control_paths(case):
         else:
             assert status == MAXITER and info.status == ostep.MAXITER and it == 1 == info.iterations
             assert np.abs(xo[s] - xr).max() <= 1e-10 * D and np.abs(vo[s] - vr).max() <= 1e-10 * D / DT
+
+
+# ---- H~ variants (the preconditioner only) -------------------------------------------------
+
+def test_hessian_approximation_variants_reach_the_same_point():
+    """H~ with and without the material term k_mat (section 2.1.1), applied in FP64 or
+    as FP32 / BF16-off-diagonal products: the preconditioner changes the iteration
+    counts, never the stationary point (FP64 within 1e-10 D of the oracle, FP32 within
+    1e-5 D)."""
+    from paper_1903_06479_amd import Mesh, Plan, default_material, default_params, CONVERGED
+    b = workloads.shear(n_cells=4, seed=97)
+    X, Tr = b.meshes[642]
+    f = workloads.drag_forces(b, b.x, b.v)
+    D = np.ptp(X[:, 0])
+    m = oracle_model(642)
+    ref = [oracle_step(m, b.x[b.cell_slice(c)], b.v[b.cell_slice(c)], f[b.cell_slice(c)])[0] for c in range(4)]
+    for k_mat in (0.0, -1.0):
+        for precision, bf16, tol in (("fp64", 0, 1e-10), ("fp32", 0, 1e-5), ("fp32", 1, 1e-5)):
+            plan = Plan([Mesh(X, Tr)], DT, material=default_material(k_mat=k_mat),
+                        params=default_params(precision=precision, inverse_bf16=bf16,
+                                              tol=1e-10 if precision == "fp64" else 1e-6,
+                                              noise_factor=64.0 if precision == "fp64" else 8.0))
+            x, v, ff = (rounded(a, precision) for a in (b.x, b.v, f))
+            xo, _, st, _ = run_step(plan, np.zeros(4, np.int32), x, v, ff)
+            assert np.all(st["status"] == CONVERGED), (k_mat, precision, bf16)
+            err = max(np.abs(xo[b.cell_slice(c)] - ref[c]).max() for c in range(4)) / D
+            print(f"k_mat {'B' if k_mat < 0 else 0}, {precision}{' bf16' if bf16 else ''}: "
+                  f"iterations {st['iterations'].tolist()}, max |x - x_oracle| / D = {err:.2e}")
+            assert err <= tol
+
+
+# ---- collisions (section 4.7) ---------------------------------------------------------------
+
+def _overlapping_cluster(k=6):
+    """Cells of the uneven (20,000-cell, 40 % volume fraction) workload that overlap:
+    a seed cell and its nearest neighbours by origin, all within reach of each other."""
+    b_all = workloads.uneven(n_cells=20000)
+    o = b_all.origin
+    from scipy.spatial import cKDTree
+    tree = cKDTree(o)
+    dist, idx = tree.query(o, k=2)
+    seed = int(np.argmin(dist[:, 1]))
+    _, near = tree.query(o[seed], k=k)
+    cells = np.sort(near)
+    return workloads.uneven(n_cells=20000, cells=cells)
+
+
+def _oracle_contacts(b, x, cutoff):
+    from oracle import collision
+    xs = [x[b.cell_slice(c)] for c in range(b.n_cells)]
+    tris = [b.meshes[int(n)][1] for n in b.cell_nverts]
+    return collision.detect(b.origin, xs, tris, cutoff)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_contact_search_matches_oracle(precision):
+    """The hashed-grid contact search against the oracle's brute force on overlapping
+    cells of the uneven workload: the same vertices have contacts, with the same
+    partner (its position in the cell frame) and normal; where two candidates are at
+    the same distance to rounding, either is accepted."""
+    b = _overlapping_cluster()
+    sizes = sorted(b.meshes)
+    cm = np.array([sizes.index(int(n)) for n in b.cell_nverts], np.int32)
+    from paper_1903_06479_amd import Batch
+    plan = make([b.meshes[n] for n in sizes], precision)
+    batch = Batch(plan, cm)
+    x = rounded(b.x, precision)
+    cutoff = 0.6
+    q, n, count = batch.detect_contacts(T(b.origin, torch.float64), T(x, plan.torch_dtype), cutoff, count=True)
+    q, n = q.cpu().numpy().astype(np.float64), n.cpu().numpy().astype(np.float64)
+    ref = _oracle_contacts(b, x, cutoff)
+    total = 0
+    for c in range(b.n_cells):
+        s = b.cell_slice(c)
+        rq, rn, partner = ref[c]
+        has = partner >= 0
+        total += int(has.sum())
+        world = b.origin[c] + x[s]
+        dref = np.linalg.norm(rq - x[s], axis=1)
+        near_cut = np.abs(dref - cutoff) < 1e-9 * cutoff
+        gpu_has = np.any(n[s] != 0, axis=1)
+        assert np.array_equal(gpu_has[~near_cut], has[~near_cut]), c
+        both = has & gpu_has
+        same = np.all(np.abs(q[s][both] - rq[both]) <= 1e-6 * (1 if precision == "fp32" else 1e-6), axis=1)
+        dg = np.linalg.norm(q[s][both] - x[s][both], axis=1)
+        assert np.all(same | (np.abs(dg - dref[both]) <= 1e-12 * cutoff)), c
+        tol_n = 1e-6 if precision == "fp32" else 1e-12
+        assert np.all(np.abs(n[s][both][same] - rn[both][same]).max(initial=0.0) <= tol_n), c
+    assert total > 50 and abs(count - total) <= 2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_step_with_contacts_matches_oracle(precision):
+    """One step of the overlapping cluster with the collision term (w = 2e4 pN/um)
+    against the oracle's step with the oracle's contacts: positions within 1e-10 D
+    (FP64) or 1e-5 D (FP32); and the collision term reduces the deepest penetration
+    relative to the step without it."""
+    from paper_1903_06479_amd import Batch, CONVERGED
+    b = _overlapping_cluster()
+    sizes = sorted(b.meshes)
+    cm = np.array([sizes.index(int(n)) for n in b.cell_nverts], np.int32)
+    fp64 = precision == "fp64"
+    plan = make([b.meshes[n] for n in sizes], precision, tol=1e-10 if fp64 else 1e-6,
+                noise_factor=64.0 if fp64 else 8.0)
+    batch = Batch(plan, cm)
+    dt = plan.torch_dtype
+    x, v = rounded(b.x, precision), rounded(b.v, precision)
+    f = rounded(workloads.drag_forces(b, x, v, step=0), precision)
+    w = 2.0e4
+    q, n = batch.detect_contacts(T(b.origin, torch.float64), T(x, dt), 0.6)
+    xo, vo, st = batch.step_contacts(T(x, dt), T(v, dt), T(f, dt), q, n, w)
+    x0, _, _ = batch.step(T(x, dt), T(v, dt), T(f, dt))
+    torch.cuda.synchronize()
+    s = Batch.stats_to_numpy(st)
+    assert np.all(s["status"] == CONVERGED), s
+    xo, x0 = xo.cpu().numpy().astype(np.float64), x0.cpu().numpy().astype(np.float64)
+    qn, nn = q.cpu().numpy().astype(np.float64), n.cpu().numpy().astype(np.float64)
+    import oracle.step as ostep
+    worst_with, worst_without = 0.0, 0.0
+    for c in range(b.n_cells):
+        sl = b.cell_slice(c)
+        m = oracle_model(int(b.cell_nverts[c]))
+        contacts = (qn[sl], nn[sl], w)
+        xr, _, info = ostep.step(m, x[sl], v[sl], f[sl], ostep.Params(tol=1e-12, polish=True), contacts=contacts)
+        D = np.ptp(m.X[:, 0])
+        err = np.abs(xo[sl] - xr).max() / D
+        print(f"cell {c} ({b.cell_nverts[c]} vertices): {int(np.sum(np.any(nn[sl] != 0, axis=1)))} contacts, "
+              f"|x - x_oracle| / D = {err:.2e}")
+        assert err <= (1e-10 if fp64 else 1e-5), c
+        pen = lambda y: -np.minimum(np.sum((y - qn[sl]) * nn[sl], axis=1), 0).min(initial=0.0)
+        worst_with = max(worst_with, pen(xo[sl]))
+        worst_without = max(worst_without, pen(x0[sl]))
+    print(f"deepest penetration: {worst_without:.3e} um without the term, {worst_with:.3e} um with it")
+    assert worst_with < worst_without
