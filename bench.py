@@ -339,6 +339,64 @@ def config_c3(args):
             "max_dx_over_D_fp32_vs_fp64_gpu": err, "schedule": b32.schedule()}
 
 
+def elongation_index(lam, lam0, lam_inf):
+    """Hochmuth's elongation index of the recovery experiment (eq. ElongationIndex):
+    e = (lam - lam_inf)(lam0 + lam_inf) / ((lam + lam_inf)(lam0 - lam_inf))."""
+    return (lam - lam_inf) * (lam0 + lam_inf) / ((lam + lam_inf) * (lam0 - lam_inf))
+
+
+def config_recovery(args):
+    """The fluid-free recovery experiment (section 4.2) on one 258-vertex cell, FP64,
+    dt = 1 us: held at a stretching load of 50, 100 or 150 pN until steady, then released;
+    lam = D_A / D_T (axial over transverse extent) is tracked and the elongation index
+    e(t) fitted by exp(-t / t_c) (the printed exponent is garbled; it is read as 1).
+    Run with the modified Skalak law (D = 35) and the original one (D = 0)."""
+    import torch
+    from rbc_inputs import workloads
+    from paper_1903_06479_amd import Batch, Mesh, Plan, default_material, default_params, CONVERGED
+    b = workloads.stretch(258)
+    X, T = b.meshes[258]
+    lam_rest = float(np.ptp(X[:, 0]) / np.ptp(X[:, 1]))
+    dt_us, hold, release = 1.0, args.rec_hold, args.rec_release
+    dev = torch.device("cuda:0")
+    out = {"config": "recovery", "workload": "recovery: 1 RBC x 258 vertices held at +-F on the 5 % end vertices, "
+                                            f"then released; FP64, dt = {dt_us} us, {hold} + {release} steps",
+           "lam_rest": lam_rest, "runs": []}
+    for D in (35.0, 0.0):
+        plan = Plan([Mesh(X, T)], dt_us, material=default_material(D=D),
+                    params=default_params(precision="fp64", tol=1e-8, noise_factor=64.0))
+        batch = Batch(plan, np.zeros(1, np.int32))
+        for F in (50.0, 100.0, 150.0):
+            x = torch.tensor(X, dtype=torch.float64, device=dev)
+            v = torch.zeros_like(x)
+            fs = [torch.tensor(workloads.recovery_forces(b, k, F, hold), dtype=torch.float64, device=dev)
+                  for k in (1, hold + 1)]
+            lam, iters, conv = [], [], True
+            t0 = time.perf_counter()
+            for k in range(1, hold + release + 1):
+                x, v, st = batch.step(x, v, fs[0] if k <= hold else fs[1])
+                s = Batch.stats_to_numpy(st)
+                iters.append(int(s["iterations"][0]))
+                conv = conv and bool(s["status"][0] & CONVERGED)
+                xh = x.cpu().numpy()
+                lam.append(float(np.ptp(xh[:, 0]) / np.ptp(xh[:, 1])))
+            wall = time.perf_counter() - t0
+            lam = np.array(lam)
+            lam0 = lam[hold - 1]
+            e = elongation_index(lam[hold:], lam0, lam_rest)
+            t = dt_us * np.arange(1, release + 1)
+            win = (e > 0.05) & (e < 0.8)
+            tc = float(-1.0 / np.polyfit(t[win], np.log(e[win]), 1)[0]) if win.sum() >= 3 else None
+            fit_dev = float(np.abs(e[win] - np.exp(-t[win] / tc)).max()) if tc else None
+            out["runs"].append({"D": D, "F_pN": F, "lam_stretched": float(lam0), "hold_drift": float(lam[hold - 1] - lam[hold - 11]),
+                                "t_c_us": tc, "max_dev_from_exp_fit": fit_dev,
+                                "e_at_us": {str(int(tt)): float(ee) for tt, ee in zip(t, e) if int(tt) in (1, 2, 5, 10, 20, 50, 100, 200, 500)},
+                                "iterations_mean": float(np.mean(iters)), "all_converged": conv,
+                                "ms_per_step": 1e3 * wall / (hold + release)})
+            log(f"[recovery] D={D} F={F}: lam {lam0:.3f}, t_c {tc} us, dev {fit_dev}")
+    return out
+
+
 def oracle_error(b, cells, xin, vin, fin, xout):
     """max |x - x_oracle| / D over the sampled cells: the oracle's stationary point (FP64,
     residual 1e-12) from the same (FP32) inputs the GPU step read."""
@@ -359,9 +417,11 @@ def oracle_error(b, cells, xin, vin, fin, xout):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--config", default="", choices=["", "c1", "c2", "c3"],
+    ap.add_argument("--config", default="", choices=["", "c1", "c2", "c3", "recovery"],
                     help="run one of the other configurations instead of the throughput benchmark")
     ap.add_argument("--c3-steps", type=int, default=5)
+    ap.add_argument("--rec-hold", type=int, default=400)
+    ap.add_argument("--rec-release", type=int, default=600)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cells", type=int, default=100000)
@@ -394,7 +454,7 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": c.numel() * 4}), flush=True)
         return
     if args.config:
-        cfg = {"c1": config_c1, "c2": config_c2, "c3": config_c3}[args.config]
+        cfg = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "recovery": config_recovery}[args.config]
         if args.config == "c2" and args.steps == 20:
             args.steps = 100
         print(json.dumps(cfg(args)), flush=True)

@@ -10,6 +10,8 @@ Poiseuille experiments without needing the lattice-Boltzmann solver.
 Workloads
   stretch  : one 258-vertex cell at rest, equal and opposite forces ramped 0-200 pN
              on the 5 % of vertices at each end of the x axis (optical-tweezers load).
+  recovery : the same cell held at a constant stretching load, then released (the
+             fluid-free recovery experiment; the forces are recovery_forces).
   shear    : N cells of one mesh, random rotation, Gaussian perturbation of the
              initial positions (sigma = 2 % of the radius), centres on a lattice,
              drag towards a per-cell linear shear flow, rate U[100, 1000] 1/s.
@@ -124,6 +126,15 @@ def stretch_forces(batch: Batch, step: int, total_steps: int = 200, f_max: float
     f[order[-n_end:], 0] = fk / n_end
     f[order[:n_end], 0] = -fk / n_end
     return f
+
+
+def recovery_forces(batch: Batch, step: int, f_stretch: float = 100.0, hold_steps: int = 300) -> np.ndarray:
+    """The recovery experiment's load (section 4.2): the stretching forces +-f_stretch on
+    the end vertices held for steps 1..hold_steps, then released (zero afterwards)."""
+    if step <= hold_steps:
+        return stretch_forces(batch, 1, total_steps=1, f_max=f_stretch)
+    n = int(batch.cell_nverts[0])
+    return np.zeros((n, 3))
 
 
 def shear(n_cells: int = 1024, n_verts: int = 642, seed: int = 1002, cells=None,

@@ -928,3 +928,37 @@ def test_step_with_contacts_matches_oracle(precision):
         worst_without = max(worst_without, pen(x0[sl]))
     print(f"deepest penetration: {worst_without:.3e} um without the term, {worst_with:.3e} um with it")
     assert worst_with < worst_without
+
+
+# ---- the recovery workload (original and modified Skalak) -------------------------------------
+
+@pytest.mark.parametrize("D", [35.0, 0.0])
+def test_recovery_hold_and_release_match_oracle(D):
+    """The fluid-free recovery experiment (one 258-vertex cell, dt = 1 us, FP64) with the
+    modified (D = 35) and the original (D = 0) Skalak law: four steps held at 100 pN,
+    then four released; every step against the oracle stepped from the GPU's state, and
+    the eight-step trajectory against the oracle's own, within 1e-10 D."""
+    import oracle.step as ostep
+    from paper_1903_06479_amd import Batch, Mesh, Plan, default_material, default_params, CONVERGED
+    b = workloads.stretch(258)
+    X, Tr = b.meshes[258]
+    m = oracle_model(258, h=1.0, D=D)
+    plan = Plan([Mesh(X, Tr)], 1.0, material=default_material(D=D),
+                params=default_params(precision="fp64", tol=1e-10, noise_factor=64.0))
+    batch = Batch(plan, np.zeros(1, np.int32))
+    D_len = np.ptp(X[:, 0])
+    xg, vg = T(X, torch.float64), T(np.zeros_like(X), torch.float64)
+    xr, vr = X.copy(), np.zeros_like(X)
+    p = ostep.Params(tol=1e-12, polish=True)
+    for k in range(1, 9):
+        f = workloads.recovery_forces(b, k, 100.0, hold_steps=4)
+        xp, vp = xg.cpu().numpy(), vg.cpu().numpy()
+        xg, vg, st = batch.step(xg, vg, T(f, torch.float64))
+        assert batch.stats_to_numpy(st)["status"][0] == CONVERGED, k
+        xs, _, _ = ostep.step(m, xp, vp, f, p)
+        xr, vr, _ = ostep.step(m, xr, vr, f, p)
+        e_step = np.abs(xg.cpu().numpy() - xs).max() / D_len
+        e_traj = np.abs(xg.cpu().numpy() - xr).max() / D_len
+        lam = np.ptp(xg.cpu().numpy()[:, 0]) / np.ptp(xg.cpu().numpy()[:, 1])
+        print(f"D={D} step {k}: lambda {lam:.4f}, this step {e_step:.2e} D, trajectory {e_traj:.2e} D")
+        assert e_step <= 1e-10 and e_traj <= 1e-10, k
