@@ -599,6 +599,8 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
       choose_layout<float>(mp.n_pad, m->nt, half, lds_cap, &mp.chunk, &mp.vec_lds, &mp.xu_lds);
     if (mp.chunk <= 0)
       return fail(NPFEM_E_UNSUPPORTED, "plan_create: mesh too large for the LDS in this precision");
+    if (!fp64 && !mp.xu_lds)
+      return fail(NPFEM_E_UNSUPPORTED, "plan_create: FP32 plans keep each cell's x_n and u in LDS; this mesh is too large for that");
     // lumped mass by barycentric area (section 2.1)
     double bsum = 0.0;
     for (double a : m->bary_area) bsum += a;
@@ -767,6 +769,9 @@ StepArgs<Real> make_args(npfem_batch* b) {
   a.cstate = b->cstate;
   a.cs_lds = b->cs_lds;
   a.n_pad_max = b->n_pad_max;
+  a.xu_global = 0;
+  for (size_t mi = 0; mi < p->meshes.size(); ++mi)
+    if (!b->by_mesh[mi].empty() && !p->meshes[mi].xu_lds) a.xu_global = 1;
   a.stage_k = b->stage_k;
   return a;
 }

@@ -18,6 +18,7 @@
 #include <cfloat>
 #include <cmath>
 #include <type_traits>
+#include <vector>
 
 #include "npfem_internal.h"
 
@@ -320,7 +321,9 @@ __device__ inline Real sl2_tau(Real a1, Real a2, Real sig1, Real J) {
   return tau;
 }
 
-template <typename Real>
+// EXT: the optional terms (global area, the literal volume normaliser, contacts) are
+// compiled in; without them the evaluation carries none of their code.
+template <typename Real, bool EXT>
 __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool literal, double h, double Gn,
                          double GA, const Contacts<Real>& col, const Real* xn, const Real* ut, const Real* bvec,
                          Real* work, Real* gout, double* red, EvalResult& res) {
@@ -337,10 +340,10 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool li
   // global-area term needs the total area beforehand, the enclosed volume and area are
   // summed in the triangle pass itself; otherwise first, in a pass of their own.
   const bool single = nt <= ch;
-  const bool area_on = mat.k_area_global > 0.0;
+  const bool area_on = EXT && mat.k_area_global > 0.0;
   const bool pre = !single || area_on;
   // ---- literal volume normaliser: |grad V|^2 at the trial point (gout as scratch) ---
-  if (literal) {
+  if (EXT && literal) {
     double gv, ga;
     normalisers(M, xn, ut, gout, static_cast<Real*>(nullptr), work, red, gv, ga);
     Gn = gv;
@@ -457,7 +460,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool li
     const Real ux = ut[i], uy = ut[np + i], uz = ut[2 * np + i];
     const Real bx = bvec[i], by = bvec[np + i], bz = bvec[2 * np + i];
     Real ox = kb * gx + (mi * ux - bx), oy = kb * gy + (mi * uy - by), oz = kb * gz + (mi * uz - bz);
-    if (col.n) {
+    if (EXT && col.n) {
       const Real cnx = gld(col.n, 3 * i), cny = gld(col.n, 3 * i + 1), cnz = gld(col.n, 3 * i + 2);
       const Real cqx = gld(col.q, 3 * i), cqy = gld(col.q, 3 * i + 1), cqz = gld(col.q, 3 * i + 2);
       const Real dd = ((xn[i] - cqx) + ux) * cnx + ((xn[np + i] - cqy) + uy) * cny + ((xn[2 * np + i] - cqz) + uz) * cnz;
@@ -604,7 +607,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool li
         // x_a . (x_b x x_c) = E1 . (E2 x x_c) with E1 = x_a - x_c, E2 = x_b - x_c (FP64)
         const double cx = (double)xc + (double)ucx, cy = (double)yc + (double)ucy, cz = (double)zc + (double)ucz;
         accC[4] += E1x * (E2y * cz - E2z * cy) + E1y * (E2z * cx - E2x * cz) + E1z * (E2x * cy - E2y * cx);
-        accC[5] += sqrt(NN);
+        accC[5] += (double)J * area_t;                      // deformed area = J A0
       }
       accC[6] += collapsed ? 1.0 : 0.0;
       accC[0] += 0.5 * (double)(Cst * A0) * ((double)dA1 * dA1 + (double)dA2 * dA2);
@@ -617,7 +620,7 @@ __device__ void evaluate(const MeshDev<Real>& M, const MaterialDev& mat, bool li
       double vv[2] = {accC[4], accC[5]};
       block_sum<2>(vv, red);                  // also the barrier before the gather
       vol = vv[0] / 6.0;
-      area = 0.5 * vv[1];
+      area = vv[1];
       coefd = mat.k_volume * (vol - M.V0) / Gn;
     } else {
       __syncthreads();
@@ -1051,7 +1054,7 @@ __device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, i
   }
 }
 
-template <typename Real, int H, typename CST>
+template <typename Real, int H, bool EXT, bool XG, typename CST>
 __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Real>& A, int tile, Real* W, CST* CS, double* red,
                          int* sint, unsigned char* lds) {
   const TileDesc td = A.tiles[tile];
@@ -1080,7 +1083,9 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
   // workspace and the LDS holds the corner chunks only
   const bool vl = M.vec_lds != 0, xl = M.xu_lds != 0;
   unsigned char* stage = lds + kLdsHeader;                   // BF16 staging of the tile product
-  Real* xn = xl ? reinterpret_cast<Real*>(lds + kLdsHeader) : W + (size_t)A.n_vec_slot * A.tile_cells_max * 3 * np;
+  // (XG: some mesh of the batch keeps them in the workspace; otherwise the pointers are
+  // LDS pointers at compile time, so every access to them is an LDS instruction)
+  Real* xn = !XG || xl ? reinterpret_cast<Real*>(lds + kLdsHeader) : W + (size_t)A.n_vec_slot * A.tile_cells_max * 3 * np;
   Real* ut = xn + 3 * np;
   Real* gl = ut + 3 * np;
   Real* bl = gl + 3 * np;
@@ -1089,9 +1094,9 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
   const int m = A.sol.m;
   const double eps = Eps<Real>::v;
   __shared__ double s_vol[kMaxTile], s_area[kMaxTile];
-  const bool area_on = A.mat.k_area_global > 0.0, literal = A.sol.literal != 0;
+  const bool area_on = EXT && A.mat.k_area_global > 0.0, literal = EXT && A.sol.literal != 0;
   auto contacts = [&](int j) {
-    return A.col_n ? Contacts<Real>{A.col_q + 3 * s_voff[j], A.col_n + 3 * s_voff[j], A.w_col}
+    return EXT && A.col_n ? Contacts<Real>{A.col_q + 3 * s_voff[j], A.col_n + 3 * s_voff[j], A.w_col}
                    : Contacts<Real>{nullptr, nullptr, 0.0};
   };
   // per cell: gradient and b in LDS, or (meshes too large for that) in the workspace
@@ -1151,7 +1156,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
     if (vl) vcopy(bl, tl.vec(VB, j), len);
     __syncthreads();
     EvalResult r;
-    evaluate(M, A.mat, literal, h, CS[j].Gn, CS[j].GA, contacts(j), xn, ut, bvec(j), work, gvec(j), red, r);
+    evaluate<Real, EXT>(M, A.mat, literal, h, CS[j].Gn, CS[j].GA, contacts(j), xn, ut, bvec(j), work, gvec(j), red, r);
     const bool bad = !isfinite(r.E) || !isfinite(r.resid);
     const bool done = bad || r.resid <= A.sol.tol;
     vcopy(tl.vec(VG, j), gvec(j), len);
@@ -1330,7 +1335,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
           }
           __syncthreads();
         }
-        evaluate(M, A.mat, literal, h, cs.Gn, cs.GA, contacts(j), xn, ut, bvec(j), work, GT, red, r);
+        evaluate<Real, EXT>(M, A.mat, literal, h, cs.Gn, cs.GA, contacts(j), xn, ut, bvec(j), work, GT, red, r);
         const double slack = A.sol.noise * fmax(cs.noise, r.noise);
         accepted = isfinite(r.E) && (r.E <= cs.E + A.sol.c1 * alpha * gd + slack);
         if (accepted) break;
@@ -1515,8 +1520,10 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
 #define NPFEM_STEP_WAVES_PER_SIMD 2
 #endif
 // H: compile-time bound on the L-BFGS history (the loops over pairs are unrolled to H);
-// CSL: the tile's cell states live in LDS at byte offset A.cs_lds (else in the workspace).
-template <typename Real, int H, bool CSL>
+// CSL: the tile's cell states live in LDS at byte offset A.cs_lds (else in the workspace);
+// EXT: the optional terms of the objective are compiled in; XG: some mesh keeps the
+// current cell's x_n and u in the workspace.
+template <typename Real, int H, bool CSL, bool EXT, bool XG>
 __global__ void __launch_bounds__(kBlock, NPFEM_STEP_WAVES_PER_SIMD) step_kernel(StepArgs<Real> A) {
   extern __shared__ __align__(16) unsigned char lds[];
   double* red = reinterpret_cast<double*>(lds);
@@ -1530,7 +1537,7 @@ __global__ void __launch_bounds__(kBlock, NPFEM_STEP_WAVES_PER_SIMD) step_kernel
     const int tile = sint[0];
     __syncthreads();
     if (tile >= A.n_tiles) break;
-    run_tile<Real, H>(A, tile, W, CS, red, sint, lds);
+    run_tile<Real, H, EXT, XG>(A, tile, W, CS, red, sint, lds);
     __syncthreads();
   }
 }
@@ -1540,7 +1547,7 @@ __global__ void reset_counter(int* c) {
 }
 
 // One workgroup per cell: objective and gradient at x_n + u (no iteration).
-template <typename Real>
+template <typename Real, bool XG>
 __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Real* u, Real* grad,
                                                       double* terms, Real* scratch) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -1552,8 +1559,8 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
   // per cell in the scratch: gradient, b, x_n, u (3 n_pad_max each), where not in LDS
   const bool vl = M.vec_lds != 0, xl = M.xu_lds != 0;
   Real* cs = scratch + (size_t)cell * 4 * 3 * A.n_pad_max;
-  Real* xn = xl ? reinterpret_cast<Real*>(lds + kLdsHeader) : cs + 2 * 3 * A.n_pad_max;
-  Real* ut = xl ? xn + 3 * np : cs + 3 * 3 * A.n_pad_max;
+  Real* xn = !XG || xl ? reinterpret_cast<Real*>(lds + kLdsHeader) : cs + 2 * 3 * A.n_pad_max;
+  Real* ut = !XG || xl ? xn + 3 * np : cs + 3 * 3 * A.n_pad_max;
   Real* G = vl ? ut + 3 * np : cs;
   Real* B = vl ? G + 3 * np : cs + 3 * A.n_pad_max;
   Real* work = reinterpret_cast<Real*>(lds + kLdsHeader) + (xl ? (vl ? 12 : 6) * np : 0);
@@ -1569,7 +1576,7 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
   stage_aos(ut, u + 3 * voff, n, np);
   __syncthreads();
   EvalResult r;
-  evaluate(M, A.mat, A.sol.literal != 0, A.sol.h, Gn, GA, Contacts<Real>{nullptr, nullptr, 0.0}, xn, ut, B, work, G,
+  evaluate<Real, true>(M, A.mat, A.sol.literal != 0, A.sol.h, Gn, GA, Contacts<Real>{nullptr, nullptr, 0.0}, xn, ut, B, work, G,
            red, r);
   for (int e = tid(); e < 3 * n; e += kBlock) {
     const int i = e / 3, c = e - 3 * i;
@@ -1735,15 +1742,32 @@ size_t lds_bytes(int n_pad, int chunk, int stage_rows, int vec_lds, int xu_lds) 
   return kLdsHeader + region;
 }
 
+// The workspace variant of x_n and u (XG) exists for FP64 plans only: FP32 plans of the
+// supported meshes always keep them in LDS (the host refuses an FP32 mesh that would not).
+template <typename Real> constexpr bool kHasXG = std::is_same<Real, double>::value;
+
+template <typename Real, bool XG>
+void step_kernel_ptrs(std::vector<const void*>& out) {
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, false, false, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, false, false, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, false, false, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, true, false, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, true, false, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, true, false, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, false, true, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, false, true, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, false, true, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, true, true, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, true, true, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, true, true, XG>));
+  out.push_back(reinterpret_cast<const void*>(&eval_kernel<Real, XG>));
+}
+
 template <typename Real>
 hipError_t set_lds_limit(size_t bytes) {
-  const void* fns[] = {reinterpret_cast<const void*>(&step_kernel<Real, 2, false>),
-                       reinterpret_cast<const void*>(&step_kernel<Real, 5, false>),
-                       reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, false>),
-                       reinterpret_cast<const void*>(&step_kernel<Real, 2, true>),
-                       reinterpret_cast<const void*>(&step_kernel<Real, 5, true>),
-                       reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, true>),
-                       reinterpret_cast<const void*>(&eval_kernel<Real>)};
+  std::vector<const void*> fns;
+  step_kernel_ptrs<Real, false>(fns);
+  if constexpr (kHasXG<Real>) step_kernel_ptrs<Real, true>(fns);
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
@@ -1753,24 +1777,43 @@ hipError_t set_lds_limit(size_t bytes) {
 
 template <typename Real>
 hipError_t occupancy(int* blocks_per_cu, size_t lds) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<Real, kMaxHistory, false>, kBlock, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<Real, kMaxHistory, false, true, kHasXG<Real>>,
+                                                      kBlock, lds);
+}
+
+template <typename Real, int H, bool EXT, bool XG>
+void launch_step_h(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s) {
+  if (a.cs_lds >= 0) hipLaunchKernelGGL((step_kernel<Real, H, true, EXT, XG>), dim3(grid), dim3(kBlock), lds, s, a);
+  else hipLaunchKernelGGL((step_kernel<Real, H, false, EXT, XG>), dim3(grid), dim3(kBlock), lds, s, a);
+}
+
+template <typename Real, bool EXT, bool XG>
+void launch_step_e(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s) {
+  if (a.sol.m <= 2) launch_step_h<Real, 2, EXT, XG>(a, grid, lds, s);
+  else if (a.sol.m <= 5) launch_step_h<Real, 5, EXT, XG>(a, grid, lds, s);
+  else launch_step_h<Real, kMaxHistory, EXT, XG>(a, grid, lds, s);
+}
+
+template <typename Real, bool XG>
+void launch_step_x(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s) {
+  // the optional terms' code only where they are used
+  const bool ext = a.mat.k_area_global > 0.0 || a.sol.literal != 0 || a.col_n != nullptr;
+  if (ext) launch_step_e<Real, true, XG>(a, grid, lds, s);
+  else launch_step_e<Real, false, XG>(a, grid, lds, s);
 }
 
 template <typename Real>
 hipError_t launch_step(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s, int* counter) {
   (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
+  if (a.xu_global && !kHasXG<Real>) return hipErrorInvalidValue;
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
-  const bool csl = a.cs_lds >= 0;
-  if (a.sol.m <= 2) {
-    if (csl) hipLaunchKernelGGL((step_kernel<Real, 2, true>), dim3(grid), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((step_kernel<Real, 2, false>), dim3(grid), dim3(kBlock), lds, s, a);
-  } else if (a.sol.m <= 5) {
-    if (csl) hipLaunchKernelGGL((step_kernel<Real, 5, true>), dim3(grid), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((step_kernel<Real, 5, false>), dim3(grid), dim3(kBlock), lds, s, a);
-  } else {
-    if (csl) hipLaunchKernelGGL((step_kernel<Real, kMaxHistory, true>), dim3(grid), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((step_kernel<Real, kMaxHistory, false>), dim3(grid), dim3(kBlock), lds, s, a);
+  if constexpr (kHasXG<Real>) {
+    if (a.xu_global) {
+      launch_step_x<Real, true>(a, grid, lds, s);
+      return hipGetLastError();
+    }
   }
+  launch_step_x<Real, false>(a, grid, lds, s);
   return hipGetLastError();
 }
 
@@ -1778,7 +1821,14 @@ template <typename Real>
 hipError_t launch_eval(const StepArgs<Real>& a, int n_cells, const Real* u, Real* grad, double* terms,
                        size_t lds, hipStream_t s) {
   (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
-  hipLaunchKernelGGL(eval_kernel<Real>, dim3(n_cells), dim3(kBlock), lds, s, a, u, grad, terms, a.work);
+  if (a.xu_global && !kHasXG<Real>) return hipErrorInvalidValue;
+  if constexpr (kHasXG<Real>) {
+    if (a.xu_global) {
+      hipLaunchKernelGGL((eval_kernel<Real, true>), dim3(n_cells), dim3(kBlock), lds, s, a, u, grad, terms, a.work);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((eval_kernel<Real, false>), dim3(n_cells), dim3(kBlock), lds, s, a, u, grad, terms, a.work);
   return hipGetLastError();
 }
 
