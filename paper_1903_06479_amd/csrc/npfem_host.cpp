@@ -769,9 +769,10 @@ StepArgs<Real> make_args(npfem_batch* b) {
   a.cstate = b->cstate;
   a.cs_lds = b->cs_lds;
   a.n_pad_max = b->n_pad_max;
-  a.xu_global = 0;
+  a.layout = 0;
   for (size_t mi = 0; mi < p->meshes.size(); ++mi)
-    if (!b->by_mesh[mi].empty() && !p->meshes[mi].xu_lds) a.xu_global = 1;
+    if (!b->by_mesh[mi].empty())
+      a.layout = std::max(a.layout, !p->meshes[mi].xu_lds ? 2 : (!p->meshes[mi].vec_lds ? 1 : 0));
   a.stage_k = b->stage_k;
   return a;
 }

@@ -107,7 +107,8 @@ struct StepArgs {
   CellState* cstate;           // [slots][T] (read as CellStateT<H>) when cs_lds < 0
   int cs_lds;                  // byte offset of the tile's cell states in LDS, or -1
   int n_pad_max;
-  int xu_global;               // 1: some mesh of the batch keeps x_n and u in the workspace
+  int layout;                  // largest over the batch's meshes: 0 current cell's vectors in LDS,
+                               // 1 gradient and b in the workspace, 2 x_n and u there too
   int stage_k;                 // k columns per LDS chunk of the BF16 tile product (0: unstaged)
   const Real* x;               // [V][3]
   const Real* v;

@@ -1054,7 +1054,7 @@ __device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, i
   }
 }
 
-template <typename Real, int H, bool EXT, bool XG, typename CST>
+template <typename Real, int H, bool EXT, int LAY, typename CST>
 __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Real>& A, int tile, Real* W, CST* CS, double* red,
                          int* sint, unsigned char* lds) {
   const TileDesc td = A.tiles[tile];
@@ -1081,11 +1081,12 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
   // the current cell's x_n and trial u (and gradient and b) in LDS, then the corner
   // chunks; for meshes too large for that, x_n and u follow the tile's vectors in the
   // workspace and the LDS holds the corner chunks only
-  const bool vl = M.vec_lds != 0, xl = M.xu_lds != 0;
+  // (LAY is the batch's layout, the largest over its meshes: 0 all in LDS, 1 gradient
+  // and b in the workspace, 2 x_n and u too; below it the placement is known at compile
+  // time and every access to these vectors is an LDS instruction)
+  const bool vl = LAY == 0 || M.vec_lds != 0, xl = LAY < 2 || M.xu_lds != 0;
   unsigned char* stage = lds + kLdsHeader;                   // BF16 staging of the tile product
-  // (XG: some mesh of the batch keeps them in the workspace; otherwise the pointers are
-  // LDS pointers at compile time, so every access to them is an LDS instruction)
-  Real* xn = !XG || xl ? reinterpret_cast<Real*>(lds + kLdsHeader) : W + (size_t)A.n_vec_slot * A.tile_cells_max * 3 * np;
+  Real* xn = xl ? reinterpret_cast<Real*>(lds + kLdsHeader) : W + (size_t)A.n_vec_slot * A.tile_cells_max * 3 * np;
   Real* ut = xn + 3 * np;
   Real* gl = ut + 3 * np;
   Real* bl = gl + 3 * np;
@@ -1521,9 +1522,10 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
 #endif
 // H: compile-time bound on the L-BFGS history (the loops over pairs are unrolled to H);
 // CSL: the tile's cell states live in LDS at byte offset A.cs_lds (else in the workspace);
-// EXT: the optional terms of the objective are compiled in; XG: some mesh keeps the
-// current cell's x_n and u in the workspace.
-template <typename Real, int H, bool CSL, bool EXT, bool XG>
+// EXT: the optional terms of the objective are compiled in; LAY: the batch's vector
+// layout (0: every mesh keeps the current cell's vectors in LDS, 1: some mesh keeps the
+// gradient and b in the workspace, 2: some mesh keeps x_n and u there too).
+template <typename Real, int H, bool CSL, bool EXT, int LAY>
 __global__ void __launch_bounds__(kBlock, NPFEM_STEP_WAVES_PER_SIMD) step_kernel(StepArgs<Real> A) {
   extern __shared__ __align__(16) unsigned char lds[];
   double* red = reinterpret_cast<double*>(lds);
@@ -1537,7 +1539,7 @@ __global__ void __launch_bounds__(kBlock, NPFEM_STEP_WAVES_PER_SIMD) step_kernel
     const int tile = sint[0];
     __syncthreads();
     if (tile >= A.n_tiles) break;
-    run_tile<Real, H, EXT, XG>(A, tile, W, CS, red, sint, lds);
+    run_tile<Real, H, EXT, LAY>(A, tile, W, CS, red, sint, lds);
     __syncthreads();
   }
 }
@@ -1547,7 +1549,7 @@ __global__ void reset_counter(int* c) {
 }
 
 // One workgroup per cell: objective and gradient at x_n + u (no iteration).
-template <typename Real, bool XG>
+template <typename Real, int LAY>
 __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Real* u, Real* grad,
                                                       double* terms, Real* scratch) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -1557,10 +1559,10 @@ __global__ void __launch_bounds__(kBlock) eval_kernel(StepArgs<Real> A, const Re
   const int n = M.n, np = M.n_pad, len = 3 * np;
   const int64_t voff = A.cell_voff[cell];
   // per cell in the scratch: gradient, b, x_n, u (3 n_pad_max each), where not in LDS
-  const bool vl = M.vec_lds != 0, xl = M.xu_lds != 0;
+  const bool vl = LAY == 0 || M.vec_lds != 0, xl = LAY < 2 || M.xu_lds != 0;
   Real* cs = scratch + (size_t)cell * 4 * 3 * A.n_pad_max;
-  Real* xn = !XG || xl ? reinterpret_cast<Real*>(lds + kLdsHeader) : cs + 2 * 3 * A.n_pad_max;
-  Real* ut = !XG || xl ? xn + 3 * np : cs + 3 * 3 * A.n_pad_max;
+  Real* xn = xl ? reinterpret_cast<Real*>(lds + kLdsHeader) : cs + 2 * 3 * A.n_pad_max;
+  Real* ut = xl ? xn + 3 * np : cs + 3 * 3 * A.n_pad_max;
   Real* G = vl ? ut + 3 * np : cs;
   Real* B = vl ? G + 3 * np : cs + 3 * A.n_pad_max;
   Real* work = reinterpret_cast<Real*>(lds + kLdsHeader) + (xl ? (vl ? 12 : 6) * np : 0);
@@ -1742,32 +1744,33 @@ size_t lds_bytes(int n_pad, int chunk, int stage_rows, int vec_lds, int xu_lds) 
   return kLdsHeader + region;
 }
 
-// The workspace variant of x_n and u (XG) exists for FP64 plans only: FP32 plans of the
+// Layout 2 (x_n and u in the workspace) exists for FP64 plans only: FP32 plans of the
 // supported meshes always keep them in LDS (the host refuses an FP32 mesh that would not).
-template <typename Real> constexpr bool kHasXG = std::is_same<Real, double>::value;
+template <typename Real> constexpr int kMaxLayout = std::is_same<Real, double>::value ? 2 : 1;
 
-template <typename Real, bool XG>
+template <typename Real, int LAY>
 void step_kernel_ptrs(std::vector<const void*>& out) {
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, false, false, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, false, false, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, false, false, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, true, false, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, true, false, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, true, false, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, false, true, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, false, true, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, false, true, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, true, true, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, true, true, XG>));
-  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, true, true, XG>));
-  out.push_back(reinterpret_cast<const void*>(&eval_kernel<Real, XG>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, false, false, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, false, false, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, false, false, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, true, false, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, true, false, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, true, false, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, false, true, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, false, true, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, false, true, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 2, true, true, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, 5, true, true, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&step_kernel<Real, kMaxHistory, true, true, LAY>));
+  out.push_back(reinterpret_cast<const void*>(&eval_kernel<Real, LAY>));
 }
 
 template <typename Real>
 hipError_t set_lds_limit(size_t bytes) {
   std::vector<const void*> fns;
-  step_kernel_ptrs<Real, false>(fns);
-  if constexpr (kHasXG<Real>) step_kernel_ptrs<Real, true>(fns);
+  step_kernel_ptrs<Real, 0>(fns);
+  step_kernel_ptrs<Real, 1>(fns);
+  if constexpr (kMaxLayout<Real> >= 2) step_kernel_ptrs<Real, 2>(fns);
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
@@ -1777,43 +1780,39 @@ hipError_t set_lds_limit(size_t bytes) {
 
 template <typename Real>
 hipError_t occupancy(int* blocks_per_cu, size_t lds) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_kernel<Real, kMaxHistory, false, true, kHasXG<Real>>,
-                                                      kBlock, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu, step_kernel<Real, kMaxHistory, false, true, kMaxLayout<Real>>, kBlock, lds);
 }
 
-template <typename Real, int H, bool EXT, bool XG>
+template <typename Real, int H, bool EXT, int LAY>
 void launch_step_h(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s) {
-  if (a.cs_lds >= 0) hipLaunchKernelGGL((step_kernel<Real, H, true, EXT, XG>), dim3(grid), dim3(kBlock), lds, s, a);
-  else hipLaunchKernelGGL((step_kernel<Real, H, false, EXT, XG>), dim3(grid), dim3(kBlock), lds, s, a);
+  if (a.cs_lds >= 0) hipLaunchKernelGGL((step_kernel<Real, H, true, EXT, LAY>), dim3(grid), dim3(kBlock), lds, s, a);
+  else hipLaunchKernelGGL((step_kernel<Real, H, false, EXT, LAY>), dim3(grid), dim3(kBlock), lds, s, a);
 }
 
-template <typename Real, bool EXT, bool XG>
+template <typename Real, bool EXT, int LAY>
 void launch_step_e(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s) {
-  if (a.sol.m <= 2) launch_step_h<Real, 2, EXT, XG>(a, grid, lds, s);
-  else if (a.sol.m <= 5) launch_step_h<Real, 5, EXT, XG>(a, grid, lds, s);
-  else launch_step_h<Real, kMaxHistory, EXT, XG>(a, grid, lds, s);
+  if (a.sol.m <= 2) launch_step_h<Real, 2, EXT, LAY>(a, grid, lds, s);
+  else if (a.sol.m <= 5) launch_step_h<Real, 5, EXT, LAY>(a, grid, lds, s);
+  else launch_step_h<Real, kMaxHistory, EXT, LAY>(a, grid, lds, s);
 }
 
-template <typename Real, bool XG>
+template <typename Real, int LAY>
 void launch_step_x(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s) {
   // the optional terms' code only where they are used
   const bool ext = a.mat.k_area_global > 0.0 || a.sol.literal != 0 || a.col_n != nullptr;
-  if (ext) launch_step_e<Real, true, XG>(a, grid, lds, s);
-  else launch_step_e<Real, false, XG>(a, grid, lds, s);
+  if (ext) launch_step_e<Real, true, LAY>(a, grid, lds, s);
+  else launch_step_e<Real, false, LAY>(a, grid, lds, s);
 }
 
 template <typename Real>
 hipError_t launch_step(const StepArgs<Real>& a, int grid, size_t lds, hipStream_t s, int* counter) {
   (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
-  if (a.xu_global && !kHasXG<Real>) return hipErrorInvalidValue;
+  if (a.layout < 0 || a.layout > kMaxLayout<Real>) return hipErrorInvalidValue;
   hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, s, counter);
-  if constexpr (kHasXG<Real>) {
-    if (a.xu_global) {
-      launch_step_x<Real, true>(a, grid, lds, s);
-      return hipGetLastError();
-    }
-  }
-  launch_step_x<Real, false>(a, grid, lds, s);
+  if (a.layout == 0) launch_step_x<Real, 0>(a, grid, lds, s);
+  else if (a.layout == 1) launch_step_x<Real, 1>(a, grid, lds, s);
+  else if constexpr (kMaxLayout<Real> >= 2) launch_step_x<Real, kMaxLayout<Real>>(a, grid, lds, s);
   return hipGetLastError();
 }
 
@@ -1821,14 +1820,13 @@ template <typename Real>
 hipError_t launch_eval(const StepArgs<Real>& a, int n_cells, const Real* u, Real* grad, double* terms,
                        size_t lds, hipStream_t s) {
   (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
-  if (a.xu_global && !kHasXG<Real>) return hipErrorInvalidValue;
-  if constexpr (kHasXG<Real>) {
-    if (a.xu_global) {
-      hipLaunchKernelGGL((eval_kernel<Real, true>), dim3(n_cells), dim3(kBlock), lds, s, a, u, grad, terms, a.work);
-      return hipGetLastError();
-    }
-  }
-  hipLaunchKernelGGL((eval_kernel<Real, false>), dim3(n_cells), dim3(kBlock), lds, s, a, u, grad, terms, a.work);
+  if (a.layout < 0 || a.layout > kMaxLayout<Real>) return hipErrorInvalidValue;
+  if (a.layout == 0)
+    hipLaunchKernelGGL((eval_kernel<Real, 0>), dim3(n_cells), dim3(kBlock), lds, s, a, u, grad, terms, a.work);
+  else if (a.layout == 1)
+    hipLaunchKernelGGL((eval_kernel<Real, 1>), dim3(n_cells), dim3(kBlock), lds, s, a, u, grad, terms, a.work);
+  else if constexpr (kMaxLayout<Real> >= 2)
+    hipLaunchKernelGGL((eval_kernel<Real, kMaxLayout<Real>>), dim3(n_cells), dim3(kBlock), lds, s, a, u, grad, terms, a.work);
   return hipGetLastError();
 }
 
