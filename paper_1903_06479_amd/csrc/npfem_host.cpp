@@ -725,6 +725,7 @@ struct npfem_batch {
   // learned warm start: the predicted correction of every vertex (allocated on first use)
   DeviceBuffers dbuf;
   void* delta = nullptr;
+  double* net_frames = nullptr;             // [n_cells][kNetFrame] frames of the resident inference
   // contact search: hashed grid buffers (allocated on first use)
   DeviceBuffers cbuf;
   int64_t c_table = 0;
@@ -1369,6 +1370,7 @@ struct npfem_net {
   const NetMeshDev* d_meshes = nullptr;
   int n_pad_max = 0, nb_deg_max = 0;
   size_t fwd_lds = 0;                       // LDS of the resident forward variant (0: not used)
+  size_t inf_lds = 0;                       // LDS of the resident inference (0: not used)
   int adam_t = 0;
   // inference scratch: per workgroup, features and two activation planes
   DeviceBuffers ibuf;
@@ -1500,7 +1502,23 @@ npfem_status net_infer_now(npfem_net* net, npfem_batch* b, const void* x, const 
   a.S.train = 0;
   a.n_cells = (int)b->n_cells;
   a.delta = static_cast<Real*>(delta);
+  if (net->inf_lds) {                       // resident inference: one workgroup per CU
+    a.cframe = b->net_frames;
+    HIP_TRY(launch_net_infer<Real>(a, std::max(1, std::min(net->plan->cu_count, (int)b->n_cells)), net->inf_lds, s));
+    return NPFEM_OK;
+  }
   HIP_TRY(launch_net_forward<Real>(a, std::min(net->igrid, net_fwd_grid(net, (int)b->n_cells)), net->fwd_lds, s));
+  return NPFEM_OK;
+}
+
+// the batch's frame buffer of the resident inference, allocated before any launch (and
+// so before a graph capture)
+npfem_status net_batch_frames(const npfem_net* net, npfem_batch* b) {
+  if (!net->inf_lds || b->net_frames) return NPFEM_OK;
+  void* p;
+  npfem_status s;
+  if ((s = b->dbuf.alloc((size_t)b->n_cells * kNetFrame * sizeof(double), &p))) return s;
+  b->net_frames = static_cast<double*>(p);
   return NPFEM_OK;
 }
 
@@ -1670,6 +1688,7 @@ npfem_status npfem_net_create(npfem_plan* p, const npfem_net_config* cfg, const 
   }
   if ((s = net->buf.upload(md.data(), md.size(), &net->d_meshes))) return s;
   net->fwd_lds = std::getenv("NPFEM_NET_NO_LDS") ? 0 : net_forward_lds_bytes(net->n_pad_max, net->nb_deg_max);
+  net->inf_lds = std::getenv("NPFEM_NET_NO_LDS") ? 0 : net_infer_lds_bytes(net->n_pad_max, net->nb_deg_max);
   if ((s = net_upload_params(net.get(), theta, nullptr))) return s;
   *out = net.release();
   return NPFEM_OK;
@@ -1703,6 +1722,7 @@ npfem_status npfem_net_infer(npfem_net* net, npfem_batch* b, const void* x, cons
   if ((s = net_check_batch(net, b))) return s;
   HIP_TRY(hipSetDevice(b->plan->device));
   if ((s = net_inference_scratch(net))) return s;
+  if ((s = net_batch_frames(net, b))) return s;
   return net_infer_any(net, b, x, v, f, delta, static_cast<hipStream_t>(stream));
 }
 
@@ -1713,6 +1733,7 @@ npfem_status npfem_step_learned(npfem_batch* b, npfem_net* net, const void* x, c
   if ((s = net_check_batch(net, b))) return s;
   HIP_TRY(hipSetDevice(b->plan->device));
   if ((s = net_inference_scratch(net))) return s;
+  if ((s = net_batch_frames(net, b))) return s;
   if (!b->delta) {
     const size_t bytes = (size_t)b->n_vert * 3 * (b->plan->precision == NPFEM_FP64 ? 8 : 4);
     if ((s = b->dbuf.alloc(bytes, &b->delta))) return s;

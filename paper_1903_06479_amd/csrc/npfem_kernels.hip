@@ -1698,6 +1698,10 @@ __global__ void stats_reset_kernel(npfem_stats_total* tot) {
 
 }  // namespace
 
+// The library builds this file as two objects, NPFEM_PART 1 (the FP32 instantiations and
+// everything that is not a template) and NPFEM_PART 2 (the FP64 instantiations), so that
+// they compile in parallel; without NPFEM_PART it holds both.
+#if !defined(NPFEM_PART) || NPFEM_PART == 1
 // Device scratch of the allocation-free step (npfem_step_noalloc): the tile counter,
 // the cell states and the workspace of the persistent workgroups.  One copy per device,
 // held until the process ends.  Host code never uses this name as an address: it takes
@@ -1728,6 +1732,7 @@ int stage_cols(size_t lds, int stage_rows, int n_pad) {
   const long k32 = kc / 32 * 32;
   return (int)(k32 >= n_pad ? n_pad : (k32 >= 32 ? k32 : 0));
 }
+#endif
 
 template <typename Real>
 size_t lds_bytes(int n_pad, int chunk, int stage_rows, int vec_lds, int xu_lds) {
@@ -1839,6 +1844,7 @@ hipError_t launch_apply_inverse(const Real* A, int n_pad, const Real* in, Real* 
   return hipGetLastError();
 }
 
+#if !defined(NPFEM_PART) || NPFEM_PART == 1
 hipError_t launch_apply_inverse_bf16(const uint16_t* A, const float* diag, int n_pad, const float* in,
                                      float* out, int rows, hipStream_t s) {
   (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
@@ -1846,6 +1852,7 @@ hipError_t launch_apply_inverse_bf16(const uint16_t* A, const float* diag, int n
                      out, rows);
   return hipGetLastError();
 }
+#endif
 
 template <typename Real>
 hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, const int* cell_mesh,
@@ -1869,7 +1876,11 @@ hipError_t launch_drag(const Real* x, const Real* v, const int64_t* cell_voff, c
   template hipError_t launch_drag<R>(const R*, const R*, const int64_t*, const int*, const int*,   \
                                      int, const double*, const double*, const double*, double,     \
                                      double, double, double, R*, hipStream_t);
+#if !defined(NPFEM_PART) || NPFEM_PART == 1
 NPFEM_INSTANTIATE(float)
+#endif
+#if !defined(NPFEM_PART) || NPFEM_PART == 2
 NPFEM_INSTANTIATE(double)
+#endif
 
 }  // namespace npfem

@@ -14,6 +14,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "npfem_internal.h"
@@ -484,6 +485,309 @@ __global__ void __launch_bounds__(kNetLdsBlock) net_forward_lds_kernel(NetFwdArg
 }
 
 // ---------------------------------------------------------------------------------
+// Inference: the frame of every cell first (one wave per cell), then the network with
+// the cell's activations resident in LDS and updated in place.
+// ---------------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Per cell k: R (rest -> world, row-major), the displacement scale s, and the centroid,
+// mean velocity and mean acceleration used by the features (kNetFrame doubles).
+template <typename Real>
+__global__ void __launch_bounds__(256) net_frame_kernel(NetFwdArgs<Real> A) {
+  const int lane = tid() & 63;
+  const int k = blockIdx.x * 4 + (tid() >> 6);
+  if (k >= A.n_cells) return;
+  const int cell = A.cells ? A.cells[k] : k;
+  const NetMeshDev& M = A.meshes[A.cell_mesh[cell]];
+  const int n = M.n;
+  const int64_t voff = A.cell_voff[cell];
+  const Real* x = A.x + 3 * voff;
+  const Real* v = A.v + 3 * voff;
+  const Real* f = A.f + 3 * voff;
+  double s1[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = lane; i < n; i += 64) {
+    const double m = M.mass[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      s1[c] += m * (double)x[3 * i + c];
+      s1[3 + c] += m * (double)v[3 * i + c];
+      s1[6 + c] += (double)f[3 * i + c];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) s1[q] = wave_sum(s1[q]);
+  const double ims = 1.0 / M.mass_sum;
+  double fr[kNetFrame];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) fr[10 + q] = s1[q] * ims;      // x_c, v_c, a_c
+  double s2[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = lane; i < n; i += 64) {
+    const double m = M.mass[i];
+    double d[3], fd[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      d[c] = (double)x[3 * i + c] - fr[10 + c];
+      fd[c] = (double)f[3 * i + c] - m * fr[16 + c];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) s2[3 * a + b] += m * d[a] * M.Xc[3 * i + b];
+    s2[9] += fd[0] * fd[0] + fd[1] * fd[1] + fd[2] * fd[2];
+  }
+#pragma unroll
+  for (int q = 0; q < 10; ++q) s2[q] = wave_sum(s2[q]);
+  polar3(s2, fr);                                          // every lane, the same values
+  fr[9] = A.h * A.h * (sqrt(s2[9] / n) + A.W.force_floor) / M.mass_mean;
+  fr[19] = 0.0;
+  double* out = A.cframe + (size_t)k * kNetFrame;
+#pragma unroll
+  for (int q = 0; q < kNetFrame; ++q)
+    if (lane == q) out[q] = fr[q];
+}
+
+constexpr int kInfBlock = 512;
+constexpr int kInfWaves = kInfBlock / 64;
+constexpr int kInfMaxRegRounds = 3;            // row-block rounds whose results stay in registers
+
+// LDS of the resident inference: h [n_pad][kHP] bf16, the neighbour lists, the degrees,
+// then the staging of the rounds beyond kInfMaxRegRounds (16 KB per round).
+__host__ __device__ inline size_t infer_lds_base(int n_pad, int nb_deg) {
+  return ((size_t)n_pad * kHP * 2 + (size_t)nb_deg * n_pad * 2 + (size_t)n_pad + 15) / 16 * 16;
+}
+
+// One message-passing layer of the resident variant.  Every wave computes h + relu(z)
+// for its row blocks rb = wave + kInfWaves r: the first RL rounds into the LDS staging
+// area Ob (per block, 8 packed dwords per lane), the last RR rounds into registers;
+// after a barrier all of them are written over h in LDS (the layer reads every
+// neighbour's old h before any row is overwritten).  The neighbour sums take one bf16
+// half of a dword per dot2 instruction (the other half weighted 0), so activations are
+// added in FP32 without being unpacked first.
+template <int RR>
+__device__ __attribute__((always_inline)) inline void infer_layer(const NetWeights& W, int l, int n, int np,
+                                                                  int width, uint16_t* H, const uint16_t* nbl,
+                                                                  const uint8_t* degl, uint32_t* Ob, int RL) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const int lane = tid() & 63, wave = tid() >> 6, l16 = lane & 15, kq = lane >> 4;
+  const uint16_t* Wl = W.Wl + (size_t)l * kNetH * 2 * kNetH;
+  bf16x8 bq[4][4];
+  float bias[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) bq[s4][cb] = ld8(Wl + (size_t)(cb * 16 + l16) * 2 * kNetH + 32 * s4 + 8 * kq);
+    bias[cb] = W.theta[W.lay.b(l) + cb * 16 + l16];
+  }
+  const bf16x2 one_lo = {(__bf16)1.f, (__bf16)0.f}, one_hi = {(__bf16)0.f, (__bf16)1.f};
+  const bf16x2 zero2 = {(__bf16)0.f, (__bf16)0.f};
+  const int nrb = np >> 4;
+  // new h of row block rb: rows rb*16 + 4kq + i, column cb*16 + l16, as bf16 pairs over i
+  auto block = [&](int rb, uint32_t (&o)[8]) {
+    const int row = rb * 16 + l16;
+    bf16x8 aq[4];
+    aq[0] = ld8(H + (size_t)row * kHP + 8 * kq);
+    aq[1] = ld8(H + (size_t)row * kHP + 32 + 8 * kq);
+    float g[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) g[e] = 0.f;
+    const int dg = degl[row];                              // 0 for padding rows
+    auto add = [&](int j, bf16x2 wl, bf16x2 wh) {
+      const uint4 h0 = *reinterpret_cast<const uint4*>(H + (size_t)j * kHP + 8 * kq);
+      const uint4 h1 = *reinterpret_cast<const uint4*>(H + (size_t)j * kHP + 32 + 8 * kq);
+      const uint32_t w[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const bf16x2 p = __builtin_bit_cast(bf16x2, w[d]);
+        g[2 * d] = __builtin_amdgcn_fdot2_f32_bf16(p, wl, g[2 * d], false);
+        g[2 * d + 1] = __builtin_amdgcn_fdot2_f32_bf16(p, wh, g[2 * d + 1], false);
+      }
+    };
+    // the first kNetUnrollDeg ELL columns are read unconditionally (ELL padding points
+    // at the row itself) and weighted by q < degree; wider meshes go on in a loop
+#pragma unroll
+    for (int q = 0; q < kNetUnrollDeg; ++q) {
+      const int j = q < width ? (int)nbl[q * np + row] : row;
+      const bool on = q < dg;
+      add(j, on ? one_lo : zero2, on ? one_hi : zero2);
+    }
+    for (int q = kNetUnrollDeg; q < dg; ++q) add((int)nbl[q * np + row], one_lo, one_hi);
+    const float inv = dg > 0 ? 1.0f / (float)dg : 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      aq[2][e] = (__bf16)(g[e] * inv);
+      aq[3][e] = (__bf16)(g[8 + e] * inv);
+    }
+    floatx4 acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[s4], bq[s4][cb], acc[cb], 0, 0, 0);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      float hv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r2 = rb * 16 + 4 * kq + i;
+        const float z = acc[cb][i] + bias[cb];
+        hv[i] = r2 < n ? bf2f(H[(size_t)r2 * kHP + cb * 16 + l16]) + fmaxf(z, 0.f) : 0.f;
+      }
+      o[2 * cb] = __builtin_bit_cast(uint32_t, bf16x2{(__bf16)hv[0], (__bf16)hv[1]});
+      o[2 * cb + 1] = __builtin_bit_cast(uint32_t, bf16x2{(__bf16)hv[2], (__bf16)hv[3]});
+    }
+  };
+  auto put = [&](int rb, const uint32_t (&o)[8]) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r2 = rb * 16 + 4 * kq + i;
+        const uint32_t w = o[2 * cb + (i >> 1)];
+        H[(size_t)r2 * kHP + cb * 16 + l16] = (uint16_t)((i & 1) ? (w >> 16) : (w & 0xffffu));
+      }
+  };
+  uint32_t* ob = Ob + (size_t)wave * 8 * 64 + lane;        // this lane's dwords of round r: ob[r * kInfWaves * 512 + 64 d]
+  for (int r = 0; r < RL; ++r) {
+    const int rb = wave + kInfWaves * r;
+    if (rb >= nrb) break;                                  // uniform over the wave
+    uint32_t o[8];
+    block(rb, o);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) ob[(size_t)r * kInfWaves * 512 + 64 * d] = o[d];
+  }
+  uint32_t out[RR][8];
+#pragma unroll
+  for (int r = 0; r < RR; ++r) {
+    const int rb = wave + kInfWaves * (RL + r);
+    if (rb >= nrb) break;
+    block(rb, out[r]);
+  }
+  __syncthreads();
+  for (int r = 0; r < RL; ++r) {
+    const int rb = wave + kInfWaves * r;
+    if (rb >= nrb) break;
+    uint32_t o[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) o[d] = ob[(size_t)r * kInfWaves * 512 + 64 * d];
+    put(rb, o);
+  }
+#pragma unroll
+  for (int r = 0; r < RR; ++r) {
+    const int rb = wave + kInfWaves * (RL + r);
+    if (rb >= nrb) break;
+    put(rb, out[r]);
+  }
+  __syncthreads();
+}
+
+// Resident inference: one cell at a time per workgroup (512 threads), its activations
+// [n_pad][kHP] and its mesh's neighbour lists in LDS.  The encoder computes each row's
+// features from x_n, v_n, F_ext and the cell's frame as it forms its operand.
+template <typename Real, int RR>
+__global__ void __launch_bounds__(kInfBlock) net_infer_kernel(NetFwdArgs<Real> A, int RL) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int np_max = A.S.n_pad_max;
+  uint16_t* H = reinterpret_cast<uint16_t*>(lds);
+  uint16_t* nbl = H + (size_t)np_max * kHP;
+  uint8_t* degl = reinterpret_cast<uint8_t*>(nbl + (size_t)A.nb_deg_max * np_max);
+  uint32_t* Ob = reinterpret_cast<uint32_t*>(lds + infer_lds_base(np_max, A.nb_deg_max));
+  const int lane = tid() & 63, wave = tid() >> 6, l16 = lane & 15, kq = lane >> 4;
+  const NetLayout L = A.W.lay;
+  int staged = -1;
+  for (int k = blockIdx.x; k < A.n_cells; k += gridDim.x) {
+    const int cell = A.cells ? A.cells[k] : k;
+    const int mi = A.cell_mesh[cell];
+    const NetMeshDev& M = A.meshes[mi];
+    const int n = M.n, np = M.n_pad, nrb = np >> 4;
+    const int64_t voff = A.cell_voff[cell];
+    __syncthreads();                                       // the previous cell's decoder is done with H
+    if (mi != staged) {                                    // neighbour lists of this mesh type
+      for (int e = tid(); e < M.nb_deg * np; e += kInfBlock) nbl[e] = (uint16_t)M.nb_ell[e];
+      for (int i = tid(); i < np; i += kInfBlock) degl[i] = (uint8_t)(i < n ? M.nb_ptr[i + 1] - M.nb_ptr[i] : 0);
+      staged = mi;
+    }
+    const double* fr = A.cframe + (size_t)k * kNetFrame;
+    // ---- encoder: features of row l16 (lanes kq = 0, 1 hold features 0-7, 8-11) --------
+    {
+      bf16x8 be[4];
+      float bias_e[4];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        be[cb] = ld8(A.W.We + (size_t)(cb * 16 + l16) * kNetFeatPad + 8 * kq);
+        bias_e[cb] = A.W.theta[L.off_be + cb * 16 + l16];
+      }
+      float R[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) R[q] = (float)fr[q];
+      const double s = fr[9];
+      const float hs = (float)(A.h / s), h2s = (float)(A.h * A.h / s), iq = (float)(1.0 / A.W.shape_scale);
+      const float irho = (float)M.inv_rho;
+      for (int rb = wave; rb < nrb; rb += kInfWaves) {
+        const int row = rb * 16 + l16;
+        float fv[kNetFeat];
+#pragma unroll
+        for (int q = 0; q < kNetFeat; ++q) fv[q] = 0.f;
+        if (row < n && kq < 2) {
+          const Real* xr = A.x + 3 * (voff + row);
+          const Real* vr = A.v + 3 * (voff + row);
+          const Real* fq = A.f + 3 * (voff + row);
+          const double m = M.mass[row];
+          float d[3], dv[3], df[3], Xa[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            d[c] = (float)((double)xr[c] - fr[10 + c]);
+            dv[c] = (float)((double)vr[c] - fr[13 + c]);
+            df[c] = (float)((double)fq[c] - m * fr[16 + c]);
+            Xa[c] = (float)M.Xc[3 * row + c];
+          }
+          const float im = (float)(1.0 / m);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            float rd = 0.f, rv = 0.f, rf = 0.f;            // (R^T w)_a = sum_b R[b][a] w_b
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              rd += R[3 * b + a] * d[b];
+              rv += R[3 * b + a] * dv[b];
+              rf += R[3 * b + a] * df[b];
+            }
+            fv[a] = (rd - Xa[a]) * iq;
+            fv[3 + a] = rv * hs;
+            fv[6 + a] = rf * h2s * im;
+            fv[9 + a] = Xa[a] * irho;
+          }
+        }
+        bf16x8 aq;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) aq[e] = (__bf16)(kq == 0 ? fv[e] : (kq == 1 && e < 4 ? fv[8 + e] : 0.f));
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, be[cb], floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r2 = rb * 16 + 4 * kq + i;
+            const float z = r2 < n ? acc[i] + bias_e[cb] : 0.f;
+            H[(size_t)r2 * kHP + cb * 16 + l16] = f2bf(fmaxf(z, 0.f));
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int l = 0; l < L.layers; ++l) infer_layer<RR>(A.W, l, n, np, M.nb_deg, H, nbl, degl, Ob, RL);
+    // ---- decoder (the frame's R and s, read from memory) --------------------------------
+    double fr2[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) fr2[q] = fr[q];
+    decoder_rows<Real, kInfWaves>(A, k, voff, n, np, H, kHP, fr2);
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // Loss: target t = R^T delta* / s with delta* = x_{n+1} - x_n - u0 = x_{n+1} - y_n,
 // squared error, dLoss/do.
 // ---------------------------------------------------------------------------------
@@ -769,6 +1073,41 @@ hipError_t launch_net_forward(const NetFwdArgs<Real>& a, int grid, size_t lds_by
   return hipGetLastError();
 }
 
+namespace {
+int infer_rounds(int n_pad) { return (n_pad / 16 + kInfWaves - 1) / kInfWaves; }
+}  // namespace
+
+size_t net_infer_lds_bytes(int n_pad, int nb_deg) {
+  const int lds_rounds = std::max(0, infer_rounds(n_pad) - kInfMaxRegRounds);
+  const size_t r = infer_lds_base(n_pad, nb_deg) + (size_t)lds_rounds * kInfWaves * 512 * 4;
+  return r <= 160 * 1024 && nb_deg <= 255 && n_pad <= 65535 ? r : 0;
+}
+
+template <typename Real, int RR>
+hipError_t launch_infer_rr(const NetFwdArgs<Real>& a, int grid, size_t lds, int RL, hipStream_t s) {
+  const void* fn = reinterpret_cast<const void*>(&net_infer_kernel<Real, RR>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((net_infer_kernel<Real, RR>), dim3(grid), dim3(kInfBlock), lds, s, a, RL);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_net_infer(const NetFwdArgs<Real>& a, int grid, size_t lds_bytes, hipStream_t s) {
+  (void)hipGetLastError();
+  if (!a.cframe || a.n_cells < 1 || grid < 1) return hipErrorInvalidValue;
+  const size_t need = net_infer_lds_bytes(a.S.n_pad_max, a.nb_deg_max);
+  if (need == 0 || lds_bytes < need) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(net_frame_kernel<Real>, dim3((a.n_cells + 3) / 4), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int rounds = infer_rounds(a.S.n_pad_max);
+  const int RL = std::max(0, rounds - kInfMaxRegRounds);   // rounds staged in LDS
+  if (rounds <= 1) return launch_infer_rr<Real, 1>(a, grid, lds_bytes, 0, s);
+  if (rounds == 2) return launch_infer_rr<Real, 2>(a, grid, lds_bytes, 0, s);
+  return launch_infer_rr<Real, kInfMaxRegRounds>(a, grid, lds_bytes, RL, s);
+}
+
 template <typename Real>
 hipError_t launch_net_loss(const NetLossArgs<Real>& a, hipStream_t s) {
   (void)hipGetLastError();
@@ -814,6 +1153,8 @@ hipError_t launch_fill_zero(float* p, int64_t count, hipStream_t s) {
 
 template hipError_t launch_net_forward<float>(const NetFwdArgs<float>&, int, size_t, hipStream_t);
 template hipError_t launch_net_forward<double>(const NetFwdArgs<double>&, int, size_t, hipStream_t);
+template hipError_t launch_net_infer<float>(const NetFwdArgs<float>&, int, size_t, hipStream_t);
+template hipError_t launch_net_infer<double>(const NetFwdArgs<double>&, int, size_t, hipStream_t);
 template hipError_t launch_net_loss<float>(const NetLossArgs<float>&, hipStream_t);
 template hipError_t launch_net_loss<double>(const NetLossArgs<double>&, hipStream_t);
 

@@ -18,6 +18,7 @@ constexpr int kNetH = 64;          // hidden width (fixed: four 16-wide MFMA col
 constexpr int kNetFeat = 12;       // node features
 constexpr int kNetFeatPad = 32;    // features padded to one BF16 MFMA k step
 constexpr int kNetMaxLayers = 8;
+constexpr int kNetFrame = 20;      // per-cell frame of inference: R (9), s, x_c (3), v_c (3), a_c (3), unused
 
 // Per mesh type: what the network needs of the rest mesh.
 struct NetMeshDev {
@@ -94,6 +95,7 @@ struct NetFwdArgs {
   const Real* v;
   const Real* f;
   Real* delta;                 // [V][3] world-frame correction (inference), or null
+  double* cframe;              // [n_cells][kNetFrame] frames of the resident inference
 };
 
 template <typename Real>
@@ -134,6 +136,12 @@ hipError_t launch_net_forward(const NetFwdArgs<Real>& a, int grid, size_t lds_by
 // LDS the resident variant needs for meshes up to n_pad rows and degree nb_deg (0 if it
 // does not fit a compute unit).
 size_t net_forward_lds_bytes(int n_pad, int nb_deg);
+// Inference with the cell's activations resident in LDS (meshes with n_pad <= 1024): a
+// frame kernel (one wave per cell, into a.cframe), then the network (512 threads per
+// cell, one workgroup per CU).  lds_bytes from net_infer_lds_bytes, 0 if it does not fit.
+template <typename Real>
+hipError_t launch_net_infer(const NetFwdArgs<Real>& a, int grid, size_t lds_bytes, hipStream_t s);
+size_t net_infer_lds_bytes(int n_pad, int nb_deg);
 template <typename Real>
 hipError_t launch_net_loss(const NetLossArgs<Real>& a, hipStream_t s);
 hipError_t launch_net_backward(const NetBwdArgs& a, int grid, hipStream_t s);

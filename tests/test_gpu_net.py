@@ -111,6 +111,36 @@ def test_inference_matches_oracle(precision, n_verts, variant, monkeypatch):
         assert relerr(delta[s], ref) <= REL, (c, relerr(delta[s], ref))
 
 
+def test_inference_on_a_mixed_batch_matches_oracle():
+    """Resident inference over more cells than workgroups, with the 258- and 642-vertex
+    meshes interleaved: each workgroup carries several cells in turn and restages the
+    neighbour lists when the mesh type changes.  Sampled cells (every 7th and the last
+    40, which are each workgroup's second or third cell) against the oracle network."""
+    from paper_1903_06479_amd import Batch, Net
+    cfg = mp.NetConfig()
+    b = workloads.uneven(n_cells=700, seed=43, sizes=(258, 642), counts=(0.5, 0.5))
+    sizes = sorted(b.meshes)
+    rng = np.random.default_rng(43)
+    x = rounded(b.x)
+    v = rounded(0.05 * rng.standard_normal(b.x.shape))
+    f = rounded(workloads.drag_forces(b, x, v) + 5.0 * rng.standard_normal(b.x.shape))
+    plan = make([b.meshes[n] for n in sizes], "fp32")
+    cm = np.array([sizes.index(int(n)) for n in b.cell_nverts], np.int32)
+    assert 0 < cm.sum() < len(cm)
+    batch = Batch(plan, cm)
+    theta = gpu_params(cfg, 5)
+    net = Net(plan, theta.astype(np.float32))
+    delta = net.infer(batch, T(x), T(v), T(f)).cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(delta))
+    models = {n: oracle_model(n) for n in sizes}
+    mats = {n: mp.neighbour_mean_matrix(len(b.meshes[n][0]), b.meshes[n][1]) for n in sizes}
+    for c in sorted(set(range(0, b.n_cells, 7)) | set(range(b.n_cells - 40, b.n_cells))):
+        n = int(b.cell_nverts[c])
+        s = b.cell_slice(c)
+        ref = mp.predict_delta(theta, b.meshes[n][0], x[s], v[s], f[s], models[n].mass, DT, mats[n], cfg)
+        assert relerr(delta[s], ref) <= REL, (c, n, relerr(delta[s], ref))
+
+
 def test_loss_and_gradient_match_oracle():
     """Loss and gradient of a minibatch (a list of batch cells) against the oracle."""
     from paper_1903_06479_amd import Batch, Net
