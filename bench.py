@@ -557,7 +557,8 @@ def main():
                "evaluations_mean": tot["evaluations"] / cs, "halvings_mean": tot["halvings"] / cs,
                "converged_fraction": 1.0 - tot["not_converged"] / cs,
                "not_converged_cell_steps": tot["not_converged"],
-               "status_counts": dict(zip(("maxiter", "ls_fail", "nonfinite", "degenerate_tri"), tot["status_count"])),
+               "status_counts": dict(zip(("maxiter", "ls_fail", "nonfinite", "degenerate_tri"), tot["status_count"]),
+                                     start_fallback=tot["start_fallback"]),
                "max_residual": tot["max_residual"],
                "stats_over": f"all {args.steps} timed steps ({cs} cell-steps)",
                "graph_captures_timed": g1["captures"] - g0["captures"],

@@ -64,6 +64,9 @@ typedef enum { NPFEM_FP32 = 0, NPFEM_FP64 = 1 } npfem_precision;
 #define NPFEM_DEGENERATE_TRI 16u  /* a triangle of x_{n+1} is collapsed (area below 1e-6 of its rest
                                      area): its in-plane direction normal to the collapse is
                                      undefined and carries no force */
+#define NPFEM_START_FALLBACK 32u  /* npfem_step_learned: the learned start y_n + delta did not lower
+                                     the objective below its value at y_n, so the cell started
+                                     from y_n (as npfem_step does) */
 
 typedef struct npfem_mesh npfem_mesh;
 typedef struct npfem_plan npfem_plan;
@@ -136,7 +139,7 @@ typedef struct {
   int64_t not_converged;    /* cells without NPFEM_CONVERGED */
   int64_t status_count[4];
   int32_t max_iterations;
-  int32_t reserved;
+  int32_t start_fallback;   /* cells with NPFEM_START_FALLBACK */
   double max_residual;
 } npfem_stats_total;
 
@@ -388,8 +391,13 @@ npfem_status npfem_net_infer(npfem_net *net, npfem_batch *batch, const void *x, 
 
 /*
  * One step that starts from y_n + delta (delta from the network) instead of y_n; otherwise
- * identical to npfem_step (same outputs, statistics and convergence test).  Honours the
- * batch's graph setting (the network and the step are captured together).
+ * identical to npfem_step (same outputs, statistics and convergence test).  The objective
+ * g (eq. GeneralizedObjectiveFunction) is evaluated at y_n and at y_n + delta, and each
+ * cell starts from y_n + delta only if g(y_n + delta) <= g(y_n); otherwise it starts from
+ * y_n and its status carries NPFEM_START_FALLBACK (the quasi-Newton iterations and their
+ * convergence test judge the result either way).  Both evaluations count in the cell's
+ * `evaluations`.  Honours the batch's graph setting (the network and the step are
+ * captured together).
  */
 npfem_status npfem_step_learned(npfem_batch *batch, npfem_net *net, const void *x, const void *v,
                                 const void *f_ext, void *x_out, void *v_out,

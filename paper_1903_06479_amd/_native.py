@@ -35,10 +35,10 @@ CELL_STATS_DTYPE = np.dtype([("iterations", np.int32), ("evaluations", np.int32)
 
 STATS_TOTAL_DTYPE = np.dtype([("cell_steps", np.int64), ("iterations", np.int64), ("evaluations", np.int64),
                               ("halvings", np.int64), ("not_converged", np.int64), ("status_count", np.int64, (4,)),
-                              ("max_iterations", np.int32), ("reserved", np.int32), ("max_residual", np.float64)])
+                              ("max_iterations", np.int32), ("start_fallback", np.int32), ("max_residual", np.float64)])
 
 FP32, FP64 = 0, 1
-CONVERGED, MAXITER, LS_FAIL, NONFINITE, DEGENERATE_TRI = 1, 2, 4, 8, 16
+CONVERGED, MAXITER, LS_FAIL, NONFINITE, DEGENERATE_TRI, START_FALLBACK = 1, 2, 4, 8, 16, 32
 N_TERMS = 11
 VOLUME_STEP_FROZEN, VOLUME_PAPER_LITERAL = 0, 1
 

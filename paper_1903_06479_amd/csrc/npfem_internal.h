@@ -73,6 +73,7 @@ struct CellStateT {
   double SY[H][H];             // s_i . y_j over the history slots
   int hist_n, hist_head, iter, evals, status, active, retry, halvings;
   int degen;                   // the current iterate has a collapsed triangle
+  int fallback;                // the learned start raised the objective: started from y_n
 };
 using CellState = CellStateT<kMaxHistory>;
 

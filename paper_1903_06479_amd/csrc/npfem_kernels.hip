@@ -1044,7 +1044,8 @@ __device__ void finalize_cell(const StepArgs<Real>& A, const MeshDev<Real>& M, i
     npfem_cell_stats st;
     st.iterations = cs.iter;
     st.evaluations = cs.evals;
-    st.status = (uint32_t)cs.status | ((cs.degen && !(cs.status & NPFEM_NONFINITE)) ? NPFEM_DEGENERATE_TRI : 0u);
+    st.status = (uint32_t)cs.status | ((cs.degen && !(cs.status & NPFEM_NONFINITE)) ? NPFEM_DEGENERATE_TRI : 0u) |
+                (cs.fallback ? NPFEM_START_FALLBACK : 0u);
     st.halvings = cs.halvings;
     st.residual = cs.resid;
     st.objective = cs.E;
@@ -1125,7 +1126,7 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
       auto& cs = CS[j];
       cs.Gn = Gn;
       cs.GA = GA;
-      cs.hist_n = cs.hist_head = cs.iter = cs.evals = cs.status = cs.retry = cs.halvings = cs.degen = 0;
+      cs.hist_n = cs.hist_head = cs.iter = cs.evals = cs.status = cs.retry = cs.halvings = cs.degen = cs.fallback = 0;
       cs.active = 1;
     }
     __syncthreads();
@@ -1133,24 +1134,23 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
   if (!A.u_guess) {
     tile_product(M, A.sol, 1, tl.mat(VB), tl.mat(VU), 3 * cnt, stage, A.stage_k);                                              // u = h^2 M~^-1 b
     __syncthreads();
-    if (A.guess_only || A.u_delta) {
+    if (A.guess_only) {
       for (int j = 0; j < cnt; ++j) {
         const int64_t voff = s_voff[j];
-        Real* U = tl.vec(VU, j);
+        const Real* U = tl.vec(VU, j);
         for (int e = tid(); e < len; e += kBlock) {
           const int c = e / np, i = e - c * np;
-          if (i < n) {
-            if (A.guess_only) A.x_out[3 * (voff + i) + c] = U[e];
-            else U[e] += A.u_delta[3 * (voff + i) + c];
-          }
+          if (i < n) A.x_out[3 * (voff + i) + c] = U[e];
         }
       }
-      __syncthreads();
-      if (A.guess_only) return;
+      return;
     }
   }
 
   // ---- first evaluation ---------------------------------------------------------
+  // With a learned correction delta the cell is evaluated at y_n and at y_n + delta and
+  // goes on from y_n + delta only if that does not raise the objective; otherwise it
+  // starts from y_n as the plain step does (status bit NPFEM_START_FALLBACK).
   for (int j = 0; j < cnt; ++j) {
     stage_aos(xn, A.x + 3 * s_voff[j], n, np);
     vcopy(ut, tl.vec(VU, j), len);
@@ -1158,17 +1158,37 @@ __device__ __attribute__((always_inline)) inline void run_tile(const StepArgs<Re
     __syncthreads();
     EvalResult r;
     evaluate<Real, EXT>(M, A.mat, literal, h, CS[j].Gn, CS[j].GA, contacts(j), xn, ut, bvec(j), work, gvec(j), red, r);
+    bool fallback = false;
+    vcopy(tl.vec(VG, j), gvec(j), len);
+    if (A.u_delta) {
+      const int64_t voff = s_voff[j];
+      for (int e = tid(); e < len; e += kBlock) {
+        const int c = e / np, i = e - c * np;
+        if (i < n) ut[e] += A.u_delta[3 * (voff + i) + c];
+      }
+      __syncthreads();                                           // VG holds grad g(y_n); ut = u0 + delta
+      EvalResult r1;
+      evaluate<Real, EXT>(M, A.mat, literal, h, CS[j].Gn, CS[j].GA, contacts(j), xn, ut, bvec(j), work, gvec(j), red,
+                          r1);
+      if (isfinite(r1.E) && isfinite(r1.resid) && r1.E <= r.E) {
+        r = r1;
+        vcopy(tl.vec(VU, j), ut, len);
+        vcopy(tl.vec(VG, j), gvec(j), len);
+      } else {
+        fallback = true;
+      }
+    }
     const bool bad = !isfinite(r.E) || !isfinite(r.resid);
     const bool done = bad || r.resid <= A.sol.tol;
-    vcopy(tl.vec(VG, j), gvec(j), len);
-    if (!done) vcopy(tl.vec(VQ, j), gvec(j), len);
+    if (!done) vcopy(tl.vec(VQ, j), fallback ? tl.vec(VG, j) : gvec(j), len);
     if (tid() == 0) {
       auto& cs = CS[j];
       cs.E = r.E;
       cs.noise = r.noise;
       cs.resid = r.resid;
-      cs.evals = 1;
+      cs.evals = A.u_delta ? 2 : 1;
       cs.degen = r.degen > 0.0;
+      cs.fallback = fallback;
       s_vol[j] = r.vol;
       s_area[j] = r.area;
       if (bad) { cs.status = NPFEM_NONFINITE; cs.active = 0; }
@@ -1639,10 +1659,10 @@ __global__ void drag_kernel(const Real* x, const Real* v, const int64_t* cell_vo
 __global__ void __launch_bounds__(kBlock) stats_accumulate_kernel(const npfem_cell_stats* st, int64_t n,
                                                                   npfem_stats_total* tot) {
   __shared__ long long s_sum[kBlock / 64][9];
-  __shared__ int s_max[kBlock / 64];
+  __shared__ int s_max[kBlock / 64], s_fb[kBlock / 64];
   __shared__ double s_res[kBlock / 64];
   long long v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // cells, iterations, evaluations, halvings, not converged, 4 status bits
-  int mx = 0;
+  int mx = 0, fb = 0;
   double rmax = 0.0;
   for (int64_t c = (int64_t)blockIdx.x * kBlock + tid(); c < n; c += (int64_t)gridDim.x * kBlock) {
     const npfem_cell_stats a = st[c];
@@ -1655,6 +1675,7 @@ __global__ void __launch_bounds__(kBlock) stats_accumulate_kernel(const npfem_ce
     v[6] += (a.status & NPFEM_LS_FAIL) ? 1 : 0;
     v[7] += (a.status & NPFEM_NONFINITE) ? 1 : 0;
     v[8] += (a.status & NPFEM_DEGENERATE_TRI) ? 1 : 0;
+    fb += (a.status & NPFEM_START_FALLBACK) ? 1 : 0;
     mx = max(mx, a.iterations);
     rmax = fmax(rmax, a.residual);
   }
@@ -1662,6 +1683,7 @@ __global__ void __launch_bounds__(kBlock) stats_accumulate_kernel(const npfem_ce
 #pragma unroll
     for (int k = 0; k < 9; ++k) v[k] += __shfl_xor(v[k], off);
     mx = max(mx, __shfl_xor(mx, off));
+    fb += __shfl_xor(fb, off);
     rmax = fmax(rmax, __shfl_xor(rmax, off));
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1669,6 +1691,7 @@ __global__ void __launch_bounds__(kBlock) stats_accumulate_kernel(const npfem_ce
 #pragma unroll
     for (int k = 0; k < 9; ++k) s_sum[wave][k] = v[k];
     s_max[wave] = mx;
+    s_fb[wave] = fb;
     s_res[wave] = rmax;
   }
   __syncthreads();
@@ -1677,6 +1700,7 @@ __global__ void __launch_bounds__(kBlock) stats_accumulate_kernel(const npfem_ce
 #pragma unroll
       for (int k = 0; k < 9; ++k) v[k] += s_sum[w][k];
       mx = max(mx, s_max[w]);
+      fb += s_fb[w];
       rmax = fmax(rmax, s_res[w]);
     }
     unsigned long long* t = reinterpret_cast<unsigned long long*>(tot);
@@ -1687,6 +1711,7 @@ __global__ void __launch_bounds__(kBlock) stats_accumulate_kernel(const npfem_ce
     atomicAdd(&t[4], (unsigned long long)v[4]);
     for (int k = 0; k < 4; ++k) atomicAdd(&t[5 + k], (unsigned long long)v[5 + k]);
     atomicMax(&tot->max_iterations, mx);
+    atomicAdd(&tot->start_fallback, fb);
     // residuals are >= 0 (or +inf / NaN), so their bit patterns order like the values
     atomicMax(reinterpret_cast<unsigned long long*>(&tot->max_residual), (unsigned long long)__double_as_longlong(rmax));
   }

@@ -330,8 +330,7 @@ class StatsTotal:
 
     def read(self) -> dict:
         a = self.buf.cpu().numpy().view(N.STATS_TOTAL_DTYPE)[0]
-        return {k: (a[k].tolist() if a[k].shape else a[k].item()) for k in N.STATS_TOTAL_DTYPE.names
-                if k != "reserved"}
+        return {k: (a[k].tolist() if a[k].shape else a[k].item()) for k in N.STATS_TOTAL_DTYPE.names}
 
 
 def default_net_config(**overrides) -> N.NetConfig:

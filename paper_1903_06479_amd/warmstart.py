@@ -6,8 +6,9 @@ and keeps the trajectories in device memory.
     python -m paper_1903_06479_amd.warmstart --out weights.npy [--epochs E] [--runs R]
 
 trains the network on the shear-flow training workload (1,024 cells of the 642-vertex
-mesh per run, shear rates U[50, 2000] 1/s, runs 0..R-1, 50 steps each), evaluates it
-on the held-out runs 100..103 and writes the FP32 parameters.
+mesh per run, shear rates U[50, 2000] 1/s, runs 0..R-1, 50 steps each), keeps the
+parameters of the epoch with the lowest loss on the validation runs 150.., evaluates
+them on the held-out runs 100..103 and writes the FP32 parameters.
 """
 from __future__ import annotations
 
@@ -58,10 +59,38 @@ def collect(batch: Batch, flow: Flow, x0, v0, steps: int):
     return traj
 
 
+def dataset_loss(net: Net, batch: Batch, trajs: list, minibatch: int = 256) -> dict:
+    """The loss over every (step, cell) sample of the trajectories, without an update: the
+    mean over all samples, over the first steps (from the perturbed rest shapes) and over
+    the later steps."""
+    import torch
+    dev = trajs[0]["x"][0].device
+    n = batch.n_cells
+    grad = torch.empty(net.n_params, dtype=torch.float32, device=dev)
+    sums = {"first": [0.0, 0], "later": [0.0, 0]}
+    for tr in trajs:
+        for s in range(len(tr["x"])):
+            part = sums["first" if s == 0 else "later"]
+            for c0 in range(0, n, minibatch):
+                k = min(minibatch, n - c0)
+                cells = torch.arange(c0, c0 + k, dtype=torch.int32, device=dev)
+                loss, _ = net.loss_grad(batch, tr["x"][s], tr["v"][s], tr["f"][s], tr["x_next"][s], tr["u0"][s],
+                                        cells=cells, grad=grad)
+                part[0] += loss * k
+                part[1] += k
+    tot = sums["first"][0] + sums["later"][0]
+    cnt = sums["first"][1] + sums["later"][1]
+    return {"mean": tot / cnt, "first": sums["first"][0] / max(1, sums["first"][1]),
+            "later": sums["later"][0] / max(1, sums["later"][1])}
+
+
 def train(net: Net, batch: Batch, trajs: list, epochs: int, minibatch: int = 256, lr: float = 1e-3,
-          lr_final: float = 1e-4, seed: int = 0, log=None):
+          lr_final: float = 1e-4, seed: int = 0, log=None, val: list | None = None):
     """Adam over (step, cell subset) minibatches of every trajectory, with the learning rate
-    decaying geometrically from lr to lr_final.  Returns the mean loss of each epoch."""
+    decaying geometrically from lr to lr_final.  With validation trajectories `val`, their
+    whole loss is computed after every epoch and the network ends with the parameters of
+    the best epoch.  Returns one record per epoch: the mean of the training losses sampled
+    during the epoch and, with `val`, the validation losses."""
     import torch
     rng = np.random.default_rng(seed)
     dev = trajs[0]["x"][0].device
@@ -70,6 +99,7 @@ def train(net: Net, batch: Batch, trajs: list, epochs: int, minibatch: int = 256
     per_epoch = len(samples) * ((n + minibatch - 1) // minibatch)
     total = epochs * per_epoch
     history = []
+    best = (np.inf, None, -1)
     it = 0
     for ep in range(epochs):
         t0 = time.time()
@@ -89,17 +119,30 @@ def train(net: Net, batch: Batch, trajs: list, epochs: int, minibatch: int = 256
                 net.adam_step(g, lr=rate)
                 it += 1
         torch.cuda.synchronize()
-        history.append(float(np.mean(losses)))
+        rec = {"epoch": ep + 1, "train_sampled": float(np.mean(losses))}
+        if val:
+            vl = dataset_loss(net, batch, val, minibatch)
+            rec.update({"val": vl["mean"], "val_first": vl["first"], "val_later": vl["later"]})
+            if vl["mean"] < best[0]:
+                best = (vl["mean"], net.get_params(), ep + 1)
+        history.append(rec)
         if log:
-            log(f"[train] epoch {ep + 1}/{epochs}: loss {history[-1]:.4e} ({time.time() - t0:.1f}s)")
+            log(f"[train] epoch {ep + 1}/{epochs}: {rec} ({time.time() - t0:.1f}s)")
+    if best[1] is not None:
+        net.set_params(best[1])
+        if log:
+            log(f"[train] kept the parameters of epoch {best[2]} (validation loss {best[0]:.4e})")
     return history
 
 
-def compare(batch: Batch, net: Net, traj: dict, diameter: float):
+def compare(batch: Batch, net: Net, traj: dict, diameter: float, g_rel: float = 1e-6):
     """Plain and learned steps from the same states of a held-out trajectory: iterations,
-    convergence, and the position difference relative to the cell diameter."""
+    convergence, the position difference relative to the cell diameter and, where the two
+    end more than 1e-5 D apart (different stationary points of a non-convex objective),
+    whether the learned one has the higher objective g (beyond g_rel |g|)."""
     import torch
-    it_p, it_l, dx, conv = [], [], [], []
+    it_p, it_l, dx, conv, fb = [], [], [], [], 0
+    higher, lower = 0, 0
     off = batch.offsets
     for s in range(len(traj["x"])):
         x, v, f = traj["x"][s], traj["v"][s], traj["f"][s]
@@ -108,9 +151,18 @@ def compare(batch: Batch, net: Net, traj: dict, diameter: float):
         sp, sl = batch.stats_to_numpy(sp), batch.stats_to_numpy(sl)
         it_p.append(sp["iterations"].astype(np.float64))
         it_l.append(sl["iterations"].astype(np.float64))
-        conv.append(bool(np.all(sp["status"] == N.CONVERGED) and np.all(sl["status"] == N.CONVERGED)))
+        conv.append(bool(np.all(sp["status"] & N.CONVERGED) and np.all(sl["status"] & N.CONVERGED)))
+        fb += int(np.sum((sl["status"] & N.START_FALLBACK) != 0))
         d = (xl - xp).abs().amax(dim=1).cpu().numpy()          # per vertex
-        dx.append(np.maximum.reduceat(d, off[:-1]) / diameter)  # per cell
+        dcell = np.maximum.reduceat(d, off[:-1]) / diameter     # per cell
+        dx.append(dcell)
+        if np.any(dcell > 1e-5):
+            _, tp = batch.eval(x, v, f, xp - x)
+            _, tl = batch.eval(x, v, f, xl - x)
+            gp, gl = tp[:, 0].cpu().numpy(), tl[:, 0].cpu().numpy()
+            far = dcell > 1e-5
+            higher += int(np.sum(far & (gl > gp + g_rel * np.abs(gp))))
+            lower += int(np.sum(far & (gl <= gp + g_rel * np.abs(gp))))
     torch.cuda.synchronize()
     it_p, it_l, dx = np.concatenate(it_p), np.concatenate(it_l), np.concatenate(dx)
     return {"iterations_plain": float(it_p.mean()), "iterations_learned": float(it_l.mean()),
@@ -119,6 +171,9 @@ def compare(batch: Batch, net: Net, traj: dict, diameter: float):
             "all_converged": all(conv), "max_dx_over_D": float(dx.max()),
             "median_dx_over_D": float(np.median(dx)),
             "cell_steps_dx_above_1e-5": int(np.sum(dx > 1e-5)),
+            "dx_above_1e-5_learned_objective_higher": higher,
+            "dx_above_1e-5_learned_objective_lower": lower,
+            "start_fallback": fb,
             "first_step_max_dx_over_D": float(dx[:batch.n_cells].max()),
             "cell_steps": int(it_p.size)}
 
@@ -146,6 +201,7 @@ def main(argv=None):
     ap.add_argument("--runs", type=int, default=4)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--cells", type=int, default=1024)
+    ap.add_argument("--val-runs", type=int, default=1, help="validation runs 150.. (model selection)")
     ap.add_argument("--eval-runs", type=int, default=4)
     ap.add_argument("--eval-steps", type=int, default=10)
     ap.add_argument("--minibatch", type=int, default=256)
@@ -180,14 +236,23 @@ def main(argv=None):
             trajs.append(collect(batch64, flow, x, v, args.steps))
             log(f"[data] run {r}: {args.steps} steps, mean iterations {np.mean(trajs[-1]['iterations']):.2f} "
                 f"({time.time() - t0:.1f}s)")
+        val = []
+        for r in range(args.val_runs):
+            b = workloads.training(150 + r, n_cells=args.cells)
+            flow = Flow(batch64, np.full(args.cells, workloads.drag_coefficient(642)), b.shear_rate, b.origin,
+                        b.poiseuille)
+            x, v = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (b.x, b.v))
+            val.append(collect(batch64, flow, x, v, args.steps))
+            log(f"[data] validation run {150 + r}: {args.steps} steps ({time.time() - t0:.1f}s)")
         net64 = Net(plan64, init_params(cfg, args.seed), cfg)
         t0 = time.time()
-        history = train(net64, batch64, trajs, args.epochs, args.minibatch, args.lr, args.lr_final, args.seed, log)
+        history = train(net64, batch64, trajs, args.epochs, args.minibatch, args.lr, args.lr_final, args.seed, log,
+                        val=val)
         t_train = time.time() - t0
         theta = net64.get_params()
         if args.out:
             np.save(args.out, theta)
-        del trajs
+        del trajs, val
         torch.cuda.empty_cache()
 
     # held-out evaluation in the FP32 configuration of the throughput runs
@@ -205,13 +270,17 @@ def main(argv=None):
     summary = {
         "train": {"runs": args.runs, "steps": args.steps, "cells": args.cells,
                   "samples": args.runs * args.steps * args.cells, "epochs": args.epochs,
-                  "loss_per_epoch": history, "seconds": t_train},
+                  "validation": {"runs": args.val_runs, "steps": args.steps},
+                  "per_epoch": history, "seconds": t_train},
         "heldout": {
             "cells": args.eval_runs * args.cells, "steps": args.eval_steps,
             "iterations_plain": float(np.mean([r["iterations_plain"] for r in results])),
             "iterations_learned": float(np.mean([r["iterations_learned"] for r in results])),
             "max_dx_over_D": float(max(r["max_dx_over_D"] for r in results)),
             "cell_steps_dx_above_1e-5": int(sum(r["cell_steps_dx_above_1e-5"] for r in results)),
+            "dx_above_1e-5_learned_objective_higher": int(sum(r["dx_above_1e-5_learned_objective_higher"]
+                                                              for r in results)),
+            "start_fallback": int(sum(r["start_fallback"] for r in results)),
             "first_step_max_dx_over_D": float(max(r["first_step_max_dx_over_D"] for r in results)),
             "all_converged": all(r["all_converged"] for r in results)},
     }

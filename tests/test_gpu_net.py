@@ -215,7 +215,7 @@ def test_gradient_is_deterministic_and_adam_matches_oracle():
 def test_learned_step_reaches_the_plain_solution():
     """Starting from y_n + delta changes only the path: the converged positions agree
     with the plain step within the FP32 tolerance, for any network output."""
-    from paper_1903_06479_amd import Batch, Net, CONVERGED
+    from paper_1903_06479_amd import Batch, Net, CONVERGED, START_FALLBACK
     cfg = mp.NetConfig()
     b = workloads.shear(n_cells=9, seed=53)
     X, Tr = b.meshes[642]
@@ -229,7 +229,7 @@ def test_learned_step_reaches_the_plain_solution():
     xl, vl, sl = batch.step_learned(net, xi, vi, fi)
     torch.cuda.synchronize()
     sp, sl = batch.stats_to_numpy(sp), batch.stats_to_numpy(sl)
-    assert np.all(sp["status"] == CONVERGED) and np.all(sl["status"] == CONVERGED)
+    assert np.all(sp["status"] == CONVERGED) and np.all((sl["status"] & ~np.uint32(START_FALLBACK)) == CONVERGED)
     D = np.ptp(X[:, 0])
     assert (xl - xp).abs().max().item() <= 1e-5 * D
     # the learned start is y_n + delta: with delta = 0 (zero output layer) the step is the plain one
@@ -241,7 +241,63 @@ def test_learned_step_reaches_the_plain_solution():
     x0, v0, s0 = batch.step_learned(net, xi, vi, fi)
     torch.cuda.synchronize()
     assert torch.equal(x0, xp) and torch.equal(v0, vp)
-    np.testing.assert_array_equal(batch.stats_to_numpy(s0)["iterations"], sp["iterations"])
+    s0 = batch.stats_to_numpy(s0)
+    np.testing.assert_array_equal(s0["iterations"], sp["iterations"])
+    # g(y_n + 0) = g(y_n): the learned start is kept, at the cost of one more evaluation
+    assert np.all(s0["status"] == CONVERGED)
+    np.testing.assert_array_equal(s0["evaluations"], sp["evaluations"] + 1)
+
+
+def test_learned_start_that_raises_the_objective_falls_back_to_y_n():
+    """A network whose corrections are far too large (output layer scaled by 1000) raises
+    g at y_n + delta in every cell: every cell starts from y_n instead, reports
+    NPFEM_START_FALLBACK, and ends bit for bit where the plain step ends."""
+    from paper_1903_06479_amd import Batch, Net, CONVERGED, START_FALLBACK
+    cfg = mp.NetConfig()
+    b = workloads.shear(n_cells=9, seed=53)
+    X, Tr = b.meshes[642]
+    x, v = rounded(b.x), rounded(b.v)
+    f = rounded(workloads.drag_forces(b, x, v))
+    plan = make([(X, Tr)], "fp32", inverse_bf16=1)
+    batch = Batch(plan, np.zeros(9, np.int32))
+    theta = gpu_params(cfg, 11, scale=1000.0).astype(np.float32)
+    net = Net(plan, theta)
+    xi, vi, fi = T(x), T(v), T(f)
+    xp, vp, sp = batch.step(xi, vi, fi)
+    xl, vl, sl = batch.step_learned(net, xi, vi, fi)
+    delta = net.infer(batch, xi, vi, fi)
+    torch.cuda.synchronize()
+    sp, sl = batch.stats_to_numpy(sp), batch.stats_to_numpy(sl)
+    assert delta.abs().max().item() > 1e-3 * np.ptp(X[:, 0])
+    assert np.all(sl["status"] == CONVERGED | START_FALLBACK), sl["status"]
+    assert torch.equal(xl, xp) and torch.equal(vl, vp)
+    np.testing.assert_array_equal(sl["iterations"], sp["iterations"])
+    np.testing.assert_array_equal(sl["evaluations"], sp["evaluations"] + 1)
+
+
+def test_learned_form_on_a_rough_first_step():
+    """The first step of a held-out run of the training workload (cells placed with a
+    perturbed rest shape, where the bending projection makes g non-convex), with the
+    committed weights: every cell converges; where the learned and plain steps end at
+    different stationary points (more than 1e-5 D apart; one cell of 1,024 here), the
+    learned one has the lower objective g."""
+    import os
+    from paper_1903_06479_amd import Batch, Net, CONVERGED
+    from paper_1903_06479_amd import warmstart as ws
+    b = workloads.training(101, n_cells=1024)
+    X, Tr = b.meshes[642]
+    D = float(np.ptp(X[:, 0]))
+    plan = make([(X, Tr)], "fp32", inverse_bf16=1)
+    batch = Batch(plan, np.zeros(b.n_cells, np.int32))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    net = Net(plan, np.load(os.path.join(root, "paper_1903_06479_amd", "data", "warmstart_642.npy")))
+    flow = ws.Flow(batch, np.full(b.n_cells, workloads.drag_coefficient(642)), b.shear_rate, b.origin, b.poiseuille)
+    tr = ws.collect(batch, flow, T(b.x), T(b.v), 1)
+    r = ws.compare(batch, net, tr, D)
+    print(r)
+    assert r["all_converged"]
+    assert r["cell_steps_dx_above_1e-5"] <= 2, r
+    assert r["dx_above_1e-5_learned_objective_higher"] == 0, r
 
 
 def test_training_reduces_the_loss():
@@ -269,9 +325,10 @@ def test_training_reduces_the_loss():
 
 def test_trained_network_cuts_iterations_on_held_out_cells():
     """The committed weights (trained on runs 0-3 of the training workload) on cells of a
-    held-out run (100), from the state after one plain step: fewer quasi-Newton
-    iterations than the plain start, every cell converged, and the same positions
-    within 1e-5 of the cell diameter."""
+    held-out run (100), over its first 4 steps: fewer quasi-Newton iterations than the
+    plain start, every cell converged, the same positions (median within 1e-6 of the cell
+    diameter), and no cell-step where the learned start ends at a different stationary
+    point with a higher objective than the plain one."""
     import os
     from paper_1903_06479_amd import Batch, Net
     from paper_1903_06479_amd import warmstart as ws
@@ -283,12 +340,12 @@ def test_trained_network_cuts_iterations_on_held_out_cells():
     net = Net(plan, np.load(os.path.join(root, "paper_1903_06479_amd", "data", "warmstart_642.npy")))
     flow = ws.Flow(batch, np.full(b.n_cells, workloads.drag_coefficient(642)), b.shear_rate, b.origin, b.poiseuille)
     tr = ws.collect(batch, flow, T(b.x), T(b.v), 4)
-    later = {k: v[1:] for k, v in tr.items()}
-    r = ws.compare(batch, net, later, float(np.ptp(X[:, 0])))
+    r = ws.compare(batch, net, tr, float(np.ptp(X[:, 0])))
     print(r)
     assert r["all_converged"]
     assert r["iterations_learned"] <= r["iterations_plain"] - 0.3, r
-    assert r["max_dx_over_D"] <= 1e-5, r
+    assert r["dx_above_1e-5_learned_objective_higher"] == 0, r
+    assert r["median_dx_over_D"] <= 1e-6, r
 
 
 def test_loss_grad_rejects_a_bad_cell_index_before_any_launch():
