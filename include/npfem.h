@@ -216,8 +216,9 @@ npfem_status npfem_batch_get_schedule(const npfem_batch *batch, int32_t *cells_p
 
 /*
  * Autotuner: times one step of the batch on the caller's inputs for each candidate
- * schedule (cells_per_tile in {5, 10, 16, 21}, lbfgs_m in {2, 3, 5, 8} up to
- * max_lbfgs_m) and keeps the fastest.  x, v, f_ext: device inputs as for npfem_step;
+ * schedule (cells_per_tile in {5, 10, 16, 21}, and also 2 and 3 when the batch has fewer
+ * than 10 cells per compute unit, so that its tiles can occupy every workgroup slot;
+ * lbfgs_m in {2, 3, 5, 8} up to max_lbfgs_m) and keeps the fastest.  x, v, f_ext: device inputs as for npfem_step;
  * x_scratch, v_scratch: device [V_total][3] outputs it may overwrite.  Synchronous.
  * best_ms (may be NULL) receives the best step time in milliseconds.
  */

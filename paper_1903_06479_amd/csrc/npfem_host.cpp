@@ -1223,10 +1223,13 @@ npfem_status npfem_batch_autotune(npfem_batch* b, const void* x, const void* v, 
   double best = 1e300;
   const int T0 = b->T, m0 = b->m;
   int bT = T0, bm = m0;
-  const int Ts[] = {5, 10, 16, 21};
+  // tiles of 2 or 3 cells only for batches that leave workgroups idle at 5 cells per tile
+  const int Ts[] = {2, 3, 5, 10, 16, 21};
   const int ms[] = {2, 3, 5, 8};
+  const bool small = b->n_cells < 5 * 2 * (int64_t)b->plan->cu_count;
   npfem_status st = NPFEM_OK;
   for (int T : Ts) {
+    if (T < 5 && !small) continue;
     if ((int64_t)T > b->n_cells && T != 5) continue;
     for (int m : ms) {
       if (m > max_lbfgs_m && !(m == 2 && max_lbfgs_m < 2)) continue;

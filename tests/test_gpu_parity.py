@@ -442,7 +442,7 @@ def test_autotuner_keeps_the_solution():
     xi, vi, fi = T(x, torch.float32), T(v, torch.float32), T(f, torch.float32)
     x0, _, _ = batch.step(xi, vi, fi)
     best = batch.autotune(xi, vi, fi)
-    assert best["cells_per_tile"] in (5, 10, 16, 21) and best["lbfgs_m"] in (2, 3, 5) and best["best_ms"] > 0
+    assert best["cells_per_tile"] in (2, 3, 5, 10, 16, 21) and best["lbfgs_m"] in (2, 3, 5) and best["best_ms"] > 0
     x1, _, st = batch.step(xi, vi, fi)
     torch.cuda.synchronize()
     assert np.all(batch.stats_to_numpy(st)["status"] == CONVERGED)
