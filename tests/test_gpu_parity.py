@@ -508,7 +508,9 @@ def test_c1_stretch_200_steps_matches_oracle_trajectory():
 def test_throughput_full_size_sampled_cells():
     """The 100,000-cell throughput step in the benchmark's launch configuration (5 cells
     per tile, history 2, BF16 products, HIP graph): every cell converges, and sampled
-    cells agree with the converged FP64 oracle on the same (FP32) inputs within 1e-5 D."""
+    cells agree with the converged FP64 oracle on the same (FP32) inputs within 1e-5 D,
+    for the first step from rest and for the second step from the GPU's own state (with
+    velocities within the velocity that tolerance implies, 1e-5 D / h)."""
     from paper_1903_06479_amd import Batch, CONVERGED
     b = workloads.throughput(n_cells=100000)
     X, Tr = b.meshes[642]
@@ -534,6 +536,18 @@ def test_throughput_full_size_sampled_cells():
         sl = b.cell_slice(c)
         xr, _, _ = oracle_step(m, xi[sl], vi[sl], fi[sl])
         assert np.abs(xg[sl] - xr).max() <= 1e-5 * D, c
+    # second step, from the GPU's state after the first
+    f2 = batch.drag_forces(xo, vo, zeta, T(b.shear_rate, torch.float64), T(b.origin, torch.float64),
+                           p["umax"], p["radius"], p["axis_y"], p["axis_z"])
+    x2, v2, st2 = batch.step(xo, vo, f2)
+    torch.cuda.synchronize()
+    assert np.all(batch.stats_to_numpy(st2)["status"] == CONVERGED)
+    xi, vi, fi, xg, vg = (a.cpu().numpy().astype(np.float64) for a in (xo, vo, f2, x2, v2))
+    for c in (1, 50000, 99998):
+        sl = b.cell_slice(c)
+        xr, vr, _ = oracle_step(m, xi[sl], vi[sl], fi[sl])
+        assert np.abs(xg[sl] - xr).max() <= 1e-5 * D, c
+        assert np.abs(vg[sl] - vr).max() <= 1e-5 * D / workloads.DT_US, c
 
 
 def test_no_history_fp64_matches_oracle():
