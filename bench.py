@@ -236,7 +236,7 @@ def config_c2(args):
     b = workloads.shear(n_cells=1024, seed=1002)
     X, T = b.meshes[642]
     D = float(np.ptp(X[:, 0]))
-    plan = Plan([Mesh(X, T)], workloads.DT_US, params=default_params(tol=args.tol, inverse_bf16=1))
+    plan = Plan([Mesh(X, T)], workloads.DT_US, params=default_params(tol=args.tol, inverse_bf16={"fp32": 0, "bf16": 1, "band": 2}[args.products]))
     batch = Batch(plan, np.zeros(b.n_cells, np.int32))
     dev = torch.device("cuda:0")
     t = lambda a, dt=torch.float64: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
@@ -299,7 +299,7 @@ def config_c3(args):
     D = {n: float(np.ptp(b.meshes[n][0][:, 0])) for n in sizes}
     cm = np.array([sizes.index(int(n)) for n in b.cell_nverts], np.int32)
     meshes = [Mesh(*b.meshes[n]) for n in sizes]
-    p32 = Plan(meshes, workloads.DT_US, params=default_params(tol=args.tol, inverse_bf16=1))
+    p32 = Plan(meshes, workloads.DT_US, params=default_params(tol=args.tol, inverse_bf16={"fp32": 0, "bf16": 1, "band": 2}[args.products]))
     b32 = Batch(p32, cm)
     p64 = Plan(meshes, workloads.DT_US, params=default_params(precision="fp64", tol=args.tol))
     b64 = Batch(p64, cm)
@@ -441,7 +441,8 @@ def main():
     ap.add_argument("--copy-check", type=int, default=0,
                     help="only copy a buffer of this many bytes 5 times (calibrates the HBM byte counters)")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--fp32-products", action="store_true", help="FP32 instead of BF16 products with the inverses")
+    ap.add_argument("--products", default="band", choices=["fp32", "bf16", "band"],
+                    help="products with the inverses: FP32, BF16 off-diagonal (dense) or BF16 banded")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1903_06479_amd", "data", "warmstart_642.npy"),
                     help="trained warm-start network (FP32 parameters); empty string: plain form only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -487,7 +488,7 @@ def main():
     # NULL stream cannot be captured) and replayed on every later step
     stream = torch.cuda.Stream(device=dev)
     params = default_params(tol=args.tol, cells_per_tile=args.cells_per_tile,
-                            inverse_bf16=0 if args.fp32_products else 1)
+                            inverse_bf16={"fp32": 0, "bf16": 1, "band": 2}[args.products])
     t0 = time.time()
     mesh = Mesh(X, T)
     plan = Plan([mesh], workloads.DT_US, params=params)
@@ -656,7 +657,8 @@ def main():
         "config": {"workload": f"throughput: {b.n_cells} RBCs x 642-vertex mesh, shear + Poiseuille drag, "
                                "dt=1e-7 s, FP32 bulk + FP64 reductions", "cells": b.n_cells, "mesh_vertices": n,
                    "form": chosen, "tol": args.tol, "schedule": sched,
-                   "inverse_products": "fp32" if args.fp32_products else "bf16 off-diagonal + fp32 diagonal",
+                   "inverse_products": {"fp32": "fp32", "bf16": "bf16 off-diagonal + fp32 diagonal",
+                                        "band": "banded bf16 off-diagonal (RCM order) + fp32 diagonal"}[args.products],
                    "hip_graph": (not args.no_graph) and ch["graph_replays_timed"] == args.steps},
         "max_dx_over_D_vs_oracle": ch.get("max_dx_over_D_vs_oracle"),
         "forms": forms,

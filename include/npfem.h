@@ -112,7 +112,12 @@ typedef struct {
   int32_t inverse_bf16;     /* FP32 plans: 1 = apply H~^-1 and h^2 M~^-1 as an exact FP32
                                diagonal plus a BF16 off-diagonal part on the matrix cores
                                (they only precondition and start the iteration, so the
-                               solution is unchanged); 0 = FP32 matrix cores */
+                               solution is unchanged); 2 = the same with the off-diagonal
+                               part banded: stored in a reverse Cuthill-McKee order of the
+                               mesh, each 16-column block applied over the k range that holds
+                               its entries above 1e-4 sqrt(A_ii A_jj) (smaller entries outside
+                               that range are dropped; the inverses decay fast away from the
+                               diagonal); 0 = FP32 matrix cores */
   int32_t volume_normaliser;  /* NPFEM_VOLUME_STEP_FROZEN (default) or NPFEM_VOLUME_PAPER_LITERAL */
 } npfem_solver_params;
 

@@ -425,6 +425,73 @@ struct npfem_plan {
 
 namespace {
 
+// Reverse Cuthill-McKee order of the mesh's vertex graph (George & Liu 1981): per
+// connected component, a breadth-first search from a pseudo-peripheral vertex (the
+// smallest-degree vertex of the last level of a search from the previous start, twice),
+// visiting neighbours by increasing degree; the whole order reversed.
+constexpr double kBandRel = 1e-4;   // banded BF16 products: entries kept above this, relative
+
+std::vector<int> rcm_order(const npfem_mesh* m) {
+  const int n = m->n;
+  auto deg = [&](int i) { return m->nb_ptr[i + 1] - m->nb_ptr[i]; };
+  std::vector<int> order;
+  order.reserve(n);
+  std::vector<char> placed(n, 0);
+  std::vector<int> stamp(n, -1), queue, nbrs;
+  int pass = 0;
+  // breadth-first search over unplaced vertices; returns the order of the visit
+  auto bfs = [&](int s0, bool sorted) {
+    queue.assign(1, s0);
+    stamp[s0] = ++pass;
+    for (size_t h = 0; h < queue.size(); ++h) {
+      const int v = queue[h];
+      nbrs.clear();
+      for (int q = m->nb_ptr[v]; q < m->nb_ptr[v + 1]; ++q) {
+        const int w = m->nb_idx[q];
+        if (!placed[w] && stamp[w] != pass) {
+          stamp[w] = pass;
+          nbrs.push_back(w);
+        }
+      }
+      if (sorted)
+        std::stable_sort(nbrs.begin(), nbrs.end(), [&](int a, int b) { return deg(a) < deg(b); });
+      queue.insert(queue.end(), nbrs.begin(), nbrs.end());
+    }
+    return queue;
+  };
+  for (;;) {
+    int start = -1;
+    for (int i = 0; i < n; ++i)
+      if (!placed[i] && (start < 0 || deg(i) < deg(start))) start = i;
+    if (start < 0) break;
+    for (int it = 0; it < 2; ++it) {                 // move the start towards the periphery
+      const std::vector<int> q = bfs(start, false);
+      // the last level: vertices at the largest distance (re-derived from a level sweep)
+      std::vector<int> level(n, -1);
+      level[start] = 0;
+      int far = 0;
+      for (int v : q)
+        for (int k = m->nb_ptr[v]; k < m->nb_ptr[v + 1]; ++k) {
+          const int w = m->nb_idx[k];
+          if (!placed[w] && level[w] < 0) {
+            level[w] = level[v] + 1;
+            far = std::max(far, level[w]);
+          }
+        }
+      int best = start;
+      for (int v : q)
+        if (level[v] == far && (best == start || deg(v) < deg(best))) best = v;
+      start = best;
+    }
+    for (int v : bfs(start, true)) {
+      placed[v] = 1;
+      order.push_back(v);
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
 template <typename Real>
 npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>& hinv,
                          const std::vector<double>& minv_h2, MeshDev<Real>& d) {
@@ -482,22 +549,64 @@ npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>&
   if ((s = p->buf.upload(Mi.data(), Mi.size(), &d.minv))) return s;
   d.hinv_bf = d.minv_bf = nullptr;
   d.hinv_diag = d.minv_diag = nullptr;
+  d.bperm = d.bband = nullptr;
   if (p->prm.inverse_bf16 && p->precision == NPFEM_FP32) {
-    // exact FP32 diagonal + BF16 off-diagonal part (zero diagonal, zero padding)
+    // exact FP32 diagonal + BF16 off-diagonal part (zero diagonal, zero padding); banded:
+    // the off-diagonal part in the reverse Cuthill-McKee order, each 16-column block kept
+    // over the k' range of its entries above kBandRel sqrt(A_ii A_jj)
+    const bool banded = p->prm.inverse_bf16 == 2;
+    std::vector<int> perm(np);
+    for (int i = 0; i < np; ++i) perm[i] = i;
+    if (banded) {
+      const std::vector<int> ord = rcm_order(m);
+      std::copy(ord.begin(), ord.end(), perm.begin());
+    }
+    const int ncb = np / 16;
+    std::vector<int> band((size_t)2 * ncb * 2, 0);
     for (int which = 0; which < 2; ++which) {
       const std::vector<double>& A = which == 0 ? hinv : minv_h2;
       std::vector<uint16_t> off((size_t)np * np, 0);
       std::vector<float> dg(np, 0.0f);
-      for (int i = 0; i < n; ++i) {
-        dg[i] = (float)A[(size_t)i * n + i];
-        for (int j = 0; j < n; ++j)
-          if (j != i) off[(size_t)i * np + j] = to_bf16((float)A[(size_t)i * n + j]);
+      for (int i = 0; i < n; ++i) dg[i] = (float)A[(size_t)i * n + i];
+      if (!banded) {
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j)
+            if (j != i) off[(size_t)i * np + j] = to_bf16((float)A[(size_t)i * n + j]);
+      } else {
+        std::vector<double> sd(n);
+        for (int i = 0; i < n; ++i) sd[i] = std::sqrt(std::fabs(A[(size_t)i * n + i]));
+        for (int cb = 0; cb < ncb; ++cb) {
+          int lo = np, hi = 0;
+          for (int a = 16 * cb; a < 16 * cb + 16 && a < n; ++a)
+            for (int k = 0; k < n; ++k) {
+              const int i = perm[a], j = perm[k];
+              if (i != j && std::fabs(A[(size_t)i * n + j]) > kBandRel * sd[i] * sd[j]) {
+                lo = std::min(lo, k);
+                hi = std::max(hi, k + 1);
+              }
+            }
+          if (lo >= hi) lo = hi = 0;
+          lo = lo / 32 * 32;
+          hi = std::min(np, (hi + 31) / 32 * 32);
+          band[((size_t)which * ncb + cb) * 2] = lo;
+          band[((size_t)which * ncb + cb) * 2 + 1] = hi;
+          for (int a = 16 * cb; a < 16 * cb + 16 && a < n; ++a)
+            for (int k = lo; k < hi && k < n; ++k)
+              if (k != a) off[(size_t)a * np + k] = to_bf16((float)A[(size_t)perm[a] * n + perm[k]]);
+        }
       }
       const uint16_t** po = which == 0 ? &d.hinv_bf : &d.minv_bf;
       const float** pd = which == 0 ? &d.hinv_diag : &d.minv_diag;
       if ((s = p->buf.upload(off.data(), off.size(), po))) return s;
       if ((s = p->buf.upload(dg.data(), dg.size(), pd))) return s;
     }
+    if (!banded)                                   // the identity order, whole ranges
+      for (size_t k = 0; k < band.size(); k += 2) {
+        band[k] = 0;
+        band[k + 1] = np;
+      }
+    if ((s = p->buf.upload(perm.data(), perm.size(), &d.bperm))) return s;
+    if ((s = p->buf.upload(band.data(), band.size(), &d.bband))) return s;
   }
   d.V0 = m->V0;
   d.A0 = m->A0;
@@ -557,6 +666,8 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
     return fail(NPFEM_E_INVALID, "plan_create: bad solver controls");
   if (prm->cells_per_tile < 0 || prm->cells_per_tile > kMaxTile)
     return fail(NPFEM_E_INVALID, "plan_create: cells_per_tile must be in [0, 21]");
+  if (prm->inverse_bf16 < 0 || prm->inverse_bf16 > 2)
+    return fail(NPFEM_E_INVALID, "plan_create: inverse_bf16 must be 0, 1 or 2");
   if (prm->volume_normaliser != NPFEM_VOLUME_STEP_FROZEN && prm->volume_normaliser != NPFEM_VOLUME_PAPER_LITERAL)
     return fail(NPFEM_E_INVALID, "plan_create: unknown volume_normaliser");
   const double mats[] = {mat->B, mat->C, mat->D, mat->k_bend, mat->k_volume, mat->beta, mat->density, mat->k_area_global};
@@ -755,7 +866,7 @@ StepArgs<Real> make_args(npfem_batch* b) {
            p->mat.k_area_global};
   const double eps = std::is_same<Real, float>::value ? 1.1920928955078125e-07 : 2.220446049250313e-16;
   a.sol = {p->dt, p->prm.tol, p->prm.c1, p->prm.noise_factor * eps, b->m, p->prm.max_iter,
-           p->prm.max_halvings, (p->prm.inverse_bf16 && std::is_same<Real, float>::value) ? 1 : 0,
+           p->prm.max_halvings, std::is_same<Real, float>::value ? p->prm.inverse_bf16 : 0,
            p->prm.volume_normaliser == NPFEM_VOLUME_PAPER_LITERAL ? 1 : 0};
   a.tiles = b->tiles;
   a.tile_cells = b->tile_cells;
@@ -817,6 +928,8 @@ npfem_status batch_schedule(npfem_batch* b, int T, int m) {
       lds = std::max(lds, lds_bytes<Real>(p->meshes[mi].n_pad, p->meshes[mi].chunk, stage_rows,
                                           p->meshes[mi].vec_lds, p->meshes[mi].xu_lds));
   b->stage_k = stage_cols(lds, stage_rows, b->n_pad_max);   // the staging stays below the cell states
+  if (p->prm.inverse_bf16 == 2 && std::is_same<Real, float>::value && b->stage_k < 32)
+    return fail(NPFEM_E_UNSUPPORTED, "batch_schedule: banded products need an LDS staging area");
   // the tile's cell states go to LDS (after everything else) when they fit the LDS a
   // workgroup may have and cost no workgroups per CU
   {
@@ -1324,6 +1437,11 @@ npfem_status npfem_apply_inverse(npfem_plan* p, int32_t mi, int32_t which, const
     const double* A = which == 0 ? mp.dev64.hinv : mp.dev64.minv;
     HIP_TRY(launch_apply_inverse<double>(A, mp.n_pad, static_cast<const double*>(in), static_cast<double*>(out),
                                          rows, s));
+  } else if (p->prm.inverse_bf16 == 2) {
+    const uint16_t* A = which == 0 ? mp.dev32.hinv_bf : mp.dev32.minv_bf;
+    const float* dg = which == 0 ? mp.dev32.hinv_diag : mp.dev32.minv_diag;
+    HIP_TRY(launch_apply_inverse_band(A, dg, mp.dev32.bperm, mp.dev32.bband + (size_t)which * 2 * (mp.n_pad / 16),
+                                      mp.n_pad, static_cast<const float*>(in), static_cast<float*>(out), rows, s));
   } else if (p->prm.inverse_bf16) {
     const uint16_t* A = which == 0 ? mp.dev32.hinv_bf : mp.dev32.minv_bf;
     const float* dg = which == 0 ? mp.dev32.hinv_diag : mp.dev32.minv_diag;

@@ -42,6 +42,13 @@ struct MeshDev {
   const uint16_t* minv_bf;     // [n_pad][n_pad] off-diagonal part of h^2 M~^-1, BF16 bits
   const float* hinv_diag;      // [n_pad] diagonal of H~^-1
   const float* minv_diag;      // [n_pad] diagonal of h^2 M~^-1
+  // staged BF16 products: hinv_bf / minv_bf hold, in row n' and column k',
+  // A[perm[n']][perm[k']] within the band of n''s 16-column block, 0 outside (inverse_bf16
+  // = 2: a reverse Cuthill-McKee order and the significant entries' range; 1: the
+  // identity and the whole range)
+  const int* bperm;            // [n_pad] vertex at position k' of the order (identity on padding)
+  const int* bband;            // [2][n_pad / 16][2] per matrix (H~^-1, h^2 M~^-1) and 16-column block:
+                               // k' range [lo, hi), multiples of 32
   double V0;                   // rest volume
   double A0;                   // rest area
   double floor_force;          // B sqrt(A0): force floor of the residual
@@ -54,7 +61,7 @@ struct MaterialDev {
 struct SolverDev {
   double h, tol, c1, noise;    // noise = noise_factor * machine epsilon
   int m, max_iter, max_halvings;
-  int bf16;                    // products with the inverses on the BF16 matrix cores
+  int bf16;                    // products with the inverses on the BF16 matrix cores (2: banded)
   int literal;                 // volume normaliser at the current x (else frozen at x_n)
 };
 
@@ -161,6 +168,8 @@ hipError_t launch_eval(const StepArgs<Real>& a, int n_cells, const Real* u, Real
 template <typename Real>
 hipError_t launch_apply_inverse(const Real* A, int n_pad, const Real* in, Real* out, int rows,
                                 hipStream_t s);
+hipError_t launch_apply_inverse_band(const uint16_t* A, const float* diag, const int* perm, const int* band,
+                                     int n_pad, const float* in, float* out, int rows, hipStream_t s);
 hipError_t launch_apply_inverse_bf16(const uint16_t* A, const float* diag, int n_pad, const float* in,
                                      float* out, int rows, hipStream_t s);
 template <typename Real>

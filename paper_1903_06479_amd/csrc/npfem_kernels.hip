@@ -850,16 +850,28 @@ __device__ inline void tile_gemm_bf16(const uint16_t* __restrict__ Abits, const 
   }
 }
 
-// Same product with the tile's rows staged in LDS as BF16 (rows padded to 16), in
-// chunks of at most kc_max columns of k (one chunk when the rows fit the LDS region),
-// and each wave carrying four column blocks at a time, so that four independent B
-// fragments are in flight per k step and every A fragment read from LDS feeds four
-// matrix instructions.  A chunk needs 16 ceil(rows/16) (kc + 8) BF16 of LDS at `stage`;
-// the partial products of later chunks are added to Out by the lane that wrote it.
-constexpr int kStageMaxPad = 1024;     // n_pad up to which the whole k range is staged
-__device__ inline void tile_gemm_bf16_lds(const uint16_t* __restrict__ Abits, const float* __restrict__ diag,
-                                          int np, const float* __restrict__ In, float* __restrict__ Out,
-                                          int rows, __bf16* stage, int kc_max) {
+// n_pad up to which the whole k range of the staged BF16 product fits one chunk.
+constexpr int kStageMaxPad = 1024;
+
+// The same product with the tile's rows staged in LDS as BF16 (rows padded to 16), in
+// chunks of at most kc_max columns of k (one chunk when the rows fit the LDS region; a
+// chunk needs 16 ceil(rows/16) (kc + 8) BF16 of LDS at `stage`; the partial products of
+// later chunks are added to Out by the lane that wrote it), each wave carrying four
+// column blocks at a time, so that four independent B fragments are in flight per k step
+// and every A fragment read from LDS feeds four matrix instructions.
+// The off-diagonal part is stored in an order of the vertices (position k' holds vertex
+// perm[k']) and each 16-column block is applied over the k' range band[2 cb],
+// band[2 cb + 1] only: with inverse_bf16 = 2 a reverse Cuthill-McKee order, in which the
+// inverse's significant entries lie near the diagonal, and the range that holds them;
+// with inverse_bf16 = 1 the identity and the whole range.  The input rows are gathered
+// through the permutation as they are staged, and each output column n' goes to vertex
+// perm[n'], with the exact FP32 diagonal of that vertex.  A wave's four column blocks
+// are consecutive, so their ranges nearly coincide; it runs over their union (the stored
+// matrix is zero outside each block's own range).
+__device__ inline void tile_gemm_bf16_band(const uint16_t* __restrict__ Abits, const float* __restrict__ diag,
+                                           const int* __restrict__ perm, const int* __restrict__ band, int np,
+                                           const float* __restrict__ In, float* __restrict__ Out, int rows,
+                                           __bf16* stage, int kc_max) {
   const __bf16* A = reinterpret_cast<const __bf16*>(Abits);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l16 = lane & 15, kq = lane >> 4;
@@ -871,61 +883,59 @@ __device__ inline void tile_gemm_bf16_lds(const uint16_t* __restrict__ Abits, co
     const int ldk = kc + 8;
     const int k8n = kc >> 3;
     __syncthreads();
+#pragma unroll 4
     for (int e = tid(); e < mb_n * 16 * k8n; e += kBlock) {
       const int r = e / k8n, k8 = (e - r * k8n) << 3;
-      bf16x8 v;
-      if (r < rows) {
-        const floatx4 lo = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + kb0 + k8);
-        const floatx4 hi = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + kb0 + k8 + 4);
-        v = bf16x8{(__bf16)lo.x, (__bf16)lo.y, (__bf16)lo.z, (__bf16)lo.w,
-                   (__bf16)hi.x, (__bf16)hi.y, (__bf16)hi.z, (__bf16)hi.w};
-      } else {
-        v = bf16x8{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f,
-                   (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-      }
+      const int4 p0 = *reinterpret_cast<const int4*>(perm + kb0 + k8);
+      const int4 p1 = *reinterpret_cast<const int4*>(perm + kb0 + k8 + 4);
+      const float* row = In + (size_t)(r < rows ? r : 0) * np;
+      const float z = r < rows ? 1.f : 0.f;
+      const bf16x8 v = {(__bf16)(z * row[p0.x]), (__bf16)(z * row[p0.y]), (__bf16)(z * row[p0.z]),
+                        (__bf16)(z * row[p0.w]), (__bf16)(z * row[p1.x]), (__bf16)(z * row[p1.y]),
+                        (__bf16)(z * row[p1.z]), (__bf16)(z * row[p1.w])};
       *reinterpret_cast<bf16x8*>(stage + r * ldk + k8) = v;
     }
     __syncthreads();
-    for (int g0 = wave; g0 < ncb; g0 += 4 * NB) {
-      floatx4 acc[4][NB];
-      const __bf16* arow[NB];
-      bool valid[NB];
+    // one 16-row block of the tile at a time (a 5-cell tile has one): the accumulators of
+    // one row block by NB column blocks stay small next to the step's other live values
+    for (int mb = 0; mb < mb_n; ++mb) {
+      for (int g0 = NB * wave; g0 < ncb; g0 += 4 * NB) {
+        floatx4 acc[NB];
+        const __bf16* arow[NB];
+        bool valid[NB];
+        int lo = np, hi = 0;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int cb = g0 + 4 * q;
-        valid[q] = cb < ncb;
-        arow[q] = A + (size_t)((valid[q] ? cb : 0) * 16 + l16) * np + kb0 + 8 * kq;
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) acc[mb][q] = floatx4{0.f, 0.f, 0.f, 0.f};
-      }
-      for (int k0 = 0; k0 < kc; k0 += 32) {
-        bf16x8 bq[NB];
-#pragma unroll
-        for (int q = 0; q < NB; ++q) bq[q] = *reinterpret_cast<const bf16x8*>(arow[q] + k0);
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          if (mb < mb_n) {
-            const bf16x8 aq = *reinterpret_cast<const bf16x8*>(stage + (mb * 16 + l16) * ldk + k0 + 8 * kq);
-#pragma unroll
-            for (int q = 0; q < NB; ++q) acc[mb][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, bq[q], acc[mb][q], 0, 0, 0);
+        for (int q = 0; q < NB; ++q) {
+          const int cb = g0 + q;
+          valid[q] = cb < ncb;
+          arow[q] = A + (size_t)((valid[q] ? cb : 0) * 16 + l16) * np + kb0 + 8 * kq;
+          if (valid[q]) {
+            lo = min(lo, band[2 * cb]);
+            hi = max(hi, band[2 * cb + 1]);
           }
+          acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-      }
+        const int k_lo = max(lo, kb0) - kb0, k_hi = min(hi, kb0 + kc) - kb0;   // this chunk's part
+        const __bf16* srow = stage + (mb * 16 + l16) * ldk + 8 * kq;
+        for (int k0 = k_lo; k0 < k_hi; k0 += 32) {
+          bf16x8 bq[NB];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        if (!valid[q]) continue;
-        const int n = (g0 + 4 * q) * 16 + l16;
-        const float dn = diag[n];
+          for (int q = 0; q < NB; ++q) bq[q] = *reinterpret_cast<const bf16x8*>(arow[q] + k0);
+          const bf16x8 aq = *reinterpret_cast<const bf16x8*>(srow + k0);
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          if (mb < mb_n) {
+          for (int q = 0; q < NB; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq, bq[q], acc[q], 0, 0, 0);
+        }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int r = mb * 16 + 4 * kq + i;
-              if (r < rows) {
-                const size_t o = (size_t)r * np + n;
-                Out[o] = acc[mb][q][i] + (kb0 == 0 ? dn * In[o] : Out[o]);
-              }
+        for (int q = 0; q < NB; ++q) {
+          if (!valid[q]) continue;
+          const int n = perm[(g0 + q) * 16 + l16];
+          const float dn = diag[n];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = mb * 16 + 4 * kq + i;
+            if (r < rows) {
+              const size_t o = (size_t)r * np + n;
+              Out[o] = acc[q][i] + (kb0 == 0 ? dn * In[o] : Out[o]);
             }
           }
         }
@@ -942,8 +952,11 @@ __device__ inline void tile_product(const MeshDev<Real>& M, const SolverDev& sol
     if (sol.bf16) {
       const uint16_t* Ab = which == 0 ? M.hinv_bf : M.minv_bf;
       const float* dg = which == 0 ? M.hinv_diag : M.minv_diag;
+      // staged (banded, or dense with the identity order); unstaged only for dense storage
+      // (the host guarantees stage_k >= 32 for banded storage)
       if (stage_k >= 32)
-        tile_gemm_bf16_lds(Ab, dg, M.n_pad, In, Out, rows, reinterpret_cast<__bf16*>(stage), stage_k);
+        tile_gemm_bf16_band(Ab, dg, M.bperm, M.bband + which * 2 * (M.n_pad >> 4), M.n_pad, In, Out, rows,
+                            reinterpret_cast<__bf16*>(stage), stage_k);
       else
         tile_gemm_bf16(Ab, dg, M.n_pad, In, Out, rows);
       return;
@@ -1622,6 +1635,16 @@ __global__ void __launch_bounds__(kBlock) apply_inverse_kernel(const Real* A, in
   tile_gemm(A, np, in + (size_t)r0 * np, out + (size_t)r0 * np, min(48, rows - r0));
 }
 
+// 48 rows per workgroup, staged in LDS in chunks of kc columns (48 (kc + 8) BF16).
+__global__ void __launch_bounds__(kBlock) apply_inverse_band_kernel(const uint16_t* A, const float* diag,
+                                                                    const int* perm, const int* band, int np,
+                                                                    const float* in, float* out, int rows, int kc) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int r0 = blockIdx.x * 48;
+  tile_gemm_bf16_band(A, diag, perm, band, np, in + (size_t)r0 * np, out + (size_t)r0 * np, min(48, rows - r0),
+                      reinterpret_cast<__bf16*>(lds), kc);
+}
+
 __global__ void __launch_bounds__(kBlock) apply_inverse_bf16_kernel(const uint16_t* A, const float* diag, int np,
                                                                     const float* in, float* out, int rows) {
   const int r0 = blockIdx.x * 48;
@@ -1870,6 +1893,16 @@ hipError_t launch_apply_inverse(const Real* A, int n_pad, const Real* in, Real* 
 }
 
 #if !defined(NPFEM_PART) || NPFEM_PART == 1
+hipError_t launch_apply_inverse_band(const uint16_t* A, const float* diag, const int* perm, const int* band,
+                                     int n_pad, const float* in, float* out, int rows, hipStream_t s) {
+  (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls
+  const int kc = std::min(n_pad, (65536 / (2 * 48) - 8) / 32 * 32);
+  const size_t lds = (size_t)48 * (kc + 8) * 2;
+  hipLaunchKernelGGL(apply_inverse_band_kernel, dim3((rows + 47) / 48), dim3(kBlock), lds, s, A, diag, perm, band,
+                     n_pad, in, out, rows, kc);
+  return hipGetLastError();
+}
+
 hipError_t launch_apply_inverse_bf16(const uint16_t* A, const float* diag, int n_pad, const float* in,
                                      float* out, int rows, hipStream_t s) {
   (void)hipGetLastError();   // drop an error left behind by unrelated earlier calls

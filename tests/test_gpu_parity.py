@@ -47,11 +47,15 @@ def oracle_step(model, xn, vn, f, tol=1e-12, x_start=None):
 # ---- the MFMA product with the dense inverses -------------------------------------
 
 @pytest.mark.parametrize("precision,n,bf16", [("fp32", 642, 0), ("fp64", 258, 0), ("fp32", 258, 0), ("fp64", 642, 0),
-                                              ("fp32", 642, 1), ("fp32", 2562, 1)])
+                                              ("fp32", 642, 1), ("fp32", 2562, 1),
+                                              ("fp32", 258, 2), ("fp32", 642, 2), ("fp32", 2562, 2)])
 def test_apply_inverse_matches_oracle(precision, n, bf16):
     """The matrix-core product with the dense inverses.  BF16 products (exact FP32
     diagonal + BF16 off-diagonal part) are checked against the bound their rounding
-    allows: 2^-7 of the off-diagonal contribution."""
+    allows: 2^-7 of the off-diagonal contribution; the banded ones (bf16 = 2) may in
+    addition drop entries below 1e-4 sqrt(A_ii A_jj), which bounds the dropped part of
+    out[r][j] by 1e-4 sqrt(A_jj) sum_i |q[r][i]| sqrt(A_ii).  The 2562-vertex case runs
+    the banded product in several k chunks."""
     m = oracle_model(n)
     plan = make([(m.X, m.tris)], precision, inverse_bf16=bf16)
     dt = torch.float64 if precision == "fp64" else torch.float32
@@ -68,6 +72,9 @@ def test_apply_inverse_matches_oracle(precision, n, bf16):
             off = Ainv - np.diag(np.diag(Ainv))
             # both operands are rounded to BF16 (unit roundoff 2^-8 each)
             bound = 1.01 * 2.0 ** -7 * (np.abs(q[:, :n]) @ np.abs(off)) + 1e-6 * np.abs(ref)
+            if bf16 == 2:
+                sd = np.sqrt(np.abs(np.diag(Ainv)))
+                bound += 1.0001e-4 * np.outer(np.abs(q[:, :n]) @ sd, sd)
             assert np.all(np.abs(out[:, :n] - ref) <= bound)
         else:
             scale = np.abs(ref).max()
@@ -160,8 +167,9 @@ def test_step_fp32_shear_matches_oracle():
 
 
 def test_step_fp32_bf16_products_same_solution():
-    """BF16 products with the inverses only precondition the iteration: the converged
-    positions agree with the FP32-product path and the oracle within tolerance."""
+    """BF16 products with the inverses (dense or banded) only precondition the iteration:
+    the converged positions agree with the FP32-product path and the oracle within
+    tolerance."""
     from paper_1903_06479_amd import CONVERGED
     b = workloads.shear(n_cells=12, seed=77)
     X, Tr = b.meshes[642]
@@ -169,17 +177,18 @@ def test_step_fp32_bf16_products_same_solution():
     x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
     f = rounded(workloads.drag_forces(b, x, v), "fp32")
     res = {}
-    for bf in (0, 1):
+    for bf in (0, 1, 2):
         xo, vo, st, _ = run_step(make([(X, Tr)], "fp32", inverse_bf16=bf), np.zeros(12, np.int32), x, v, f)
         assert np.all(st["status"] == CONVERGED), st
         res[bf] = (xo, st["iterations"])
     D = np.ptp(X[:, 0])
-    assert np.abs(res[0][0] - res[1][0]).max() <= 1e-5 * D
-    assert res[1][1].mean() <= res[0][1].mean() + 1.0
-    for c in (0, 7):
-        s = b.cell_slice(c)
-        xr, _, _ = oracle_step(m, x[s], v[s], f[s])
-        assert np.abs(res[1][0][s] - xr).max() <= 1e-5 * D
+    for bf in (1, 2):
+        assert np.abs(res[0][0] - res[bf][0]).max() <= 1e-5 * D
+        assert res[bf][1].mean() <= res[0][1].mean() + 1.0
+        for c in (0, 7):
+            s = b.cell_slice(c)
+            xr, _, _ = oracle_step(m, x[s], v[s], f[s])
+            assert np.abs(res[bf][0][s] - xr).max() <= 1e-5 * D
 
 
 def test_step_tile_size_and_repeat_bitwise():
@@ -267,17 +276,25 @@ def test_step_fp64_stretch_trajectory():
     assert np.ptp(xr[:, 0]) > D                    # it did stretch
 
 
-def test_step_uneven_mesh_mix():
-    """258/642/2562-vertex cells in one launch (FP32) against the oracle."""
-    from paper_1903_06479_amd import CONVERGED
+@pytest.mark.parametrize("bf16,tile", [(0, 0), (2, 0), (2, 7)])
+def test_step_uneven_mesh_mix(bf16, tile):
+    """258/642/2562-vertex cells in one launch (FP32) against the oracle: FP32 products,
+    and banded BF16 products (the 2562-vertex products staged in several k chunks), also
+    with 7-cell tiles (21 rows: two 16-row blocks per product)."""
+    from paper_1903_06479_amd import Batch, CONVERGED
     b = workloads.uneven(n_cells=200, cells=np.arange(12))
     sizes = sorted(b.meshes)
     meshes = [b.meshes[k] for k in sizes]
     cm = np.array([sizes.index(int(k)) for k in b.cell_nverts], np.int32)
     x, v = rounded(b.x, "fp32"), rounded(b.v, "fp32")
     f = rounded(workloads.drag_forces(b, x, v, step=0), "fp32")
-    plan = make(meshes, "fp32")
-    xo, vo, st, _ = run_step(plan, cm, x, v, f)
+    plan = make(meshes, "fp32", inverse_bf16=bf16)
+    batch = Batch(plan, cm)
+    if tile:
+        batch.schedule(cells_per_tile=tile)
+    xo, vo, st = batch.step(T(x, torch.float32), T(v, torch.float32), T(f, torch.float32))
+    torch.cuda.synchronize()
+    xo, st = xo.cpu().numpy().astype(np.float64), batch.stats_to_numpy(st)
     assert np.all(st["status"] == CONVERGED), st
     for c in range(b.n_cells):
         s = b.cell_slice(c)
