@@ -605,7 +605,7 @@ npfem_status upload_mesh(npfem_plan* p, MeshPlan& mp, const std::vector<double>&
         band[k] = 0;
         band[k + 1] = np;
       }
-    if ((s = p->buf.upload(perm.data(), perm.size(), &d.bperm))) return s;
+    if (banded && (s = p->buf.upload(perm.data(), perm.size(), &d.bperm))) return s;   // null: identity
     if ((s = p->buf.upload(band.data(), band.size(), &d.bband))) return s;
   }
   d.V0 = m->V0;

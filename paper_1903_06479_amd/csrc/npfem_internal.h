@@ -46,7 +46,8 @@ struct MeshDev {
   // A[perm[n']][perm[k']] within the band of n''s 16-column block, 0 outside (inverse_bf16
   // = 2: a reverse Cuthill-McKee order and the significant entries' range; 1: the
   // identity and the whole range)
-  const int* bperm;            // [n_pad] vertex at position k' of the order (identity on padding)
+  const int* bperm;            // [n_pad] vertex at position k' of the order (identity on padding);
+                               // null for the identity order
   const int* bband;            // [2][n_pad / 16][2] per matrix (H~^-1, h^2 M~^-1) and 16-column block:
                                // k' range [lo, hi), multiples of 32
   double V0;                   // rest volume

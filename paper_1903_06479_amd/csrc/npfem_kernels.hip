@@ -863,8 +863,8 @@ constexpr int kStageMaxPad = 1024;
 // perm[k']) and each 16-column block is applied over the k' range band[2 cb],
 // band[2 cb + 1] only: with inverse_bf16 = 2 a reverse Cuthill-McKee order, in which the
 // inverse's significant entries lie near the diagonal, and the range that holds them;
-// with inverse_bf16 = 1 the identity and the whole range.  The input rows are gathered
-// through the permutation as they are staged, and each output column n' goes to vertex
+// with inverse_bf16 = 1 the identity (perm null) and the whole range.  The input rows
+// are gathered through the permutation as they are staged, and each output column n' goes to vertex
 // perm[n'], with the exact FP32 diagonal of that vertex.  A wave's four column blocks
 // are consecutive, so their ranges nearly coincide; it runs over their union (the stored
 // matrix is zero outside each block's own range).
@@ -883,17 +883,34 @@ __device__ inline void tile_gemm_bf16_band(const uint16_t* __restrict__ Abits, c
     const int ldk = kc + 8;
     const int k8n = kc >> 3;
     __syncthreads();
+    if (perm) {                                         // gathered through the order
 #pragma unroll 4
-    for (int e = tid(); e < mb_n * 16 * k8n; e += kBlock) {
-      const int r = e / k8n, k8 = (e - r * k8n) << 3;
-      const int4 p0 = *reinterpret_cast<const int4*>(perm + kb0 + k8);
-      const int4 p1 = *reinterpret_cast<const int4*>(perm + kb0 + k8 + 4);
-      const float* row = In + (size_t)(r < rows ? r : 0) * np;
-      const float z = r < rows ? 1.f : 0.f;
-      const bf16x8 v = {(__bf16)(z * row[p0.x]), (__bf16)(z * row[p0.y]), (__bf16)(z * row[p0.z]),
-                        (__bf16)(z * row[p0.w]), (__bf16)(z * row[p1.x]), (__bf16)(z * row[p1.y]),
-                        (__bf16)(z * row[p1.z]), (__bf16)(z * row[p1.w])};
-      *reinterpret_cast<bf16x8*>(stage + r * ldk + k8) = v;
+      for (int e = tid(); e < mb_n * 16 * k8n; e += kBlock) {
+        const int r = e / k8n, k8 = (e - r * k8n) << 3;
+        const int4 p0 = *reinterpret_cast<const int4*>(perm + kb0 + k8);
+        const int4 p1 = *reinterpret_cast<const int4*>(perm + kb0 + k8 + 4);
+        const float* row = In + (size_t)(r < rows ? r : 0) * np;
+        const float z = r < rows ? 1.f : 0.f;
+        const bf16x8 v = {(__bf16)(z * row[p0.x]), (__bf16)(z * row[p0.y]), (__bf16)(z * row[p0.z]),
+                          (__bf16)(z * row[p0.w]), (__bf16)(z * row[p1.x]), (__bf16)(z * row[p1.y]),
+                          (__bf16)(z * row[p1.z]), (__bf16)(z * row[p1.w])};
+        *reinterpret_cast<bf16x8*>(stage + r * ldk + k8) = v;
+      }
+    } else {                                            // the identity order: 16-byte loads
+      for (int e = tid(); e < mb_n * 16 * k8n; e += kBlock) {
+        const int r = e / k8n, k8 = (e - r * k8n) << 3;
+        bf16x8 v;
+        if (r < rows) {
+          const floatx4 lo = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + kb0 + k8);
+          const floatx4 hi = *reinterpret_cast<const floatx4*>(In + (size_t)r * np + kb0 + k8 + 4);
+          v = bf16x8{(__bf16)lo.x, (__bf16)lo.y, (__bf16)lo.z, (__bf16)lo.w,
+                     (__bf16)hi.x, (__bf16)hi.y, (__bf16)hi.z, (__bf16)hi.w};
+        } else {
+          v = bf16x8{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f,
+                     (__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
+        }
+        *reinterpret_cast<bf16x8*>(stage + r * ldk + k8) = v;
+      }
     }
     __syncthreads();
     // one 16-row block of the tile at a time (a 5-cell tile has one): the accumulators of
@@ -928,7 +945,7 @@ __device__ inline void tile_gemm_bf16_band(const uint16_t* __restrict__ Abits, c
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
           if (!valid[q]) continue;
-          const int n = perm[(g0 + q) * 16 + l16];
+          const int n = perm ? perm[(g0 + q) * 16 + l16] : (g0 + q) * 16 + l16;
           const float dn = diag[n];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -945,8 +962,10 @@ __device__ inline void tile_gemm_bf16_band(const uint16_t* __restrict__ Abits, c
 }
 
 // The tile's product with H~^-1 (which 0) or h^2 M~^-1 (which 1) in the plan's format.
+// Kept out of line: inlined into the step, its accumulators and staging add to the
+// register pressure of the whole iteration loop and the step kernel spills more.
 template <typename Real>
-__device__ inline void tile_product(const MeshDev<Real>& M, const SolverDev& sol, int which, const Real* In,
+__device__ __attribute__((noinline)) void tile_product(const MeshDev<Real>& M, const SolverDev& sol, int which, const Real* In,
                                     Real* Out, int rows, unsigned char* stage, int stage_k) {
   if constexpr (std::is_same<Real, float>::value) {
     if (sol.bf16) {
