@@ -304,6 +304,18 @@ def test_step_uneven_mesh_mix(bf16, tile):
         assert np.abs(xo[s] - xr).max() <= 1e-5 * np.ptp(m.X[:, 0]), (c, n)
 
 
+def test_empty_batch_and_bad_mesh_index_are_rejected():
+    """A batch of no cells, or with a cell of an unknown mesh, is refused with an error at
+    creation (NPFEM_E_INVALID), before anything is launched."""
+    from paper_1903_06479_amd import Batch
+    X, Tr = workloads.shear(n_cells=1).meshes[642]
+    plan = make([(X, Tr)], "fp32")
+    with pytest.raises(RuntimeError, match="n_cells"):
+        Batch(plan, np.zeros(0, np.int32))
+    with pytest.raises(RuntimeError, match="mesh index"):
+        Batch(plan, np.array([0, 1], np.int32))
+
+
 def test_rest_cells_stay_put_and_nonfinite_is_flagged():
     """Zero force at the rest shape: a cell at rest with v = 0, F = 0 converges at the
     first guess and does not move (the mesh is given in FP32-representable coordinates,
