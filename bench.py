@@ -37,6 +37,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s; the
 # published 157.3 TFLOP/s counts packed FP32.
 VALU_FP32_PEAK_TFLOPS = 78.6
+# products with the inverses (npfem_solver_params.inverse_bf16): FP32, dense BF16, banded BF16
+PRODUCTS = {"fp32": 0, "bf16": 1, "band": 2}
 N_CU = 256
 
 # Algorithmic arithmetic of one objective + gradient evaluation, counted operation by
@@ -236,7 +238,7 @@ def config_c2(args):
     b = workloads.shear(n_cells=1024, seed=1002)
     X, T = b.meshes[642]
     D = float(np.ptp(X[:, 0]))
-    plan = Plan([Mesh(X, T)], workloads.DT_US, params=default_params(tol=args.tol, inverse_bf16={"fp32": 0, "bf16": 1, "band": 2}[args.products]))
+    plan = Plan([Mesh(X, T)], workloads.DT_US, params=default_params(tol=args.tol, inverse_bf16=PRODUCTS[args.products]))
     batch = Batch(plan, np.zeros(b.n_cells, np.int32))
     dev = torch.device("cuda:0")
     t = lambda a, dt=torch.float64: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
@@ -299,7 +301,7 @@ def config_c3(args):
     D = {n: float(np.ptp(b.meshes[n][0][:, 0])) for n in sizes}
     cm = np.array([sizes.index(int(n)) for n in b.cell_nverts], np.int32)
     meshes = [Mesh(*b.meshes[n]) for n in sizes]
-    p32 = Plan(meshes, workloads.DT_US, params=default_params(tol=args.tol, inverse_bf16={"fp32": 0, "bf16": 1, "band": 2}[args.products]))
+    p32 = Plan(meshes, workloads.DT_US, params=default_params(tol=args.tol, inverse_bf16=PRODUCTS[args.products]))
     b32 = Batch(p32, cm)
     p64 = Plan(meshes, workloads.DT_US, params=default_params(precision="fp64", tol=args.tol))
     b64 = Batch(p64, cm)
@@ -488,7 +490,7 @@ def main():
     # NULL stream cannot be captured) and replayed on every later step
     stream = torch.cuda.Stream(device=dev)
     params = default_params(tol=args.tol, cells_per_tile=args.cells_per_tile,
-                            inverse_bf16={"fp32": 0, "bf16": 1, "band": 2}[args.products])
+                            inverse_bf16=PRODUCTS[args.products])
     t0 = time.time()
     mesh = Mesh(X, T)
     plan = Plan([mesh], workloads.DT_US, params=params)
