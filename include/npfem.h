@@ -346,6 +346,31 @@ npfem_status npfem_apply_inverse(npfem_plan *plan, int32_t mesh_index, int32_t w
                                  void *stream);
 
 /*
+ * The paper's own route to the same products (section 2.1.1: H~ is factored once and
+ * each iteration solves with the factor).  A = H~ (which = 0) or M~/h^2 (which = 1) is
+ * factored at plan creation as P A P^T = L L^T, with P the reverse Cuthill-McKee order
+ * of the mesh's vertex graph, so that L is banded (half bandwidth b); out[r] = A^-1 in[r]
+ * is then solved by forward and back substitution with L, one right-hand side per GPU
+ * lane, in the plan's precision.  The result equals npfem_apply_inverse's up to
+ * rounding.
+ *   in, out  : device [rows][n_pad] row-major, as for npfem_apply_inverse (padding
+ *              entries of `in` must be zero; those of `out` are written as zero)
+ *   work     : device workspace owned by the caller, at least
+ *              npfem_solve_factor_workspace(plan, mesh_index, rows) bytes (work_bytes);
+ *              calls that share a workspace must not overlap
+ *   bandwidth_out (may be NULL): receives b, the larger of the two factors' half
+ *              bandwidths
+ * NPFEM_E_INVALID for bad arguments or a short workspace; NPFEM_E_UNSUPPORTED when
+ * the band is too wide for the kernel's LDS ring (b above about 500 in FP32, 250 in
+ * FP64).  Exposed to measure the factor route against the products with the inverses;
+ * the step applies the inverses.
+ */
+int64_t npfem_solve_factor_workspace(const npfem_plan *plan, int32_t mesh_index, int32_t rows);  /* -1: bad args */
+npfem_status npfem_solve_factor(npfem_plan *plan, int32_t mesh_index, int32_t which, const void *in,
+                                void *out, int32_t rows, void *work, int64_t work_bytes,
+                                int32_t *bandwidth_out, void *stream);
+
+/*
  * First guess of the step (Algorithm 1, first line): u_out = y_n - x_n = h^2 M~^-1 b
  * with b = M v_n / h + f_ext, for every cell.  x, v, f_ext, u_out: device [V_total][3]
  * in the plan's precision.  Used to form the training targets of the learned warm start.

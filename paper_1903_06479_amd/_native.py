@@ -71,6 +71,8 @@ _SIGNATURES = {
     "npfem_stats_accumulate": (c_int32, [_P, c_int64, _P, _P]),
     "npfem_stats_reset": (c_int32, [_P, _P]),
     "npfem_apply_inverse": (c_int32, [c_void_p, c_int32, c_int32, _P, _P, c_int32, _P, _P]),
+    "npfem_solve_factor_workspace": (c_int64, [c_void_p, c_int32, c_int32]),
+    "npfem_solve_factor": (c_int32, [c_void_p, c_int32, c_int32, _P, _P, c_int32, _P, c_int64, _P, _P]),
     "npfem_drag_forces": (c_int32, [c_void_p, _P, _P, _P, _P, _P, c_double, c_double, c_double,
                                     c_double, _P, _P]),
     "npfem_first_guess": (c_int32, [c_void_p, _P, _P, _P, _P, _P]),

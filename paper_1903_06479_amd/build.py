@@ -13,13 +13,14 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnpfem.so")
 OBJ = os.path.join(HERE, "_build")
 
-SOURCES = ["npfem_host.cpp", "npfem_kernels.hip", "npfem_net.hip", "npfem_collide.hip"]
+SOURCES = ["npfem_host.cpp", "npfem_kernels.hip", "npfem_net.hip", "npfem_collide.hip", "npfem_factor.hip"]
 # (object, source, extra flags): the largest source first, so that it starts first
 UNITS = [
     ("kernels64", "npfem_kernels.hip", ["-DNPFEM_PART=2"]),
     ("kernels32", "npfem_kernels.hip", ["-DNPFEM_PART=1"]),
     ("net", "npfem_net.hip", []),
     ("collide", "npfem_collide.hip", []),
+    ("factor", "npfem_factor.hip", []),
     ("host", "npfem_host.cpp", []),
 ]
 FLAGS = [

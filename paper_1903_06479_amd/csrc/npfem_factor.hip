@@ -1,0 +1,244 @@
+// Batched banded Cholesky substitution: the paper's own route to the products with the
+// constant matrices (section 2.1.1 factors H~ once and solves with the factor in every
+// iteration).  A = H~ or M~/h^2 is factored on the host as P A P^T = L L^T, P the
+// reverse Cuthill-McKee order of the mesh, so that L is banded (half bandwidth b); each
+// right-hand side q then needs L y = P q and L^T z = y, out = P^T z.
+//
+// Mapping: one wave per 64 right-hand sides, one lane per right-hand side.  The serial
+// chain over the n rows is the same for every lane, so the factor entries are uniform
+// across the wave and are read through the scalar unit; the lane's last b solution
+// entries sit in an LDS ring (one 256-byte row per position).  Rows are solved eight at a
+// time: every ring entry read feeds eight FMAs (one per row of the block), and the
+// 8 x 8 diagonal block is solved in registers.  The right-hand sides are brought into
+// the order and transposed to [position][lane] once, through an LDS tile, into the
+// caller's workspace, which then holds y and z; the result goes back the same way.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "npfem_factor.h"
+
+namespace npfem {
+namespace {
+
+constexpr int kRhs = 64;        // right-hand sides per wave (one per lane)
+constexpr int kTileRow = 65;    // padded row of the 64 x 64 transpose tile
+
+// acc[k] += sum over jj < B of C[jj][k] * ring[(base + jj) & mask], B a multiple of 16
+// (the factor entries are stored negated).
+//
+// FP64: in groups of one position; the next group's factor entries (scalar loads) and
+// ring value (LDS) are requested before the current group's FMAs.
+template <typename Real>
+__device__ __forceinline__ void band_dot(Real (&acc)[kFactorRows], const Real* __restrict__ C, const Real* win,
+                                         int base, int mask, int B, int lane) {
+  Real c[kFactorRows], v = win[(base & mask) * kRhs + lane];
+#pragma unroll
+  for (int k = 0; k < kFactorRows; ++k) c[k] = C[k];
+  for (int g = 0; g < B; ++g) {
+    Real cc[kFactorRows], vv = v;
+#pragma unroll
+    for (int k = 0; k < kFactorRows; ++k) cc[k] = c[k];
+    if (g + 1 < B) {
+      v = win[((base + g + 1) & mask) * kRhs + lane];
+#pragma unroll
+      for (int k = 0; k < kFactorRows; ++k) c[k] = C[(g + 1) * kFactorRows + k];
+    }
+#pragma unroll
+    for (int k = 0; k < kFactorRows; ++k) acc[k] = fma(cc[k], vv, acc[k]);
+  }
+}
+
+// FP32: the factor entries are uniform across the wave, but scalar loads would share
+// their wait counter with the ring's LDS reads, which leaves only one group of entries
+// in flight.  Instead each lane holds, per chunk of 16 positions, one entry of each pair
+// of positions (pair p: lane l & 15 holds C[2p + (l & 15) / 8][(l & 15) % 8], the same
+// in each 16-lane row), fetched by vector loads one chunk ahead, and a DPP row
+// broadcast (row_newbcast) hands entry j of the pair to every lane of the row.
+#define NPFEM_ROW_BCAST(x, j) \
+  __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, (x)), 0x150 + (j), 0xF, 0xF, true))
+#define NPFEM_PAIR_FMA(c, v0, v1)                                                    \
+  do {                                                                               \
+    acc[0] = fmaf(NPFEM_ROW_BCAST(c, 0), v0, acc[0]);                                \
+    acc[1] = fmaf(NPFEM_ROW_BCAST(c, 1), v0, acc[1]);                                \
+    acc[2] = fmaf(NPFEM_ROW_BCAST(c, 2), v0, acc[2]);                                \
+    acc[3] = fmaf(NPFEM_ROW_BCAST(c, 3), v0, acc[3]);                                \
+    acc[4] = fmaf(NPFEM_ROW_BCAST(c, 4), v0, acc[4]);                                \
+    acc[5] = fmaf(NPFEM_ROW_BCAST(c, 5), v0, acc[5]);                                \
+    acc[6] = fmaf(NPFEM_ROW_BCAST(c, 6), v0, acc[6]);                                \
+    acc[7] = fmaf(NPFEM_ROW_BCAST(c, 7), v0, acc[7]);                                \
+    acc[0] = fmaf(NPFEM_ROW_BCAST(c, 8), v1, acc[0]);                                \
+    acc[1] = fmaf(NPFEM_ROW_BCAST(c, 9), v1, acc[1]);                                \
+    acc[2] = fmaf(NPFEM_ROW_BCAST(c, 10), v1, acc[2]);                               \
+    acc[3] = fmaf(NPFEM_ROW_BCAST(c, 11), v1, acc[3]);                               \
+    acc[4] = fmaf(NPFEM_ROW_BCAST(c, 12), v1, acc[4]);                               \
+    acc[5] = fmaf(NPFEM_ROW_BCAST(c, 13), v1, acc[5]);                               \
+    acc[6] = fmaf(NPFEM_ROW_BCAST(c, 14), v1, acc[6]);                               \
+    acc[7] = fmaf(NPFEM_ROW_BCAST(c, 15), v1, acc[7]);                               \
+  } while (0)
+
+__device__ __forceinline__ void band_dot(float (&acc)[kFactorRows], const float* __restrict__ C, const float* win,
+                                         int base, int mask, int B, int lane) {
+  const int l16 = lane & 15;
+  const int nch = B / 16;
+  float cn[8];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) cn[p] = C[p * 16 + l16];
+  for (int ch = 0; ch < nch; ++ch) {
+    float c[8], v[16];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) c[p] = cn[p];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = win[((base + ch * 16 + j) & mask) * kRhs + lane];
+    if (ch + 1 < nch) {
+#pragma unroll
+      for (int p = 0; p < 8; ++p) cn[p] = C[(ch + 1) * 128 + p * 16 + l16];
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) NPFEM_PAIR_FMA(c[p], v[2 * p], v[2 * p + 1]);
+  }
+}
+#undef NPFEM_PAIR_FMA
+#undef NPFEM_ROW_BCAST
+
+// The pointers are kernel arguments (not struct members) so that their no-alias
+// guarantee lets uniform entries (the FP64 factor, the diagonal blocks) be fetched by
+// scalar loads.
+template <typename Real>
+__global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict__ F, const Real* __restrict__ G,
+                                                          const Real* __restrict__ T, const int* __restrict__ iperm,
+                                                          const Real* __restrict__ in, Real* __restrict__ out,
+                                                          Real* __restrict__ work, int np, int B, int mask,
+                                                          int rows) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Real* lds = reinterpret_cast<Real*>(smem);
+  const int lane = threadIdx.x;
+  const int nblk = np / kFactorRows;
+  const int64_t r0 = (int64_t)blockIdx.x * kRhs;
+  Real* __restrict__ Y = work + (size_t)blockIdx.x * np * kRhs;
+
+  // in[r][k] -> Y[iperm[k]][r - r0]: rows read whole, written back one position per row
+  for (int k0 = 0; k0 < np; k0 += kRhs) {
+    const int k = k0 + lane;
+    for (int rr = 0; rr < kRhs; ++rr) {
+      const int64_t r = r0 + rr;
+      lds[rr * kTileRow + lane] = (r < rows && k < np) ? in[r * np + k] : Real(0);
+    }
+    __syncthreads();
+    const int kn = min(kRhs, np - k0);
+    for (int kk = 0; kk < kn; ++kk) Y[(size_t)iperm[k0 + kk] * kRhs + lane] = lds[lane * kTileRow + kk];
+    __syncthreads();
+  }
+
+  Real* win = lds;              // ring of the last solved positions, [mask + 1][64]
+  Real nxt[kFactorRows], x[kFactorRows];
+
+  // forward: L y = P q, positions ascending
+  for (int s = 0; s <= mask; ++s) win[s * kRhs + lane] = Real(0);
+#pragma unroll
+  for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)k * kRhs + lane];
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int i0 = blk * kFactorRows;
+    Real acc[kFactorRows];
+#pragma unroll
+    for (int k = 0; k < kFactorRows; ++k) acc[k] = nxt[k];
+    if (blk + 1 < nblk) {
+#pragma unroll
+      for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(i0 + kFactorRows + k) * kRhs + lane];
+    }
+    band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, mask, B, lane);
+    const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
+#pragma unroll
+    for (int k = 0; k < kFactorRows; ++k) {
+      Real s = acc[k];
+#pragma unroll
+      for (int l = 0; l < k; ++l) s = fma(-Tb[kFactorRows + k * kFactorRows + l], x[l], s);
+      x[k] = s * Tb[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kFactorRows; ++k) {
+      win[((i0 + k) & mask) * kRhs + lane] = x[k];
+      Y[(size_t)(i0 + k) * kRhs + lane] = x[k];
+    }
+  }
+
+  // backward: L^T z = y, positions descending
+  for (int s = 0; s <= mask; ++s) win[s * kRhs + lane] = Real(0);
+#pragma unroll
+  for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(np - kFactorRows + k) * kRhs + lane];
+  for (int blk = nblk - 1; blk >= 0; --blk) {
+    const int i0 = blk * kFactorRows;
+    Real acc[kFactorRows];
+#pragma unroll
+    for (int k = 0; k < kFactorRows; ++k) acc[k] = nxt[k];
+    if (blk > 0) {
+#pragma unroll
+      for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(i0 - kFactorRows + k) * kRhs + lane];
+    }
+    band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, mask, B, lane);
+    const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
+#pragma unroll
+    for (int k = kFactorRows - 1; k >= 0; --k) {
+      Real s = acc[k];
+#pragma unroll
+      for (int l = k + 1; l < kFactorRows; ++l) s = fma(-Tb[kFactorRows + l * kFactorRows + k], x[l], s);
+      x[k] = s * Tb[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kFactorRows; ++k) {
+      win[((i0 + k) & mask) * kRhs + lane] = x[k];
+      Y[(size_t)(i0 + k) * kRhs + lane] = x[k];
+    }
+  }
+  __syncthreads();
+
+  // out[r][k] = Y[iperm[k]][r - r0]
+  for (int k0 = 0; k0 < np; k0 += kRhs) {
+    const int kn = min(kRhs, np - k0);
+    for (int kk = 0; kk < kn; ++kk) lds[lane * kTileRow + kk] = Y[(size_t)iperm[k0 + kk] * kRhs + lane];
+    __syncthreads();
+    const int k = k0 + lane;
+    for (int rr = 0; rr < kRhs; ++rr) {
+      const int64_t r = r0 + rr;
+      if (r < rows && k < np) out[r * np + k] = lds[rr * kTileRow + lane];
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+template <typename Real>
+size_t band_solve_lds_bytes(int mask) {
+  return (size_t)std::max(mask + 1, kTileRow) * kRhs * sizeof(Real);
+}
+
+size_t band_solve_work_bytes(int n_pad, int rows, int real_bytes) {
+  return (size_t)((rows + kRhs - 1) / kRhs) * kRhs * n_pad * real_bytes;
+}
+
+template <typename Real>
+hipError_t launch_band_solve(const BandFactorDev<Real>& f, int which, int n_pad, const Real* in, Real* out,
+                             Real* work, int rows, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  const size_t lds = band_solve_lds_bytes<Real>(f.mask);
+  if (lds > kBandSolveMaxLds) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {          // above the default dynamic LDS limit (set on the current device)
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_kernel<Real>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int grid = (rows + kRhs - 1) / kRhs;
+  hipLaunchKernelGGL(band_solve_kernel<Real>, dim3(grid), dim3(kRhs), lds, s, f.F[which], f.G[which], f.T[which],
+                     f.iperm, in, out, work, n_pad, f.B, f.mask, rows);
+  return hipGetLastError();
+}
+
+template size_t band_solve_lds_bytes<float>(int);
+template size_t band_solve_lds_bytes<double>(int);
+template hipError_t launch_band_solve<float>(const BandFactorDev<float>&, int, int, const float*, float*, float*,
+                                             int, hipStream_t);
+template hipError_t launch_band_solve<double>(const BandFactorDev<double>&, int, int, const double*, double*,
+                                              double*, int, hipStream_t);
+
+}  // namespace npfem

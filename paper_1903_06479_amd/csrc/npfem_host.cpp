@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "npfem.h"
+#include "npfem_factor.h"
 #include "npfem_internal.h"
 #include "npfem_net_internal.h"
 
@@ -401,6 +402,8 @@ struct MeshPlan {
   double floor_force;
   MeshDev<float> dev32;
   MeshDev<double> dev64;
+  BandFactorDev<float> fac32{};      // banded Cholesky factors of H~ and M~/h^2 (F null: not available)
+  BandFactorDev<double> fac64{};
 };
 
 template <typename Real>
@@ -490,6 +493,107 @@ std::vector<int> rcm_order(const npfem_mesh* m) {
   }
   std::reverse(order.begin(), order.end());
   return order;
+}
+
+// Banded Cholesky factor of P A P^T (P: the order `perm`, A dense FP64 n x n) in the
+// block layout of the substitution kernel (see BandFactorDev): coefficient arrays F, G,
+// T of n_pad / 8 blocks; false if A is not positive definite.  The factor is computed
+// within the band of the permuted matrix only (a banded matrix's Cholesky factor keeps
+// its band).
+struct BandFactorHost {
+  int b = 0, B = 0;
+  std::vector<double> F, G, T;
+};
+
+bool band_factor(const std::vector<double>& A, int n, int np, const std::vector<int>& perm, BandFactorHost& out) {
+  std::vector<double> Ap((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Ap[(size_t)i * n + j] = A[(size_t)perm[i] * n + perm[j]];
+  int b = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j)
+      if (Ap[(size_t)i * n + j] != 0.0) {
+        b = std::max(b, i - j);
+        break;
+      }
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const int lo = std::max(0, i - b);
+    for (int j = lo; j <= i; ++j) {
+      double s = Ap[(size_t)i * n + j];
+      for (int k = lo; k < j; ++k) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      if (j < i) {
+        L[(size_t)i * n + j] = s / L[(size_t)j * n + j];
+      } else {
+        if (!(s > 0.0) || !std::isfinite(s)) return false;
+        L[(size_t)i * n + i] = std::sqrt(s);
+      }
+    }
+  }
+  // entry (i, j) of the padded factor: the identity on the padding positions
+  auto Lf = [&](int i, int j) -> double {
+    if (i < n && j < n) return (j <= i && i - j <= b) ? L[(size_t)i * n + j] : 0.0;
+    return i == j ? 1.0 : 0.0;
+  };
+  const int R = kFactorRows, nblk = np / R;
+  const int B = std::max(16, (b + 15) / 16 * 16);
+  out.b = b;
+  out.B = B;
+  out.F.assign((size_t)nblk * B * R, 0.0);
+  out.G.assign((size_t)nblk * B * R, 0.0);
+  out.T.assign((size_t)nblk * kFactorDiag, 0.0);
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int i0 = blk * R;
+    for (int jj = 0; jj < B; ++jj)
+      for (int k = 0; k < R; ++k) {
+        const int jf = i0 - B + jj, jg = i0 + R + jj;
+        if (jf >= 0) out.F[((size_t)blk * B + jj) * R + k] = -Lf(i0 + k, jf);
+        if (jg < np) out.G[((size_t)blk * B + jj) * R + k] = -Lf(jg, i0 + k);
+      }
+    double* Tb = &out.T[(size_t)blk * kFactorDiag];
+    for (int k = 0; k < R; ++k) {
+      Tb[k] = 1.0 / Lf(i0 + k, i0 + k);
+      for (int l = 0; l < k; ++l) Tb[R + k * R + l] = Lf(i0 + k, i0 + l);
+    }
+  }
+  return true;
+}
+
+// Uploads both factors (H~ and M~/h^2) in precision Real with the order's inverse
+// permutation; leaves f.F[0] null when the kernel's LDS ring would not fit a compute unit.
+template <typename Real>
+npfem_status upload_factor(npfem_plan* p, int np, const std::vector<int>& perm, const BandFactorHost (&fh)[2],
+                           BandFactorDev<Real>& f) {
+  f = BandFactorDev<Real>{};
+  const int B = std::max(fh[0].B, fh[1].B);
+  int ring = 1;
+  while (ring < B + kFactorRows) ring *= 2;
+  f.b = std::max(fh[0].b, fh[1].b);
+  f.mask = ring - 1;
+  if (band_solve_lds_bytes<Real>(f.mask) > kBandSolveMaxLds) return NPFEM_OK;
+  std::vector<int> ip(np);
+  for (int k = 0; k < np; ++k) ip[k] = k;
+  for (size_t a = 0; a < perm.size(); ++a) ip[perm[a]] = (int)a;
+  npfem_status s;
+  if ((s = p->buf.upload(ip.data(), ip.size(), &f.iperm))) return s;
+  f.B = B;
+  const int R = kFactorRows, nblk = np / R;
+  for (int w = 0; w < 2; ++w) {
+    // both factors in the wider of the two bands (zero-extended)
+    std::vector<Real> F((size_t)nblk * B * R, Real(0)), G((size_t)nblk * B * R, Real(0));
+    const int Bw = fh[w].B, sh = B - Bw;
+    for (int blk = 0; blk < nblk; ++blk)
+      for (int jj = 0; jj < Bw; ++jj)
+        for (int k = 0; k < R; ++k) {
+          F[((size_t)blk * B + jj + sh) * R + k] = Real(fh[w].F[((size_t)blk * Bw + jj) * R + k]);
+          G[((size_t)blk * B + jj) * R + k] = Real(fh[w].G[((size_t)blk * Bw + jj) * R + k]);
+        }
+    std::vector<Real> T(fh[w].T.begin(), fh[w].T.end());
+    if ((s = p->buf.upload(F.data(), F.size(), &f.F[w]))) return s;
+    if ((s = p->buf.upload(G.data(), G.size(), &f.G[w]))) return s;
+    if ((s = p->buf.upload(T.data(), T.size(), &f.T[w]))) return s;
+  }
+  return NPFEM_OK;
 }
 
 template <typename Real>
@@ -753,6 +857,20 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
         Mt[k] = mat->beta * h * h * Lp[k] + (i == j ? mp.mass[i] : 0.0);
         Ht[k] = Mt[k] / (h * h) + Lp[k] + Km[k] + (i == j ? mat->k_volume + mat->k_area_global : 0.0);
       }
+    // the paper's route: banded factors of H~ and M~/h^2 in the reverse Cuthill-McKee order
+    {
+      const std::vector<int> perm = rcm_order(m);
+      std::vector<double> Ms(Mt);
+      for (double& v : Ms) v /= h * h;
+      BandFactorHost fh[2];
+      if (!band_factor(Ht, n, mp.n_pad, perm, fh[0]))
+        return fail(NPFEM_E_NOT_SPD, "plan_create: H~ is not positive definite");
+      if (!band_factor(Ms, n, mp.n_pad, perm, fh[1]))
+        return fail(NPFEM_E_NOT_SPD, "plan_create: M~ is not positive definite");
+      npfem_status fs = fp64 ? upload_factor<double>(p.get(), mp.n_pad, perm, fh, mp.fac64)
+                             : upload_factor<float>(p.get(), mp.n_pad, perm, fh, mp.fac32);
+      if (fs) return fs;
+    }
     if (!cholesky(Mt, n)) return fail(NPFEM_E_NOT_SPD, "plan_create: M~ is not positive definite");
     if (!cholesky(Ht, n)) return fail(NPFEM_E_NOT_SPD, "plan_create: H~ is not positive definite");
     const std::vector<double> Hinv = spd_inverse(Ht, n);
@@ -1452,6 +1570,37 @@ npfem_status npfem_apply_inverse(npfem_plan* p, int32_t mi, int32_t which, const
     HIP_TRY(launch_apply_inverse<float>(A, mp.n_pad, static_cast<const float*>(in), static_cast<float*>(out),
                                         rows, s));
   }
+  return NPFEM_OK;
+}
+
+int64_t npfem_solve_factor_workspace(const npfem_plan* p, int32_t mi, int32_t rows) {
+  if (!p || mi < 0 || mi >= (int)p->meshes.size() || rows < 0) return -1;
+  const int rb = p->precision == NPFEM_FP64 ? (int)sizeof(double) : (int)sizeof(float);
+  return (int64_t)band_solve_work_bytes(p->meshes[mi].n_pad, rows, rb);
+}
+
+npfem_status npfem_solve_factor(npfem_plan* p, int32_t mi, int32_t which, const void* in, void* out, int32_t rows,
+                                void* work, int64_t work_bytes, int32_t* bandwidth_out, void* stream) {
+  if (!p) return fail(NPFEM_E_INVALID, "solve_factor: NULL plan");
+  if (mi < 0 || mi >= (int)p->meshes.size()) return fail(NPFEM_E_INVALID, "solve_factor: bad mesh index");
+  if (which != 0 && which != 1) return fail(NPFEM_E_INVALID, "solve_factor: which must be 0 or 1");
+  const MeshPlan& mp = p->meshes[mi];
+  const bool fp64 = p->precision == NPFEM_FP64;
+  if (bandwidth_out) *bandwidth_out = fp64 ? mp.fac64.b : mp.fac32.b;
+  if (!(fp64 ? (const void*)mp.fac64.F[0] : (const void*)mp.fac32.F[0]))
+    return fail(NPFEM_E_UNSUPPORTED, "solve_factor: the factor's band is too wide for the substitution kernel");
+  if (rows == 0) return NPFEM_OK;
+  if (!in || !out || !work || rows < 0) return fail(NPFEM_E_INVALID, "solve_factor: bad buffers or rows");
+  if (work_bytes < npfem_solve_factor_workspace(p, mi, rows))
+    return fail(NPFEM_E_INVALID, "solve_factor: workspace too small");
+  HIP_TRY(hipSetDevice(p->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (fp64)
+    HIP_TRY(launch_band_solve<double>(mp.fac64, which, mp.n_pad, static_cast<const double*>(in),
+                                      static_cast<double*>(out), static_cast<double*>(work), rows, s));
+  else
+    HIP_TRY(launch_band_solve<float>(mp.fac32, which, mp.n_pad, static_cast<const float*>(in),
+                                     static_cast<float*>(out), static_cast<float*>(work), rows, s));
   return NPFEM_OK;
 }
 

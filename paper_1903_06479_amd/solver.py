@@ -117,6 +117,36 @@ class Plan:
                                             inp.shape[0], None, _stream(stream)), "npfem_apply_inverse")
         return out
 
+    def factor_bandwidth(self, mesh_index: int) -> int:
+        """Half bandwidth b of the banded Cholesky factors used by solve_factor."""
+        b = c_int32()
+        N.check(N.lib().npfem_solve_factor(self._h, mesh_index, 0, None, None, 0, None, 0, byref(b), None),
+                "npfem_solve_factor")
+        return b.value
+
+    def solve_factor_workspace(self, mesh_index: int, rows: int) -> int:
+        nb = N.lib().npfem_solve_factor_workspace(self._h, mesh_index, rows)
+        if nb < 0:
+            raise ValueError("npfem_solve_factor_workspace: bad arguments")
+        return nb
+
+    def solve_factor(self, mesh_index: int, which: int, inp, out=None, work=None, stream=None):
+        """out[r] = A^-1 inp[r] by substitution with the banded Cholesky factor of A = H~
+        (which 0) or M~/h^2 (which 1); inp [rows, n_pad].  work: a device byte tensor of at
+        least solve_factor_workspace(mesh_index, rows) bytes (allocated when None)."""
+        import torch
+        if out is None:
+            out = torch.empty_like(inp)
+        self._check(inp, out)
+        rows = inp.shape[0]
+        if work is None:
+            work = torch.empty(max(1, self.solve_factor_workspace(mesh_index, rows)), dtype=torch.uint8,
+                               device=inp.device)
+        N.check(N.lib().npfem_solve_factor(self._h, mesh_index, which, _dptr(inp), _dptr(out), rows,
+                                           _dptr(work), work.numel() * work.element_size(), None,
+                                           _stream(stream)), "npfem_solve_factor")
+        return out
+
     def _check(self, *ts):
         for t in ts:
             if t is None:

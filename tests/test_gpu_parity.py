@@ -82,6 +82,70 @@ def test_apply_inverse_matches_oracle(precision, n, bf16):
         assert np.abs(out[:, n:]).max() == 0.0
 
 
+# ---- the paper's route: substitution with the banded Cholesky factor ---------------
+
+@pytest.mark.parametrize("precision,n", [("fp32", 258), ("fp32", 642), ("fp32", 2562), ("fp64", 258),
+                                         ("fp64", 642), ("fp64", 2562)])
+def test_solve_factor_matches_oracle(precision, n):
+    """out = A^-1 q by forward and back substitution with the banded Cholesky factor of
+    A = H~ or M~/h^2 (reverse Cuthill-McKee order), against the oracle's solve.  Bound:
+    a Cholesky solve returns x with (A + dA) x = q, |dA| <= gamma |L||L^T|
+    (Higham, Accuracy and Stability of Numerical Algorithms, thm 10.4), gamma = (3b + 6) u
+    for a factor of half bandwidth b rounded to unit roundoff u; by Cauchy-Schwarz
+    (|L||L^T|)_ij <= sqrt(A_ii A_jj), and each row of |L||L^T| has at most 4b + 1
+    non-zeros.  130 right-hand sides: three waves of 64, the last one ragged."""
+    m = oracle_model(n)
+    plan = make([(m.X, m.tris)], precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
+    npad = plan.n_pad(0)
+    b = plan.factor_bandwidth(0)
+    assert 0 < b < n // 2
+    rows = 130
+    rng = np.random.default_rng(n + 1)
+    q = np.zeros((rows, npad))
+    q[:, :n] = rng.standard_normal((rows, n))
+    q = q.astype(np.float32).astype(np.float64) if precision == "fp32" else q
+    gamma = 1.01 * (3 * b + 6) * u
+    for which, A, solve in ((0, m.Ht, m.solve_Ht), (1, m.Mt / (DT * DT), lambda r: DT * DT * m.solve_Mt(r))):
+        out = plan.solve_factor(0, which, T(q, dt)).cpu().numpy().astype(np.float64)
+        assert np.abs(out[:, n:]).max() == 0.0
+        x = out[:, :n]
+        resid = np.abs(q[:, :n] - x @ A)                     # A symmetric
+        sd = np.sqrt(np.diag(A))
+        w = np.sort(np.abs(x) * sd, axis=1)[:, ::-1][:, :4 * b + 1].sum(axis=1)
+        assert np.all(resid <= gamma * np.outer(w, sd))
+        # against the oracle's solution: x - ref = A^-1 (A x - q)
+        ref = solve(q[:, :n].T).T
+        inv_norm = 1.0 / np.linalg.eigvalsh(A)[0]
+        err = np.linalg.norm(x - ref, axis=1)
+        assert np.all(err <= 1.01 * inv_norm * np.linalg.norm(resid, axis=1) + 1e-12 * np.linalg.norm(ref, axis=1))
+
+
+def test_solve_factor_arguments_and_workspace_reuse():
+    """Workspace size checks, rows = 0, a bad `which`, and one workspace reused by two
+    calls of different sizes (the second smaller)."""
+    from paper_1903_06479_amd._native import NpfemError
+    m = oracle_model(642)
+    plan = make([(m.X, m.tris)])
+    npad = plan.n_pad(0)
+    need = plan.solve_factor_workspace(0, 200)
+    assert need == 256 * npad * 4
+    work = torch.empty(need, dtype=torch.uint8, device=dev())
+    rng = np.random.default_rng(5)
+    q = np.zeros((200, npad), np.float32)
+    q[:, :642] = rng.standard_normal((200, 642))
+    big = plan.solve_factor(0, 0, T(q, torch.float32), work=work).cpu().numpy()
+    small = plan.solve_factor(0, 0, T(q[:70], torch.float32), work=work).cpu().numpy()
+    assert np.array_equal(small, big[:70])
+    with pytest.raises(NpfemError):
+        plan.solve_factor(0, 0, T(q, torch.float32), work=work[: need - 1])
+    with pytest.raises(NpfemError):
+        plan.solve_factor(0, 2, T(q, torch.float32), work=work)
+    empty = torch.zeros((0, npad), dtype=torch.float32, device=dev())
+    assert plan.solve_factor(0, 0, empty, work=work).shape == (0, npad)
+
+
 # ---- objective and gradient -------------------------------------------------------
 
 def eval_case(n, precision, n_cells=6, seed=3):
