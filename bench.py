@@ -350,6 +350,65 @@ def config_c3(args):
             "max_dx_over_D_fp32_vs_fp64_gpu": err, "schedule": b32.schedule()}
 
 
+def config_solves(args):
+    """The constant-matrix solves by four routes on the same right-hand sides: the products
+    with the dense inverse in FP32, with its BF16 off-diagonal part (dense and banded in
+    the reverse Cuthill-McKee order), and the paper's route, forward and back substitution
+    with the banded Cholesky factor of H~.  3 x 100,000 right-hand sides for the
+    642-vertex mesh, 3 x 20,000 for the 2562-vertex one (one per coordinate and cell)."""
+    import torch
+    from rbc_inputs import meshes, workloads
+    from paper_1903_06479_amd import Mesh, Plan, default_params
+    dev = torch.device("cuda:0")
+    out = {"config": "solves", "unit": "ns per right-hand side", "routes": {}}
+    for n, rows in ((642, 300000), (2562, 60000)):
+        X, T = meshes.rbc_mesh(n)
+        g = torch.Generator(device=dev).manual_seed(n)
+        res, ref = {}, None
+        for name, mode in (("dense fp32 product", 0), ("dense bf16 product", 1), ("banded bf16 product", 2)):
+            plan = Plan([Mesh(X, T)], workloads.DT_US, params=default_params(inverse_bf16=mode))
+            npad = plan.n_pad(0)
+            q = torch.zeros((rows, npad), dtype=torch.float32, device=dev)
+            q[:, :n] = torch.randn((rows, n), generator=g, device=dev)
+            g.manual_seed(n)
+            o = torch.empty_like(q)
+            us = _time_us(lambda: plan.apply_inverse(0, 0, q, o))
+            res[name] = us * 1e3 / rows
+            if mode == 0:
+                ref = o[:4096].clone()
+                work = torch.empty(plan.solve_factor_workspace(0, rows), dtype=torch.uint8, device=dev)
+                us = _time_us(lambda: plan.solve_factor(0, 0, q, o, work=work))
+                b = plan.factor_bandwidth(0)
+                res["banded cholesky substitution"] = us * 1e3 / rows
+                flops = 4.0 * n * b * rows
+                res["substitution_half_bandwidth"] = b
+                res["substitution_tflops_4nb"] = flops / us / 1e6
+                res["substitution_frac_of_fp32_valu_peak"] = flops / us / 1e6 / 78.6
+                res["substitution_max_rel_diff_vs_fp32_product"] = float(
+                    ((o[:4096] - ref).abs().max() / ref.abs().max()).item())
+                del work
+            del q, o
+            torch.cuda.empty_cache()
+        out["routes"][f"n={n}, {rows} right-hand sides"] = res
+        log(f"[solves] n={n}: " + ", ".join(f"{k} {v:.3g}" for k, v in res.items()))
+    return out
+
+
+def _time_us(fn, reps=5):
+    """Mean time of fn over reps calls after one untimed call, by events on the current
+    stream (the stream the library launches on)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e3
+
+
 def elongation_index(lam, lam0, lam_inf):
     """Hochmuth's elongation index of the recovery experiment (eq. ElongationIndex):
     e = (lam - lam_inf)(lam0 + lam_inf) / ((lam + lam_inf)(lam0 - lam_inf))."""
@@ -428,7 +487,7 @@ def oracle_error(b, cells, xin, vin, fin, xout):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--config", default="", choices=["", "c1", "c2", "c3", "recovery"],
+    ap.add_argument("--config", default="", choices=["", "c1", "c2", "c3", "recovery", "solves"],
                     help="run one of the other configurations instead of the throughput benchmark")
     ap.add_argument("--c3-steps", type=int, default=5)
     ap.add_argument("--rec-hold", type=int, default=400)
@@ -466,7 +525,8 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": c.numel() * 4}), flush=True)
         return
     if args.config:
-        cfg = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "recovery": config_recovery}[args.config]
+        cfg = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "recovery": config_recovery,
+               "solves": config_solves}[args.config]
         if args.config == "c2" and args.steps == 20:
             args.steps = 100
         print(json.dumps(cfg(args)), flush=True)

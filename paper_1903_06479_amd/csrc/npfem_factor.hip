@@ -77,22 +77,23 @@ __device__ __forceinline__ void band_dot(Real (&acc)[kFactorRows], const Real* _
     acc[7] = fmaf(NPFEM_ROW_BCAST(c, 15), v1, acc[7]);                               \
   } while (0)
 
+// cn holds chunk 0 of this block on entry and chunk 0 of the next block (C_next, null
+// for none) on return, so that the stream of factor entries runs ahead across blocks.
 __device__ __forceinline__ void band_dot(float (&acc)[kFactorRows], const float* __restrict__ C, const float* win,
-                                         int base, int mask, int B, int lane) {
+                                         int base, int mask, int B, int lane, float (&cn)[8],
+                                         const float* __restrict__ C_next) {
   const int l16 = lane & 15;
   const int nch = B / 16;
-  float cn[8];
-#pragma unroll
-  for (int p = 0; p < 8; ++p) cn[p] = C[p * 16 + l16];
   for (int ch = 0; ch < nch; ++ch) {
     float c[8], v[16];
 #pragma unroll
     for (int p = 0; p < 8; ++p) c[p] = cn[p];
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = win[((base + ch * 16 + j) & mask) * kRhs + lane];
-    if (ch + 1 < nch) {
+    const float* __restrict__ src = ch + 1 < nch ? C + (ch + 1) * 128 : C_next;
+    if (src) {
 #pragma unroll
-      for (int p = 0; p < 8; ++p) cn[p] = C[(ch + 1) * 128 + p * 16 + l16];
+      for (int p = 0; p < 8; ++p) cn[p] = src[p * 16 + l16];
     }
 #pragma unroll
     for (int p = 0; p < 8; ++p) NPFEM_PAIR_FMA(c[p], v[2 * p], v[2 * p + 1]);
@@ -100,6 +101,18 @@ __device__ __forceinline__ void band_dot(float (&acc)[kFactorRows], const float*
 }
 #undef NPFEM_PAIR_FMA
 #undef NPFEM_ROW_BCAST
+
+// FP32 diagonal blocks: lane l holds entry l of the block's 72 (t0) and entry 64 + l
+// (t1, lanes < 8), loaded one block ahead; readlane makes each entry a wave-uniform
+// operand.
+__device__ __forceinline__ float diag_entry(float t0, float t1, int idx) {
+  return __builtin_bit_cast(float, idx < 64 ? __builtin_amdgcn_readlane(__builtin_bit_cast(int, t0), idx)
+                                            : __builtin_amdgcn_readlane(__builtin_bit_cast(int, t1), idx - 64));
+}
+__device__ __forceinline__ void load_diag(const float* __restrict__ Tb, int lane, float& t0, float& t1) {
+  t0 = Tb[lane];
+  t1 = lane < kFactorDiag - 64 ? Tb[64 + lane] : 0.0f;
+}
 
 // The pointers are kernel arguments (not struct members) so that their no-alias
 // guarantee lets uniform entries (the FP64 factor, the diagonal blocks) be fetched by
@@ -113,20 +126,32 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
   extern __shared__ __align__(16) unsigned char smem[];
   Real* lds = reinterpret_cast<Real*>(smem);
   const int lane = threadIdx.x;
+  constexpr bool kBcast = sizeof(Real) == 4;   // FP32: factor entries through lane registers
   const int nblk = np / kFactorRows;
   const int64_t r0 = (int64_t)blockIdx.x * kRhs;
   Real* __restrict__ Y = work + (size_t)blockIdx.x * np * kRhs;
 
-  // in[r][k] -> Y[iperm[k]][r - r0]: rows read whole, written back one position per row
+  // in[r][k] -> Y[iperm[k]][r - r0]: rows read whole, written back one position per row.
+  // Addresses are clamped into range (and the values past the end dropped) so that the
+  // loads carry no branches and issue back to back; the chunk's iperm entries are read
+  // once, one per lane, and handed out with readlane.
+  const int64_t r_last = rows - 1;
   for (int k0 = 0; k0 < np; k0 += kRhs) {
-    const int k = k0 + lane;
+    const int k = min(k0 + lane, np - 1);
+    const bool k_ok = k0 + lane < np;
+    const int ip = iperm[k];
+#pragma unroll 16
     for (int rr = 0; rr < kRhs; ++rr) {
       const int64_t r = r0 + rr;
-      lds[rr * kTileRow + lane] = (r < rows && k < np) ? in[r * np + k] : Real(0);
+      const Real val = in[min(r, r_last) * np + k];
+      lds[rr * kTileRow + lane] = (r <= r_last && k_ok) ? val : Real(0);
     }
     __syncthreads();
     const int kn = min(kRhs, np - k0);
-    for (int kk = 0; kk < kn; ++kk) Y[(size_t)iperm[k0 + kk] * kRhs + lane] = lds[lane * kTileRow + kk];
+    for (int kk = 0; kk < kn; ++kk) {
+      const int pos = __builtin_amdgcn_readlane(ip, kk);
+      Y[(size_t)pos * kRhs + lane] = lds[lane * kTileRow + kk];
+    }
     __syncthreads();
   }
 
@@ -137,6 +162,12 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
   for (int s = 0; s <= mask; ++s) win[s * kRhs + lane] = Real(0);
 #pragma unroll
   for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)k * kRhs + lane];
+  [[maybe_unused]] float cn[8], t0, t1;
+  if constexpr (kBcast) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) cn[p] = F[p * 16 + (lane & 15)];
+    load_diag(T, lane, t0, t1);
+  }
   for (int blk = 0; blk < nblk; ++blk) {
     const int i0 = blk * kFactorRows;
     Real acc[kFactorRows];
@@ -146,14 +177,29 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
 #pragma unroll
       for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(i0 + kFactorRows + k) * kRhs + lane];
     }
-    band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, mask, B, lane);
-    const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
+    if constexpr (kBcast) {
+      const bool more = blk + 1 < nblk;
+      band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, mask, B, lane, cn,
+               more ? F + (size_t)(blk + 1) * B * kFactorRows : nullptr);
+      const float ta = t0, tb = t1;
+      if (more) load_diag(T + (size_t)(blk + 1) * kFactorDiag, lane, t0, t1);
 #pragma unroll
-    for (int k = 0; k < kFactorRows; ++k) {
-      Real s = acc[k];
+      for (int k = 0; k < kFactorRows; ++k) {
+        float s = acc[k];
 #pragma unroll
-      for (int l = 0; l < k; ++l) s = fma(-Tb[kFactorRows + k * kFactorRows + l], x[l], s);
-      x[k] = s * Tb[k];
+        for (int l = 0; l < k; ++l) s = fmaf(-diag_entry(ta, tb, kFactorRows + k * kFactorRows + l), x[l], s);
+        x[k] = s * diag_entry(ta, tb, k);
+      }
+    } else {
+      band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, mask, B, lane);
+      const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
+#pragma unroll
+      for (int k = 0; k < kFactorRows; ++k) {
+        Real s = acc[k];
+#pragma unroll
+        for (int l = 0; l < k; ++l) s = fma(-Tb[kFactorRows + k * kFactorRows + l], x[l], s);
+        x[k] = s * Tb[k];
+      }
     }
 #pragma unroll
     for (int k = 0; k < kFactorRows; ++k) {
@@ -166,6 +212,11 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
   for (int s = 0; s <= mask; ++s) win[s * kRhs + lane] = Real(0);
 #pragma unroll
   for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(np - kFactorRows + k) * kRhs + lane];
+  if constexpr (kBcast) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) cn[p] = G[(size_t)(nblk - 1) * B * kFactorRows + p * 16 + (lane & 15)];
+    load_diag(T + (size_t)(nblk - 1) * kFactorDiag, lane, t0, t1);
+  }
   for (int blk = nblk - 1; blk >= 0; --blk) {
     const int i0 = blk * kFactorRows;
     Real acc[kFactorRows];
@@ -175,14 +226,29 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
 #pragma unroll
       for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(i0 - kFactorRows + k) * kRhs + lane];
     }
-    band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, mask, B, lane);
-    const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
+    if constexpr (kBcast) {
+      band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, mask, B, lane, cn,
+               blk > 0 ? G + (size_t)(blk - 1) * B * kFactorRows : nullptr);
+      const float ta = t0, tb = t1;
+      if (blk > 0) load_diag(T + (size_t)(blk - 1) * kFactorDiag, lane, t0, t1);
 #pragma unroll
-    for (int k = kFactorRows - 1; k >= 0; --k) {
-      Real s = acc[k];
+      for (int k = kFactorRows - 1; k >= 0; --k) {
+        float s = acc[k];
 #pragma unroll
-      for (int l = k + 1; l < kFactorRows; ++l) s = fma(-Tb[kFactorRows + l * kFactorRows + k], x[l], s);
-      x[k] = s * Tb[k];
+        for (int l = k + 1; l < kFactorRows; ++l)
+          s = fmaf(-diag_entry(ta, tb, kFactorRows + l * kFactorRows + k), x[l], s);
+        x[k] = s * diag_entry(ta, tb, k);
+      }
+    } else {
+      band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, mask, B, lane);
+      const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
+#pragma unroll
+      for (int k = kFactorRows - 1; k >= 0; --k) {
+        Real s = acc[k];
+#pragma unroll
+        for (int l = k + 1; l < kFactorRows; ++l) s = fma(-Tb[kFactorRows + l * kFactorRows + k], x[l], s);
+        x[k] = s * Tb[k];
+      }
     }
 #pragma unroll
     for (int k = 0; k < kFactorRows; ++k) {
@@ -194,13 +260,17 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
 
   // out[r][k] = Y[iperm[k]][r - r0]
   for (int k0 = 0; k0 < np; k0 += kRhs) {
-    const int kn = min(kRhs, np - k0);
-    for (int kk = 0; kk < kn; ++kk) lds[lane * kTileRow + kk] = Y[(size_t)iperm[k0 + kk] * kRhs + lane];
+    const int ip = iperm[min(k0 + lane, np - 1)];
+#pragma unroll 16
+    for (int kk = 0; kk < kRhs; ++kk) {       // past np: a repeat of the last position, not stored
+      const int pos = __builtin_amdgcn_readlane(ip, kk);
+      lds[lane * kTileRow + kk] = Y[(size_t)pos * kRhs + lane];
+    }
     __syncthreads();
     const int k = k0 + lane;
-    for (int rr = 0; rr < kRhs; ++rr) {
-      const int64_t r = r0 + rr;
-      if (r < rows && k < np) out[r * np + k] = lds[rr * kTileRow + lane];
+    if (k < np) {
+      const int rn = (int)min((int64_t)kRhs, rows - r0);
+      for (int rr = 0; rr < rn; ++rr) out[(r0 + rr) * np + k] = lds[rr * kTileRow + lane];
     }
     __syncthreads();
   }
