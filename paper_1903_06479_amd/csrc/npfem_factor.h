@@ -21,14 +21,14 @@ constexpr int kFactorDiag = kFactorRows + kFactorRows * kFactorRows;
 constexpr size_t kBandSolveMaxLds = 160 * 1024;
 template <typename Real>
 struct BandFactorDev {
-  int b, B, mask;              // half bandwidth, b rounded up to 16, LDS ring size - 1 (ring >= B + 8)
+  int b, B, ring;              // half bandwidth, b rounded up to 16, LDS ring positions (B + 16)
   const int* iperm;            // [n_pad] position of vertex k in the order (identity on padding)
   const Real* F[2];
   const Real* G[2];
   const Real* T[2];
 };
 template <typename Real>
-size_t band_solve_lds_bytes(int mask);
+size_t band_solve_lds_bytes(int ring);
 size_t band_solve_work_bytes(int n_pad, int rows, int real_bytes);
 template <typename Real>
 hipError_t launch_band_solve(const BandFactorDev<Real>& f, int which, int n_pad, const Real* in, Real* out,

@@ -24,15 +24,18 @@ namespace {
 constexpr int kRhs = 64;        // right-hand sides per wave (one per lane)
 constexpr int kTileRow = 65;    // padded row of the 64 x 64 transpose tile
 
-// acc[k] += sum over jj < B of C[jj][k] * ring[(base + jj) & mask], B a multiple of 16
+// acc[k] += sum over jj < B of C[jj][k] * ring[(base + jj) mod W], B a multiple of 16; the
+// ring holds W = B + 16 positions and base is a multiple of 8, so a run of 8 positions
+// that starts at a multiple of 8 never wraps: slots advance 8 at a time.
 // (the factor entries are stored negated).
 //
 // FP64: in groups of one position; the next group's factor entries (scalar loads) and
 // ring value (LDS) are requested before the current group's FMAs.
 template <typename Real>
 __device__ __forceinline__ void band_dot(Real (&acc)[kFactorRows], const Real* __restrict__ C, const Real* win,
-                                         int base, int mask, int B, int lane) {
-  Real c[kFactorRows], v = win[(base & mask) * kRhs + lane];
+                                         int base, int W, int B, int lane) {
+  int slot = ((base % W) + W) % W;
+  Real c[kFactorRows], v = win[slot * kRhs + lane];
 #pragma unroll
   for (int k = 0; k < kFactorRows; ++k) c[k] = C[k];
   for (int g = 0; g < B; ++g) {
@@ -40,7 +43,8 @@ __device__ __forceinline__ void band_dot(Real (&acc)[kFactorRows], const Real* _
 #pragma unroll
     for (int k = 0; k < kFactorRows; ++k) cc[k] = c[k];
     if (g + 1 < B) {
-      v = win[((base + g + 1) & mask) * kRhs + lane];
+      slot = slot + 1 == W ? 0 : slot + 1;
+      v = win[slot * kRhs + lane];
 #pragma unroll
       for (int k = 0; k < kFactorRows; ++k) c[k] = C[(g + 1) * kFactorRows + k];
     }
@@ -59,37 +63,46 @@ __device__ __forceinline__ void band_dot(Real (&acc)[kFactorRows], const Real* _
   __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, (x)), 0x150 + (j), 0xF, 0xF, true))
 #define NPFEM_PAIR_FMA(c, v0, v1)                                                    \
   do {                                                                               \
-    acc[0] = fmaf(NPFEM_ROW_BCAST(c, 0), v0, acc[0]);                                \
-    acc[1] = fmaf(NPFEM_ROW_BCAST(c, 1), v0, acc[1]);                                \
-    acc[2] = fmaf(NPFEM_ROW_BCAST(c, 2), v0, acc[2]);                                \
-    acc[3] = fmaf(NPFEM_ROW_BCAST(c, 3), v0, acc[3]);                                \
-    acc[4] = fmaf(NPFEM_ROW_BCAST(c, 4), v0, acc[4]);                                \
-    acc[5] = fmaf(NPFEM_ROW_BCAST(c, 5), v0, acc[5]);                                \
-    acc[6] = fmaf(NPFEM_ROW_BCAST(c, 6), v0, acc[6]);                                \
-    acc[7] = fmaf(NPFEM_ROW_BCAST(c, 7), v0, acc[7]);                                \
-    acc[0] = fmaf(NPFEM_ROW_BCAST(c, 8), v1, acc[0]);                                \
-    acc[1] = fmaf(NPFEM_ROW_BCAST(c, 9), v1, acc[1]);                                \
-    acc[2] = fmaf(NPFEM_ROW_BCAST(c, 10), v1, acc[2]);                               \
-    acc[3] = fmaf(NPFEM_ROW_BCAST(c, 11), v1, acc[3]);                               \
-    acc[4] = fmaf(NPFEM_ROW_BCAST(c, 12), v1, acc[4]);                               \
-    acc[5] = fmaf(NPFEM_ROW_BCAST(c, 13), v1, acc[5]);                               \
-    acc[6] = fmaf(NPFEM_ROW_BCAST(c, 14), v1, acc[6]);                               \
-    acc[7] = fmaf(NPFEM_ROW_BCAST(c, 15), v1, acc[7]);                               \
+    float b_[16];                                                                    \
+    b_[0] = NPFEM_ROW_BCAST(c, 0);                                                   \
+    b_[1] = NPFEM_ROW_BCAST(c, 1);                                                   \
+    b_[2] = NPFEM_ROW_BCAST(c, 2);                                                   \
+    b_[3] = NPFEM_ROW_BCAST(c, 3);                                                   \
+    b_[4] = NPFEM_ROW_BCAST(c, 4);                                                   \
+    b_[5] = NPFEM_ROW_BCAST(c, 5);                                                   \
+    b_[6] = NPFEM_ROW_BCAST(c, 6);                                                   \
+    b_[7] = NPFEM_ROW_BCAST(c, 7);                                                   \
+    b_[8] = NPFEM_ROW_BCAST(c, 8);                                                   \
+    b_[9] = NPFEM_ROW_BCAST(c, 9);                                                   \
+    b_[10] = NPFEM_ROW_BCAST(c, 10);                                                 \
+    b_[11] = NPFEM_ROW_BCAST(c, 11);                                                 \
+    b_[12] = NPFEM_ROW_BCAST(c, 12);                                                 \
+    b_[13] = NPFEM_ROW_BCAST(c, 13);                                                 \
+    b_[14] = NPFEM_ROW_BCAST(c, 14);                                                 \
+    b_[15] = NPFEM_ROW_BCAST(c, 15);                                                 \
+    _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_) acc[k_] = fmaf(b_[k_], v0, acc[k_]);      \
+    _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_) acc[k_] = fmaf(b_[8 + k_], v1, acc[k_]);  \
   } while (0)
 
 // cn holds chunk 0 of this block on entry and chunk 0 of the next block (C_next, null
 // for none) on return, so that the stream of factor entries runs ahead across blocks.
 __device__ __forceinline__ void band_dot(float (&acc)[kFactorRows], const float* __restrict__ C, const float* win,
-                                         int base, int mask, int B, int lane, float (&cn)[8],
+                                         int base, int W, int B, int lane, float (&cn)[8],
                                          const float* __restrict__ C_next) {
   const int l16 = lane & 15;
   const int nch = B / 16;
+  int s0 = ((base % W) + W) % W;                        // slot of the chunk's first position
   for (int ch = 0; ch < nch; ++ch) {
     float c[8], v[16];
 #pragma unroll
     for (int p = 0; p < 8; ++p) c[p] = cn[p];
+    const int s1 = s0 + 8 == W ? 0 : s0 + 8;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = win[((base + ch * 16 + j) & mask) * kRhs + lane];
+    for (int j = 0; j < 8; ++j) {
+      v[j] = win[(s0 + j) * kRhs + lane];
+      v[8 + j] = win[(s1 + j) * kRhs + lane];
+    }
+    s0 = s1 + 8 == W ? 0 : s1 + 8;
     const float* __restrict__ src = ch + 1 < nch ? C + (ch + 1) * 128 : C_next;
     if (src) {
 #pragma unroll
@@ -121,7 +134,7 @@ template <typename Real>
 __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict__ F, const Real* __restrict__ G,
                                                           const Real* __restrict__ T, const int* __restrict__ iperm,
                                                           const Real* __restrict__ in, Real* __restrict__ out,
-                                                          Real* __restrict__ work, int np, int B, int mask,
+                                                          Real* __restrict__ work, int np, int B, int W,
                                                           int rows) {
   extern __shared__ __align__(16) unsigned char smem[];
   Real* lds = reinterpret_cast<Real*>(smem);
@@ -155,11 +168,11 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
     __syncthreads();
   }
 
-  Real* win = lds;              // ring of the last solved positions, [mask + 1][64]
+  Real* win = lds;              // ring of the last solved positions, [W][64]
   Real nxt[kFactorRows], x[kFactorRows];
 
   // forward: L y = P q, positions ascending
-  for (int s = 0; s <= mask; ++s) win[s * kRhs + lane] = Real(0);
+  for (int s = 0; s < W; ++s) win[s * kRhs + lane] = Real(0);
 #pragma unroll
   for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)k * kRhs + lane];
   [[maybe_unused]] float cn[8], t0, t1;
@@ -179,7 +192,7 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
     }
     if constexpr (kBcast) {
       const bool more = blk + 1 < nblk;
-      band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, mask, B, lane, cn,
+      band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, W, B, lane, cn,
                more ? F + (size_t)(blk + 1) * B * kFactorRows : nullptr);
       const float ta = t0, tb = t1;
       if (more) load_diag(T + (size_t)(blk + 1) * kFactorDiag, lane, t0, t1);
@@ -191,7 +204,7 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
         x[k] = s * diag_entry(ta, tb, k);
       }
     } else {
-      band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, mask, B, lane);
+      band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, W, B, lane);
       const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
 #pragma unroll
       for (int k = 0; k < kFactorRows; ++k) {
@@ -201,15 +214,16 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
         x[k] = s * Tb[k];
       }
     }
+    const int slot = i0 % W;                              // i0 and W are multiples of 8
 #pragma unroll
     for (int k = 0; k < kFactorRows; ++k) {
-      win[((i0 + k) & mask) * kRhs + lane] = x[k];
+      win[(slot + k) * kRhs + lane] = x[k];
       Y[(size_t)(i0 + k) * kRhs + lane] = x[k];
     }
   }
 
   // backward: L^T z = y, positions descending
-  for (int s = 0; s <= mask; ++s) win[s * kRhs + lane] = Real(0);
+  for (int s = 0; s < W; ++s) win[s * kRhs + lane] = Real(0);
 #pragma unroll
   for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(np - kFactorRows + k) * kRhs + lane];
   if constexpr (kBcast) {
@@ -227,7 +241,7 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
       for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(i0 - kFactorRows + k) * kRhs + lane];
     }
     if constexpr (kBcast) {
-      band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, mask, B, lane, cn,
+      band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, W, B, lane, cn,
                blk > 0 ? G + (size_t)(blk - 1) * B * kFactorRows : nullptr);
       const float ta = t0, tb = t1;
       if (blk > 0) load_diag(T + (size_t)(blk - 1) * kFactorDiag, lane, t0, t1);
@@ -240,7 +254,7 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
         x[k] = s * diag_entry(ta, tb, k);
       }
     } else {
-      band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, mask, B, lane);
+      band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, W, B, lane);
       const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
 #pragma unroll
       for (int k = kFactorRows - 1; k >= 0; --k) {
@@ -250,9 +264,10 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
         x[k] = s * Tb[k];
       }
     }
+    const int slot = i0 % W;                              // i0 and W are multiples of 8
 #pragma unroll
     for (int k = 0; k < kFactorRows; ++k) {
-      win[((i0 + k) & mask) * kRhs + lane] = x[k];
+      win[(slot + k) * kRhs + lane] = x[k];
       Y[(size_t)(i0 + k) * kRhs + lane] = x[k];
     }
   }
@@ -279,8 +294,8 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
 }  // namespace
 
 template <typename Real>
-size_t band_solve_lds_bytes(int mask) {
-  return (size_t)std::max(mask + 1, kTileRow) * kRhs * sizeof(Real);
+size_t band_solve_lds_bytes(int ring) {
+  return (size_t)std::max(ring, kTileRow) * kRhs * sizeof(Real);
 }
 
 size_t band_solve_work_bytes(int n_pad, int rows, int real_bytes) {
@@ -291,7 +306,7 @@ template <typename Real>
 hipError_t launch_band_solve(const BandFactorDev<Real>& f, int which, int n_pad, const Real* in, Real* out,
                              Real* work, int rows, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
-  const size_t lds = band_solve_lds_bytes<Real>(f.mask);
+  const size_t lds = band_solve_lds_bytes<Real>(f.ring);
   if (lds > kBandSolveMaxLds) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {          // above the default dynamic LDS limit (set on the current device)
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_kernel<Real>),
@@ -300,7 +315,7 @@ hipError_t launch_band_solve(const BandFactorDev<Real>& f, int which, int n_pad,
   }
   const int grid = (rows + kRhs - 1) / kRhs;
   hipLaunchKernelGGL(band_solve_kernel<Real>, dim3(grid), dim3(kRhs), lds, s, f.F[which], f.G[which], f.T[which],
-                     f.iperm, in, out, work, n_pad, f.B, f.mask, rows);
+                     f.iperm, in, out, work, n_pad, f.B, f.ring, rows);
   return hipGetLastError();
 }
 

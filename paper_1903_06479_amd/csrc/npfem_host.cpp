@@ -566,11 +566,9 @@ npfem_status upload_factor(npfem_plan* p, int np, const std::vector<int>& perm, 
                            BandFactorDev<Real>& f) {
   f = BandFactorDev<Real>{};
   const int B = std::max(fh[0].B, fh[1].B);
-  int ring = 1;
-  while (ring < B + kFactorRows) ring *= 2;
   f.b = std::max(fh[0].b, fh[1].b);
-  f.mask = ring - 1;
-  if (band_solve_lds_bytes<Real>(f.mask) > kBandSolveMaxLds) return NPFEM_OK;
+  f.ring = B + 16;
+  if (band_solve_lds_bytes<Real>(f.ring) > kBandSolveMaxLds) return NPFEM_OK;
   std::vector<int> ip(np);
   for (int k = 0; k < np; ++k) ip[k] = k;
   for (size_t a = 0; a < perm.size(); ++a) ip[perm[a]] = (int)a;
