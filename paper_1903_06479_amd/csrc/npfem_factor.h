@@ -16,7 +16,14 @@ namespace npfem {
 //   T[k] = 1 / L[i0+k][i0+k],  T[8 + 8k + l] = L[i0+k][i0+l] for l < k (else 0)
 // with B the half bandwidth b rounded up to a multiple of 16; padding positions carry
 // the identity.
+//
+// Matrix-core layouts (FP32): blocks of kFactorMfmaRows = 16 positions i0 .. i0+15, k steps
+// of 4 positions, one entry per lane l (row r = l & 15, k index q = l >> 4):
+//   FA[st][l] = -L[i0+r][i0-B+4st+q]     GA[st][l] = -L[i0+16+4st+q][i0+r]
+//   DA[st][l] = (L_D^-1)[r][4st+q]       DB[st][l] = (L_D^-1)[4st+q][r]
+// with L_D the block's 16 x 16 diagonal block.
 constexpr int kFactorRows = 8;
+constexpr int kFactorMfmaRows = 16;
 constexpr int kFactorDiag = kFactorRows + kFactorRows * kFactorRows;
 constexpr size_t kBandSolveMaxLds = 160 * 1024;
 template <typename Real>
@@ -26,6 +33,10 @@ struct BandFactorDev {
   const Real* F[2];
   const Real* G[2];
   const Real* T[2];
+  const Real* FA[2];           // [n_pad / 16][B / 4][64]
+  const Real* GA[2];
+  const Real* DA[2];           // [n_pad / 16][4][64]
+  const Real* DB[2];
 };
 template <typename Real>
 size_t band_solve_lds_bytes(int ring);

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "npfem_factor.h"
 
@@ -127,27 +128,14 @@ __device__ __forceinline__ void load_diag(const float* __restrict__ Tb, int lane
   t1 = lane < kFactorDiag - 64 ? Tb[64 + lane] : 0.0f;
 }
 
-// The pointers are kernel arguments (not struct members) so that their no-alias
-// guarantee lets uniform entries (the FP64 factor, the diagonal blocks) be fetched by
-// scalar loads.
+// in[r][k] -> Y[iperm[k]][r - r0] for the wave's 64 right-hand sides r0 .. r0+63, through
+// the LDS tile `lds` ([64][65]): rows read whole, written back one position per row.
+// Addresses are clamped into range (and the values past the end dropped) so that the
+// loads carry no branches and issue back to back; the chunk's iperm entries are read
+// once, one per lane, and handed out with readlane.
 template <typename Real>
-__global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict__ F, const Real* __restrict__ G,
-                                                          const Real* __restrict__ T, const int* __restrict__ iperm,
-                                                          const Real* __restrict__ in, Real* __restrict__ out,
-                                                          Real* __restrict__ work, int np, int B, int W,
-                                                          int rows) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  Real* lds = reinterpret_cast<Real*>(smem);
-  const int lane = threadIdx.x;
-  constexpr bool kBcast = sizeof(Real) == 4;   // FP32: factor entries through lane registers
-  const int nblk = np / kFactorRows;
-  const int64_t r0 = (int64_t)blockIdx.x * kRhs;
-  Real* __restrict__ Y = work + (size_t)blockIdx.x * np * kRhs;
-
-  // in[r][k] -> Y[iperm[k]][r - r0]: rows read whole, written back one position per row.
-  // Addresses are clamped into range (and the values past the end dropped) so that the
-  // loads carry no branches and issue back to back; the chunk's iperm entries are read
-  // once, one per lane, and handed out with readlane.
+__device__ __forceinline__ void load_rhs(const Real* __restrict__ in, Real* __restrict__ Y, Real* lds,
+                                         const int* __restrict__ iperm, int np, int rows, int64_t r0, int lane) {
   const int64_t r_last = rows - 1;
   for (int k0 = 0; k0 < np; k0 += kRhs) {
     const int k = min(k0 + lane, np - 1);
@@ -167,6 +155,47 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
     }
     __syncthreads();
   }
+}
+
+// out[r][k] = Y[iperm[k]][r - r0], the same way back.
+template <typename Real>
+__device__ __forceinline__ void store_solution(const Real* __restrict__ Y, Real* lds, const int* __restrict__ iperm,
+                                               Real* __restrict__ out, int np, int rows, int64_t r0, int lane) {
+  for (int k0 = 0; k0 < np; k0 += kRhs) {
+    const int ip = iperm[min(k0 + lane, np - 1)];
+#pragma unroll 16
+    for (int kk = 0; kk < kRhs; ++kk) {       // past np: a repeat of the last position, not stored
+      const int pos = __builtin_amdgcn_readlane(ip, kk);
+      lds[lane * kTileRow + kk] = Y[(size_t)pos * kRhs + lane];
+    }
+    __syncthreads();
+    const int k = k0 + lane;
+    if (k < np) {
+      const int rn = (int)min((int64_t)kRhs, rows - r0);
+      for (int rr = 0; rr < rn; ++rr) out[(r0 + rr) * np + k] = lds[rr * kTileRow + lane];
+    }
+    __syncthreads();
+  }
+}
+
+// The pointers are kernel arguments (not struct members) so that their no-alias
+// guarantee lets uniform entries (the FP64 factor, the diagonal blocks) be fetched by
+// scalar loads.
+template <typename Real>
+__global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict__ F, const Real* __restrict__ G,
+                                                          const Real* __restrict__ T, const int* __restrict__ iperm,
+                                                          const Real* __restrict__ in, Real* __restrict__ out,
+                                                          Real* __restrict__ work, int np, int B, int W,
+                                                          int rows) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Real* lds = reinterpret_cast<Real*>(smem);
+  const int lane = threadIdx.x;
+  constexpr bool kBcast = sizeof(Real) == 4;   // FP32: factor entries through lane registers
+  const int nblk = np / kFactorRows;
+  const int64_t r0 = (int64_t)blockIdx.x * kRhs;
+  Real* __restrict__ Y = work + (size_t)blockIdx.x * np * kRhs;
+
+  load_rhs(in, Y, lds, iperm, np, rows, r0, lane);
 
   Real* win = lds;              // ring of the last solved positions, [W][64]
   Real nxt[kFactorRows], x[kFactorRows];
@@ -273,22 +302,124 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
   }
   __syncthreads();
 
-  // out[r][k] = Y[iperm[k]][r - r0]
-  for (int k0 = 0; k0 < np; k0 += kRhs) {
-    const int ip = iperm[min(k0 + lane, np - 1)];
-#pragma unroll 16
-    for (int kk = 0; kk < kRhs; ++kk) {       // past np: a repeat of the last position, not stored
-      const int pos = __builtin_amdgcn_readlane(ip, kk);
-      lds[lane * kTileRow + kk] = Y[(size_t)pos * kRhs + lane];
-    }
-    __syncthreads();
-    const int k = k0 + lane;
-    if (k < np) {
-      const int rn = (int)min((int64_t)kRhs, rows - r0);
-      for (int rr = 0; rr < rn; ++rr) out[(r0 + rr) * np + k] = lds[rr * kTileRow + lane];
-    }
-    __syncthreads();
+  store_solution(Y, lds, iperm, out, np, rows, r0, lane);
+}
+
+// FP32 substitution on the matrix cores (v_mfma_f32_16x16x4_f32), blocks of 16 positions.
+// A block's update from the solved window, acc -= L[block][window] x[window], is a 16 x B
+// by B x 64 product: A operand the factor (one entry per lane, so no broadcast), B operand
+// the ring (position x right-hand side), four accumulator tiles of 16 right-hand sides
+// (lane l holds rows 4 (l >> 4) .. +3 of column l & 15).  The 16 x 16 diagonal block is
+// applied as its inverse, 16 more matrix instructions; the right-hand sides reach the B
+// layout through the ring slots the block is about to fill.  The factor stream runs one
+// 16-position group ahead across blocks; Y rows and the diagonal inverse one block ahead.
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+template <bool kFwd>
+__device__ __forceinline__ void mfma_pass(const float* __restrict__ A, const float* __restrict__ D,
+                                          float* __restrict__ Y, float* win, int np, int B, int W, int lane) {
+  const int l16 = lane & 15, kq = lane >> 4;
+  const int nb = np / kFactorMfmaRows, ks = B / 4, ng = B / 16;
+  for (int s = 0; s < W; ++s) win[s * kRhs + lane] = 0.f;
+  const int b_first = kFwd ? 0 : nb - 1;
+  floatx4_t nxt[4];
+  float an[4], dn[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) nxt[t][r] = Y[(size_t)(b_first * 16 + 4 * kq + r) * kRhs + t * 16 + l16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    an[q] = A[((size_t)b_first * ks + q) * 64 + lane];
+    dn[q] = D[((size_t)b_first * 4 + q) * 64 + lane];
   }
+  for (int it = 0; it < nb; ++it) {
+    const int bi = kFwd ? it : nb - 1 - it;
+    const bool more = it + 1 < nb;
+    const int bn = kFwd ? bi + 1 : bi - 1;
+    const int i0 = bi * kFactorMfmaRows;
+    floatx4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = nxt[t];
+    if (more) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) nxt[t][r] = Y[(size_t)(bn * 16 + 4 * kq + r) * kRhs + t * 16 + l16];
+    }
+    const float* __restrict__ Ab = A + (size_t)bi * ks * 64;
+    const float* __restrict__ An = more ? A + (size_t)bn * ks * 64 : nullptr;
+    const int base = kFwd ? i0 - B : i0 + kFactorMfmaRows;
+    int sb = ((base % W) + W) % W;                   // a multiple of 16, as are B and W
+    for (int g = 0; g < ng; ++g) {
+      float a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = an[q];
+      const float* __restrict__ src = g + 1 < ng ? Ab + (g + 1) * 256 : An;
+      if (src) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) an[q] = src[q * 64 + lane];
+      }
+      float bv[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[q][t] = win[(sb + 4 * q + kq) * kRhs + t * 16 + l16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], bv[q][t], acc[t], 0, 0, 0);
+      sb = sb + 16 == W ? 0 : sb + 16;
+    }
+    // the diagonal block: x = L_D^-1 acc (forward) or L_D^-T acc (backward)
+    float d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[q] = dn[q];
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dn[q] = D[((size_t)bn * 4 + q) * 64 + lane];
+    }
+    const int sd = i0 % W;                           // multiples of 16: no wrap inside the block
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) win[(sd + 4 * kq + r) * kRhs + t * 16 + l16] = acc[t][r];
+    floatx4_t x[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) x[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        x[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(d[q], win[(sd + 4 * q + kq) * kRhs + t * 16 + l16], x[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        win[(sd + 4 * kq + r) * kRhs + t * 16 + l16] = x[t][r];
+        Y[(size_t)(i0 + 4 * kq + r) * kRhs + t * 16 + l16] = x[t][r];
+      }
+  }
+}
+
+__global__ __launch_bounds__(kRhs) void band_solve_mfma_kernel(const float* __restrict__ FA,
+                                                               const float* __restrict__ GA,
+                                                               const float* __restrict__ DA,
+                                                               const float* __restrict__ DB,
+                                                               const int* __restrict__ iperm,
+                                                               const float* __restrict__ in, float* __restrict__ out,
+                                                               float* __restrict__ work, int np, int B, int W,
+                                                               int rows) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* lds = reinterpret_cast<float*>(smem);
+  const int lane = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kRhs;
+  float* __restrict__ Y = work + (size_t)blockIdx.x * np * kRhs;
+  load_rhs(in, Y, lds, iperm, np, rows, r0, lane);       // ends with a barrier: Y visible to all lanes
+  mfma_pass<true>(FA, DA, Y, lds, np, B, W, lane);
+  mfma_pass<false>(GA, DB, Y, lds, np, B, W, lane);
+  __syncthreads();
+  store_solution(Y, lds, iperm, out, np, rows, r0, lane);
 }
 
 }  // namespace
@@ -314,6 +445,18 @@ hipError_t launch_band_solve(const BandFactorDev<Real>& f, int which, int n_pad,
     if (e != hipSuccess) return e;
   }
   const int grid = (rows + kRhs - 1) / kRhs;
+  if constexpr (std::is_same<Real, float>::value) {
+    if (f.FA[which]) {                       // FP32: the matrix-core form
+      if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_mfma_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(band_solve_mfma_kernel, dim3(grid), dim3(kRhs), lds, s, f.FA[which], f.GA[which],
+                         f.DA[which], f.DB[which], f.iperm, in, out, work, n_pad, f.B, f.ring, rows);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL(band_solve_kernel<Real>, dim3(grid), dim3(kRhs), lds, s, f.F[which], f.G[which], f.T[which],
                      f.iperm, in, out, work, n_pad, f.B, f.ring, rows);
   return hipGetLastError();

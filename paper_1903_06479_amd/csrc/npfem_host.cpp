@@ -495,17 +495,20 @@ std::vector<int> rcm_order(const npfem_mesh* m) {
   return order;
 }
 
-// Banded Cholesky factor of P A P^T (P: the order `perm`, A dense FP64 n x n) in the
-// block layout of the substitution kernel (see BandFactorDev): coefficient arrays F, G,
-// T of n_pad / 8 blocks; false if A is not positive definite.  The factor is computed
+// Banded Cholesky factor of P A P^T (P: the order `perm`, A dense FP64 n x n), computed
 // within the band of the permuted matrix only (a banded matrix's Cholesky factor keeps
-// its band).
+// its band); false if A is not positive definite.
 struct BandFactorHost {
-  int b = 0, B = 0;
-  std::vector<double> F, G, T;
+  int n = 0, b = 0;
+  std::vector<double> L;               // [n][n], zero outside the band
+  // entry (i, j) of the factor padded to n_pad: the identity on the padding positions
+  double at(int i, int j) const {
+    if (i < n && j < n) return (j <= i && i - j <= b) ? L[(size_t)i * n + j] : 0.0;
+    return i == j ? 1.0 : 0.0;
+  }
 };
 
-bool band_factor(const std::vector<double>& A, int n, int np, const std::vector<int>& perm, BandFactorHost& out) {
+bool band_factor(const std::vector<double>& A, int n, const std::vector<int>& perm, BandFactorHost& out) {
   std::vector<double> Ap((size_t)n * n);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) Ap[(size_t)i * n + j] = A[(size_t)perm[i] * n + perm[j]];
@@ -516,7 +519,8 @@ bool band_factor(const std::vector<double>& A, int n, int np, const std::vector<
         b = std::max(b, i - j);
         break;
       }
-  std::vector<double> L((size_t)n * n, 0.0);
+  std::vector<double>& L = out.L;
+  L.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) {
     const int lo = std::max(0, i - b);
     for (int j = lo; j <= i; ++j) {
@@ -530,43 +534,77 @@ bool band_factor(const std::vector<double>& A, int n, int np, const std::vector<
       }
     }
   }
-  // entry (i, j) of the padded factor: the identity on the padding positions
-  auto Lf = [&](int i, int j) -> double {
-    if (i < n && j < n) return (j <= i && i - j <= b) ? L[(size_t)i * n + j] : 0.0;
-    return i == j ? 1.0 : 0.0;
-  };
-  const int R = kFactorRows, nblk = np / R;
-  const int B = std::max(16, (b + 15) / 16 * 16);
+  out.n = n;
   out.b = b;
-  out.B = B;
-  out.F.assign((size_t)nblk * B * R, 0.0);
-  out.G.assign((size_t)nblk * B * R, 0.0);
-  out.T.assign((size_t)nblk * kFactorDiag, 0.0);
+  return true;
+}
+
+// The factor in the layouts of the substitution kernels (see BandFactorDev) for a band
+// width B (a multiple of 16, at least b) and n_pad positions.
+template <typename Real>
+void factor_layouts(const BandFactorHost& f, int np, int B, std::vector<Real>& F, std::vector<Real>& G,
+                    std::vector<Real>& T, std::vector<Real>& FA, std::vector<Real>& GA, std::vector<Real>& DA,
+                    std::vector<Real>& DB) {
+  const int R = kFactorRows, nblk = np / R;
+  F.assign((size_t)nblk * B * R, Real(0));
+  G.assign((size_t)nblk * B * R, Real(0));
+  T.assign((size_t)nblk * kFactorDiag, Real(0));
   for (int blk = 0; blk < nblk; ++blk) {
     const int i0 = blk * R;
     for (int jj = 0; jj < B; ++jj)
       for (int k = 0; k < R; ++k) {
         const int jf = i0 - B + jj, jg = i0 + R + jj;
-        if (jf >= 0) out.F[((size_t)blk * B + jj) * R + k] = -Lf(i0 + k, jf);
-        if (jg < np) out.G[((size_t)blk * B + jj) * R + k] = -Lf(jg, i0 + k);
+        if (jf >= 0) F[((size_t)blk * B + jj) * R + k] = Real(-f.at(i0 + k, jf));
+        if (jg < np) G[((size_t)blk * B + jj) * R + k] = Real(-f.at(jg, i0 + k));
       }
-    double* Tb = &out.T[(size_t)blk * kFactorDiag];
+    Real* Tb = &T[(size_t)blk * kFactorDiag];
     for (int k = 0; k < R; ++k) {
-      Tb[k] = 1.0 / Lf(i0 + k, i0 + k);
-      for (int l = 0; l < k; ++l) Tb[R + k * R + l] = Lf(i0 + k, i0 + l);
+      Tb[k] = Real(1.0 / f.at(i0 + k, i0 + k));
+      for (int l = 0; l < k; ++l) Tb[R + k * R + l] = Real(f.at(i0 + k, i0 + l));
     }
   }
-  return true;
+  // matrix-core layouts: blocks of 16 positions, k steps of 4, one entry per lane
+  // (lane l: row l & 15, k index l >> 4)
+  const int M = kFactorMfmaRows, nb = np / M, ks = B / 4;
+  FA.assign((size_t)nb * ks * 64, Real(0));
+  GA.assign((size_t)nb * ks * 64, Real(0));
+  DA.assign((size_t)nb * 4 * 64, Real(0));
+  DB.assign((size_t)nb * 4 * 64, Real(0));
+  for (int bi = 0; bi < nb; ++bi) {
+    const int i0 = bi * M;
+    for (int st = 0; st < ks; ++st)
+      for (int l = 0; l < 64; ++l) {
+        const int row = i0 + (l & 15), kq = l >> 4;
+        const int jf = i0 - B + 4 * st + kq, jg = i0 + M + 4 * st + kq;
+        if (jf >= 0) FA[((size_t)bi * ks + st) * 64 + l] = Real(-f.at(row, jf));
+        if (jg < np) GA[((size_t)bi * ks + st) * 64 + l] = Real(-f.at(jg, row));
+      }
+    // inverse of the 16 x 16 lower-triangular diagonal block, by forward substitution
+    double Dinv[16][16] = {};
+    for (int c = 0; c < M; ++c)
+      for (int r = c; r < M; ++r) {
+        double t = r == c ? 1.0 : 0.0;
+        for (int q = c; q < r; ++q) t -= f.at(i0 + r, i0 + q) * Dinv[q][c];
+        Dinv[r][c] = t / f.at(i0 + r, i0 + r);
+      }
+    for (int st = 0; st < 4; ++st)
+      for (int l = 0; l < 64; ++l) {
+        const int r = l & 15, k = 4 * st + (l >> 4);
+        DA[((size_t)bi * 4 + st) * 64 + l] = Real(Dinv[r][k]);     // L_D^-1
+        DB[((size_t)bi * 4 + st) * 64 + l] = Real(Dinv[k][r]);     // L_D^-T
+      }
+  }
 }
 
-// Uploads both factors (H~ and M~/h^2) in precision Real with the order's inverse
-// permutation; leaves f.F[0] null when the kernel's LDS ring would not fit a compute unit.
+// Uploads both factors (H~ and M~/h^2) in precision Real, in one band width B (the wider
+// of the two), with the order's inverse permutation; leaves f.F[0] null when the
+// kernel's LDS ring would not fit a compute unit.
 template <typename Real>
 npfem_status upload_factor(npfem_plan* p, int np, const std::vector<int>& perm, const BandFactorHost (&fh)[2],
                            BandFactorDev<Real>& f) {
   f = BandFactorDev<Real>{};
-  const int B = std::max(fh[0].B, fh[1].B);
   f.b = std::max(fh[0].b, fh[1].b);
+  const int B = std::max(16, (f.b + 15) / 16 * 16);
   f.ring = B + 16;
   if (band_solve_lds_bytes<Real>(f.ring) > kBandSolveMaxLds) return NPFEM_OK;
   std::vector<int> ip(np);
@@ -575,21 +613,18 @@ npfem_status upload_factor(npfem_plan* p, int np, const std::vector<int>& perm, 
   npfem_status s;
   if ((s = p->buf.upload(ip.data(), ip.size(), &f.iperm))) return s;
   f.B = B;
-  const int R = kFactorRows, nblk = np / R;
   for (int w = 0; w < 2; ++w) {
-    // both factors in the wider of the two bands (zero-extended)
-    std::vector<Real> F((size_t)nblk * B * R, Real(0)), G((size_t)nblk * B * R, Real(0));
-    const int Bw = fh[w].B, sh = B - Bw;
-    for (int blk = 0; blk < nblk; ++blk)
-      for (int jj = 0; jj < Bw; ++jj)
-        for (int k = 0; k < R; ++k) {
-          F[((size_t)blk * B + jj + sh) * R + k] = Real(fh[w].F[((size_t)blk * Bw + jj) * R + k]);
-          G[((size_t)blk * B + jj) * R + k] = Real(fh[w].G[((size_t)blk * Bw + jj) * R + k]);
-        }
-    std::vector<Real> T(fh[w].T.begin(), fh[w].T.end());
+    std::vector<Real> F, G, T, FA, GA, DA, DB;
+    factor_layouts<Real>(fh[w], np, B, F, G, T, FA, GA, DA, DB);
     if ((s = p->buf.upload(F.data(), F.size(), &f.F[w]))) return s;
     if ((s = p->buf.upload(G.data(), G.size(), &f.G[w]))) return s;
     if ((s = p->buf.upload(T.data(), T.size(), &f.T[w]))) return s;
+    if constexpr (std::is_same<Real, float>::value) {       // the matrix-core kernel is FP32 only
+      if ((s = p->buf.upload(FA.data(), FA.size(), &f.FA[w]))) return s;
+      if ((s = p->buf.upload(GA.data(), GA.size(), &f.GA[w]))) return s;
+      if ((s = p->buf.upload(DA.data(), DA.size(), &f.DA[w]))) return s;
+      if ((s = p->buf.upload(DB.data(), DB.size(), &f.DB[w]))) return s;
+    }
   }
   return NPFEM_OK;
 }
@@ -861,9 +896,9 @@ npfem_status npfem_plan_create(int32_t device, const npfem_mesh* const* meshes, 
       std::vector<double> Ms(Mt);
       for (double& v : Ms) v /= h * h;
       BandFactorHost fh[2];
-      if (!band_factor(Ht, n, mp.n_pad, perm, fh[0]))
+      if (!band_factor(Ht, n, perm, fh[0]))
         return fail(NPFEM_E_NOT_SPD, "plan_create: H~ is not positive definite");
-      if (!band_factor(Ms, n, mp.n_pad, perm, fh[1]))
+      if (!band_factor(Ms, n, perm, fh[1]))
         return fail(NPFEM_E_NOT_SPD, "plan_create: M~ is not positive definite");
       npfem_status fs = fp64 ? upload_factor<double>(p.get(), mp.n_pad, perm, fh, mp.fac64)
                              : upload_factor<float>(p.get(), mp.n_pad, perm, fh, mp.fac32);
