@@ -9,8 +9,9 @@
 namespace npfem {
 
 // Banded Cholesky factors of H~ (index 0) and M~/h^2 (index 1) in the reverse
-// Cuthill-McKee order, laid out for the substitution kernel (npfem_factor.hip): rows in
-// blocks of kFactorRows positions i0 .. i0+7, per block
+// Cuthill-McKee order, laid out for the substitution kernels (npfem_factor.hip).
+// Vector-unit layouts (FP64): rows in blocks of kFactorRows positions i0 .. i0+7, per
+// block
 //   F[jj][k] = -L[i0+k][i0-B+jj]     (0 outside the band or for negative columns)
 //   G[jj][k] = -L[i0+8+jj][i0+k]     (0 outside the band or beyond n_pad)
 //   T[k] = 1 / L[i0+k][i0+k],  T[8 + 8k + l] = L[i0+k][i0+l] for l < k (else 0)

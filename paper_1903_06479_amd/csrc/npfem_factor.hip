@@ -4,14 +4,16 @@
 // reverse Cuthill-McKee order of the mesh, so that L is banded (half bandwidth b); each
 // right-hand side q then needs L y = P q and L^T z = y, out = P^T z.
 //
-// Mapping: one wave per 64 right-hand sides, one lane per right-hand side.  The serial
-// chain over the n rows is the same for every lane, so the factor entries are uniform
-// across the wave and are read through the scalar unit; the lane's last b solution
-// entries sit in an LDS ring (one 256-byte row per position).  Rows are solved eight at a
-// time: every ring entry read feeds eight FMAs (one per row of the block), and the
-// 8 x 8 diagonal block is solved in registers.  The right-hand sides are brought into
-// the order and transposed to [position][lane] once, through an LDS tile, into the
-// caller's workspace, which then holds y and z; the result goes back the same way.
+// Both kernels give one wave 64 right-hand sides.  The right-hand sides are brought into
+// the order and transposed to [position][right-hand side] once, through an LDS tile, into
+// the caller's workspace, which then holds y and z; the result goes back the same way.
+// The solved positions still inside the band sit in an LDS ring (one 256-byte row per
+// position).
+//   FP32: the matrix cores, blocks of 16 positions (band_solve_mfma_kernel).
+//   FP64: the vector units, one lane per right-hand side, blocks of 8 positions; the
+//         factor entries are uniform across the wave and are read through the scalar
+//         unit, every ring read feeds eight FMAs and the 8 x 8 diagonal block is solved
+//         in registers (band_solve_kernel).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,80 +54,6 @@ __device__ __forceinline__ void band_dot(Real (&acc)[kFactorRows], const Real* _
 #pragma unroll
     for (int k = 0; k < kFactorRows; ++k) acc[k] = fma(cc[k], vv, acc[k]);
   }
-}
-
-// FP32: the factor entries are uniform across the wave, but scalar loads would share
-// their wait counter with the ring's LDS reads, which leaves only one group of entries
-// in flight.  Instead each lane holds, per chunk of 16 positions, one entry of each pair
-// of positions (pair p: lane l & 15 holds C[2p + (l & 15) / 8][(l & 15) % 8], the same
-// in each 16-lane row), fetched by vector loads one chunk ahead, and a DPP row
-// broadcast (row_newbcast) hands entry j of the pair to every lane of the row.
-#define NPFEM_ROW_BCAST(x, j) \
-  __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, (x)), 0x150 + (j), 0xF, 0xF, true))
-#define NPFEM_PAIR_FMA(c, v0, v1)                                                    \
-  do {                                                                               \
-    float b_[16];                                                                    \
-    b_[0] = NPFEM_ROW_BCAST(c, 0);                                                   \
-    b_[1] = NPFEM_ROW_BCAST(c, 1);                                                   \
-    b_[2] = NPFEM_ROW_BCAST(c, 2);                                                   \
-    b_[3] = NPFEM_ROW_BCAST(c, 3);                                                   \
-    b_[4] = NPFEM_ROW_BCAST(c, 4);                                                   \
-    b_[5] = NPFEM_ROW_BCAST(c, 5);                                                   \
-    b_[6] = NPFEM_ROW_BCAST(c, 6);                                                   \
-    b_[7] = NPFEM_ROW_BCAST(c, 7);                                                   \
-    b_[8] = NPFEM_ROW_BCAST(c, 8);                                                   \
-    b_[9] = NPFEM_ROW_BCAST(c, 9);                                                   \
-    b_[10] = NPFEM_ROW_BCAST(c, 10);                                                 \
-    b_[11] = NPFEM_ROW_BCAST(c, 11);                                                 \
-    b_[12] = NPFEM_ROW_BCAST(c, 12);                                                 \
-    b_[13] = NPFEM_ROW_BCAST(c, 13);                                                 \
-    b_[14] = NPFEM_ROW_BCAST(c, 14);                                                 \
-    b_[15] = NPFEM_ROW_BCAST(c, 15);                                                 \
-    _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_) acc[k_] = fmaf(b_[k_], v0, acc[k_]);      \
-    _Pragma("unroll") for (int k_ = 0; k_ < 8; ++k_) acc[k_] = fmaf(b_[8 + k_], v1, acc[k_]);  \
-  } while (0)
-
-// cn holds chunk 0 of this block on entry and chunk 0 of the next block (C_next, null
-// for none) on return, so that the stream of factor entries runs ahead across blocks.
-__device__ __forceinline__ void band_dot(float (&acc)[kFactorRows], const float* __restrict__ C, const float* win,
-                                         int base, int W, int B, int lane, float (&cn)[8],
-                                         const float* __restrict__ C_next) {
-  const int l16 = lane & 15;
-  const int nch = B / 16;
-  int s0 = ((base % W) + W) % W;                        // slot of the chunk's first position
-  for (int ch = 0; ch < nch; ++ch) {
-    float c[8], v[16];
-#pragma unroll
-    for (int p = 0; p < 8; ++p) c[p] = cn[p];
-    const int s1 = s0 + 8 == W ? 0 : s0 + 8;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      v[j] = win[(s0 + j) * kRhs + lane];
-      v[8 + j] = win[(s1 + j) * kRhs + lane];
-    }
-    s0 = s1 + 8 == W ? 0 : s1 + 8;
-    const float* __restrict__ src = ch + 1 < nch ? C + (ch + 1) * 128 : C_next;
-    if (src) {
-#pragma unroll
-      for (int p = 0; p < 8; ++p) cn[p] = src[p * 16 + l16];
-    }
-#pragma unroll
-    for (int p = 0; p < 8; ++p) NPFEM_PAIR_FMA(c[p], v[2 * p], v[2 * p + 1]);
-  }
-}
-#undef NPFEM_PAIR_FMA
-#undef NPFEM_ROW_BCAST
-
-// FP32 diagonal blocks: lane l holds entry l of the block's 72 (t0) and entry 64 + l
-// (t1, lanes < 8), loaded one block ahead; readlane makes each entry a wave-uniform
-// operand.
-__device__ __forceinline__ float diag_entry(float t0, float t1, int idx) {
-  return __builtin_bit_cast(float, idx < 64 ? __builtin_amdgcn_readlane(__builtin_bit_cast(int, t0), idx)
-                                            : __builtin_amdgcn_readlane(__builtin_bit_cast(int, t1), idx - 64));
-}
-__device__ __forceinline__ void load_diag(const float* __restrict__ Tb, int lane, float& t0, float& t1) {
-  t0 = Tb[lane];
-  t1 = lane < kFactorDiag - 64 ? Tb[64 + lane] : 0.0f;
 }
 
 // in[r][k] -> Y[iperm[k]][r - r0] for the wave's 64 right-hand sides r0 .. r0+63, through
@@ -190,7 +118,6 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
   extern __shared__ __align__(16) unsigned char smem[];
   Real* lds = reinterpret_cast<Real*>(smem);
   const int lane = threadIdx.x;
-  constexpr bool kBcast = sizeof(Real) == 4;   // FP32: factor entries through lane registers
   const int nblk = np / kFactorRows;
   const int64_t r0 = (int64_t)blockIdx.x * kRhs;
   Real* __restrict__ Y = work + (size_t)blockIdx.x * np * kRhs;
@@ -204,12 +131,6 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
   for (int s = 0; s < W; ++s) win[s * kRhs + lane] = Real(0);
 #pragma unroll
   for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)k * kRhs + lane];
-  [[maybe_unused]] float cn[8], t0, t1;
-  if constexpr (kBcast) {
-#pragma unroll
-    for (int p = 0; p < 8; ++p) cn[p] = F[p * 16 + (lane & 15)];
-    load_diag(T, lane, t0, t1);
-  }
   for (int blk = 0; blk < nblk; ++blk) {
     const int i0 = blk * kFactorRows;
     Real acc[kFactorRows];
@@ -219,29 +140,14 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
 #pragma unroll
       for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(i0 + kFactorRows + k) * kRhs + lane];
     }
-    if constexpr (kBcast) {
-      const bool more = blk + 1 < nblk;
-      band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, W, B, lane, cn,
-               more ? F + (size_t)(blk + 1) * B * kFactorRows : nullptr);
-      const float ta = t0, tb = t1;
-      if (more) load_diag(T + (size_t)(blk + 1) * kFactorDiag, lane, t0, t1);
+    band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, W, B, lane);
+    const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
 #pragma unroll
-      for (int k = 0; k < kFactorRows; ++k) {
-        float s = acc[k];
+    for (int k = 0; k < kFactorRows; ++k) {
+      Real s = acc[k];
 #pragma unroll
-        for (int l = 0; l < k; ++l) s = fmaf(-diag_entry(ta, tb, kFactorRows + k * kFactorRows + l), x[l], s);
-        x[k] = s * diag_entry(ta, tb, k);
-      }
-    } else {
-      band_dot(acc, F + (size_t)blk * B * kFactorRows, win, i0 - B, W, B, lane);
-      const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
-#pragma unroll
-      for (int k = 0; k < kFactorRows; ++k) {
-        Real s = acc[k];
-#pragma unroll
-        for (int l = 0; l < k; ++l) s = fma(-Tb[kFactorRows + k * kFactorRows + l], x[l], s);
-        x[k] = s * Tb[k];
-      }
+      for (int l = 0; l < k; ++l) s = fma(-Tb[kFactorRows + k * kFactorRows + l], x[l], s);
+      x[k] = s * Tb[k];
     }
     const int slot = i0 % W;                              // i0 and W are multiples of 8
 #pragma unroll
@@ -255,11 +161,6 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
   for (int s = 0; s < W; ++s) win[s * kRhs + lane] = Real(0);
 #pragma unroll
   for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(np - kFactorRows + k) * kRhs + lane];
-  if constexpr (kBcast) {
-#pragma unroll
-    for (int p = 0; p < 8; ++p) cn[p] = G[(size_t)(nblk - 1) * B * kFactorRows + p * 16 + (lane & 15)];
-    load_diag(T + (size_t)(nblk - 1) * kFactorDiag, lane, t0, t1);
-  }
   for (int blk = nblk - 1; blk >= 0; --blk) {
     const int i0 = blk * kFactorRows;
     Real acc[kFactorRows];
@@ -269,29 +170,14 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
 #pragma unroll
       for (int k = 0; k < kFactorRows; ++k) nxt[k] = Y[(size_t)(i0 - kFactorRows + k) * kRhs + lane];
     }
-    if constexpr (kBcast) {
-      band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, W, B, lane, cn,
-               blk > 0 ? G + (size_t)(blk - 1) * B * kFactorRows : nullptr);
-      const float ta = t0, tb = t1;
-      if (blk > 0) load_diag(T + (size_t)(blk - 1) * kFactorDiag, lane, t0, t1);
+    band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, W, B, lane);
+    const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
 #pragma unroll
-      for (int k = kFactorRows - 1; k >= 0; --k) {
-        float s = acc[k];
+    for (int k = kFactorRows - 1; k >= 0; --k) {
+      Real s = acc[k];
 #pragma unroll
-        for (int l = k + 1; l < kFactorRows; ++l)
-          s = fmaf(-diag_entry(ta, tb, kFactorRows + l * kFactorRows + k), x[l], s);
-        x[k] = s * diag_entry(ta, tb, k);
-      }
-    } else {
-      band_dot(acc, G + (size_t)blk * B * kFactorRows, win, i0 + kFactorRows, W, B, lane);
-      const Real* __restrict__ Tb = T + (size_t)blk * kFactorDiag;
-#pragma unroll
-      for (int k = kFactorRows - 1; k >= 0; --k) {
-        Real s = acc[k];
-#pragma unroll
-        for (int l = k + 1; l < kFactorRows; ++l) s = fma(-Tb[kFactorRows + l * kFactorRows + k], x[l], s);
-        x[k] = s * Tb[k];
-      }
+      for (int l = k + 1; l < kFactorRows; ++l) s = fma(-Tb[kFactorRows + l * kFactorRows + k], x[l], s);
+      x[k] = s * Tb[k];
     }
     const int slot = i0 % W;                              // i0 and W are multiples of 8
 #pragma unroll
@@ -439,26 +325,20 @@ hipError_t launch_band_solve(const BandFactorDev<Real>& f, int which, int n_pad,
   if (rows <= 0) return hipSuccess;
   const size_t lds = band_solve_lds_bytes<Real>(f.ring);
   if (lds > kBandSolveMaxLds) return hipErrorInvalidValue;
+  const int grid = (rows + kRhs - 1) / kRhs;
+  const void* fn;
+  if constexpr (std::is_same<Real, float>::value) fn = reinterpret_cast<const void*>(&band_solve_mfma_kernel);
+  else fn = reinterpret_cast<const void*>(&band_solve_kernel<double>);
   if (lds > 64 * 1024) {          // above the default dynamic LDS limit (set on the current device)
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_kernel<Real>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const int grid = (rows + kRhs - 1) / kRhs;
-  if constexpr (std::is_same<Real, float>::value) {
-    if (f.FA[which]) {                       // FP32: the matrix-core form
-      if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&band_solve_mfma_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-      }
-      hipLaunchKernelGGL(band_solve_mfma_kernel, dim3(grid), dim3(kRhs), lds, s, f.FA[which], f.GA[which],
-                         f.DA[which], f.DB[which], f.iperm, in, out, work, n_pad, f.B, f.ring, rows);
-      return hipGetLastError();
-    }
-  }
-  hipLaunchKernelGGL(band_solve_kernel<Real>, dim3(grid), dim3(kRhs), lds, s, f.F[which], f.G[which], f.T[which],
-                     f.iperm, in, out, work, n_pad, f.B, f.ring, rows);
+  if constexpr (std::is_same<Real, float>::value)
+    hipLaunchKernelGGL(band_solve_mfma_kernel, dim3(grid), dim3(kRhs), lds, s, f.FA[which], f.GA[which],
+                       f.DA[which], f.DB[which], f.iperm, in, out, work, n_pad, f.B, f.ring, rows);
+  else
+    hipLaunchKernelGGL(band_solve_kernel<double>, dim3(grid), dim3(kRhs), lds, s, f.F[which], f.G[which],
+                       f.T[which], f.iperm, in, out, work, n_pad, f.B, f.ring, rows);
   return hipGetLastError();
 }
 

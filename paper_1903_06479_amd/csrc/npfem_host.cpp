@@ -597,8 +597,9 @@ void factor_layouts(const BandFactorHost& f, int np, int B, std::vector<Real>& F
 }
 
 // Uploads both factors (H~ and M~/h^2) in precision Real, in one band width B (the wider
-// of the two), with the order's inverse permutation; leaves f.F[0] null when the
-// kernel's LDS ring would not fit a compute unit.
+// of the two), with the order's inverse permutation, in the layout of the plan's kernel
+// (FP32: FA, GA, DA, DB; FP64: F, G, T); leaves them null when the kernel's LDS ring
+// would not fit a compute unit.
 template <typename Real>
 npfem_status upload_factor(npfem_plan* p, int np, const std::vector<int>& perm, const BandFactorHost (&fh)[2],
                            BandFactorDev<Real>& f) {
@@ -616,14 +617,15 @@ npfem_status upload_factor(npfem_plan* p, int np, const std::vector<int>& perm, 
   for (int w = 0; w < 2; ++w) {
     std::vector<Real> F, G, T, FA, GA, DA, DB;
     factor_layouts<Real>(fh[w], np, B, F, G, T, FA, GA, DA, DB);
-    if ((s = p->buf.upload(F.data(), F.size(), &f.F[w]))) return s;
-    if ((s = p->buf.upload(G.data(), G.size(), &f.G[w]))) return s;
-    if ((s = p->buf.upload(T.data(), T.size(), &f.T[w]))) return s;
-    if constexpr (std::is_same<Real, float>::value) {       // the matrix-core kernel is FP32 only
+    if constexpr (std::is_same<Real, float>::value) {       // FP32: the matrix-core kernel
       if ((s = p->buf.upload(FA.data(), FA.size(), &f.FA[w]))) return s;
       if ((s = p->buf.upload(GA.data(), GA.size(), &f.GA[w]))) return s;
       if ((s = p->buf.upload(DA.data(), DA.size(), &f.DA[w]))) return s;
       if ((s = p->buf.upload(DB.data(), DB.size(), &f.DB[w]))) return s;
+    } else {                                                // FP64: the vector-unit kernel
+      if ((s = p->buf.upload(F.data(), F.size(), &f.F[w]))) return s;
+      if ((s = p->buf.upload(G.data(), G.size(), &f.G[w]))) return s;
+      if ((s = p->buf.upload(T.data(), T.size(), &f.T[w]))) return s;
     }
   }
   return NPFEM_OK;
@@ -1620,7 +1622,7 @@ npfem_status npfem_solve_factor(npfem_plan* p, int32_t mi, int32_t which, const 
   const MeshPlan& mp = p->meshes[mi];
   const bool fp64 = p->precision == NPFEM_FP64;
   if (bandwidth_out) *bandwidth_out = fp64 ? mp.fac64.b : mp.fac32.b;
-  if (!(fp64 ? (const void*)mp.fac64.F[0] : (const void*)mp.fac32.F[0]))
+  if (!(fp64 ? (const void*)mp.fac64.F[0] : (const void*)mp.fac32.FA[0]))
     return fail(NPFEM_E_UNSUPPORTED, "solve_factor: the factor's band is too wide for the substitution kernel");
   if (rows == 0) return NPFEM_OK;
   if (!in || !out || !work || rows < 0) return fail(NPFEM_E_INVALID, "solve_factor: bad buffers or rows");
