@@ -198,7 +198,8 @@ __global__ __launch_bounds__(kRhs) void band_solve_kernel(const Real* __restrict
 // (lane l holds rows 4 (l >> 4) .. +3 of column l & 15).  The 16 x 16 diagonal block is
 // applied as its inverse, 16 more matrix instructions; the right-hand sides reach the B
 // layout through the ring slots the block is about to fill.  The factor stream runs one
-// 16-position group ahead across blocks; Y rows and the diagonal inverse one block ahead.
+// 16-position group ahead across blocks, the ring values one group ahead within a block;
+// Y rows and the diagonal inverse one block ahead.
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 template <bool kFwd>
@@ -219,6 +220,20 @@ __device__ __forceinline__ void mfma_pass(const float* __restrict__ A, const flo
     an[q] = A[((size_t)b_first * ks + q) * 64 + lane];
     dn[q] = D[((size_t)b_first * 4 + q) * 64 + lane];
   }
+  // ring values of a 16-position group starting at slot sb (a multiple of 16, as are B
+  // and W, so the group does not wrap), in the B-operand layout
+  auto ring_group = [&](int sb, float (&bv)[4][4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bv[q][t] = win[(sb + 4 * q + kq) * kRhs + t * 16 + l16];
+  };
+  auto first_slot = [&](int i0) {
+    const int base = kFwd ? i0 - B : i0 + kFactorMfmaRows;
+    return ((base % W) + W) % W;
+  };
+  float bn_[4][4];
+  ring_group(first_slot(b_first * kFactorMfmaRows), bn_);
   for (int it = 0; it < nb; ++it) {
     const int bi = kFwd ? it : nb - 1 - it;
     const bool more = it + 1 < nb;
@@ -235,27 +250,26 @@ __device__ __forceinline__ void mfma_pass(const float* __restrict__ A, const flo
     }
     const float* __restrict__ Ab = A + (size_t)bi * ks * 64;
     const float* __restrict__ An = more ? A + (size_t)bn * ks * 64 : nullptr;
-    const int base = kFwd ? i0 - B : i0 + kFactorMfmaRows;
-    int sb = ((base % W) + W) % W;                   // a multiple of 16, as are B and W
+    int sb = first_slot(i0);
     for (int g = 0; g < ng; ++g) {
-      float a[4];
+      float a[4], bv[4][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = an[q];
+      for (int q = 0; q < 4; ++q) {
+        a[q] = an[q];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[q][t] = bn_[q][t];
+      }
       const float* __restrict__ src = g + 1 < ng ? Ab + (g + 1) * 256 : An;
       if (src) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) an[q] = src[q * 64 + lane];
       }
-      float bv[4][4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) bv[q][t] = win[(sb + 4 * q + kq) * kRhs + t * 16 + l16];
+      sb = sb + 16 == W ? 0 : sb + 16;
+      if (g + 1 < ng) ring_group(sb, bn_);           // the next group: solved positions only
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], bv[q][t], acc[t], 0, 0, 0);
-      sb = sb + 16 == W ? 0 : sb + 16;
     }
     // the diagonal block: x = L_D^-1 acc (forward) or L_D^-T acc (backward)
     float d[4];
@@ -285,6 +299,8 @@ __device__ __forceinline__ void mfma_pass(const float* __restrict__ A, const flo
         win[(sd + 4 * kq + r) * kRhs + t * 16 + l16] = x[t][r];
         Y[(size_t)(i0 + 4 * kq + r) * kRhs + t * 16 + l16] = x[t][r];
       }
+    // the next block's first group, which may hold the positions just solved
+    if (more) ring_group(first_slot(bn * kFactorMfmaRows), bn_);
   }
 }
 
