@@ -350,9 +350,9 @@ npfem_status npfem_apply_inverse(npfem_plan *plan, int32_t mesh_index, int32_t w
  * each iteration solves with the factor).  A = H~ (which = 0) or M~/h^2 (which = 1) is
  * factored at plan creation as P A P^T = L L^T, with P the reverse Cuthill-McKee order
  * of the mesh's vertex graph, so that L is banded (half bandwidth b); out[r] = A^-1 in[r]
- * is then solved by forward and back substitution with L, one right-hand side per GPU
- * lane, in the plan's precision.  The result equals npfem_apply_inverse's up to
- * rounding.
+ * is then solved by forward and back substitution with L, 64 right-hand sides per GPU
+ * wave, in the plan's precision (FP32 on the matrix cores, in blocks of 16 positions;
+ * FP64 on the vector units).  The result equals npfem_apply_inverse's up to rounding.
  *   in, out  : device [rows][n_pad] row-major, as for npfem_apply_inverse (padding
  *              entries of `in` must be zero; those of `out` are written as zero)
  *   work     : device workspace owned by the caller, at least
