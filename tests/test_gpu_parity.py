@@ -122,6 +122,38 @@ def test_solve_factor_matches_oracle(precision, n):
         assert np.all(err <= 1.01 * inv_norm * np.linalg.norm(resid, axis=1) + 1e-12 * np.linalg.norm(ref, axis=1))
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_solve_factor_second_mesh_and_row_counts(precision):
+    """A plan of two mesh types (258 and 642 vertices, different n_pad and bands): the
+    solves of mesh index 1 with 1, 64 (one full wave) and 65 right-hand sides, each
+    against the oracle's solve within the backward-error bound of
+    test_solve_factor_matches_oracle; mesh index 0 is solved by its own factor."""
+    from paper_1903_06479_amd import Mesh, Plan, default_params
+    m0, m1 = oracle_model(258), oracle_model(642)
+    plan = Plan([Mesh(m0.X, m0.tris), Mesh(m1.X, m1.tris)], DT, params=default_params(precision=precision))
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    u = 2.0 ** -53 if precision == "fp64" else 2.0 ** -24
+    rng = np.random.default_rng(11)
+    for mi, m in ((1, m1), (0, m0)):
+        n, npad, b = m.X.shape[0], plan.n_pad(mi), plan.factor_bandwidth(mi)
+        gamma = 1.01 * (3 * b + 6) * u
+        sd = np.sqrt(np.diag(m.Ht))
+        for rows in (1, 64, 65):
+            q = np.zeros((rows, npad))
+            q[:, :n] = rng.standard_normal((rows, n))
+            q = q.astype(np.float32).astype(np.float64) if precision == "fp32" else q
+            out = plan.solve_factor(mi, 0, T(q, dt)).cpu().numpy().astype(np.float64)
+            assert np.abs(out[:, n:]).max() == 0.0
+            x = out[:, :n]
+            resid = np.abs(q[:, :n] - x @ m.Ht)
+            w = np.sort(np.abs(x) * sd, axis=1)[:, ::-1][:, :4 * b + 1].sum(axis=1)
+            assert np.all(resid <= gamma * np.outer(w, sd)), (mi, rows)
+            ref = m.solve_Ht(q[:, :n].T).T
+            err = np.linalg.norm(x - ref, axis=1)
+            inv_norm = 1.0 / np.linalg.eigvalsh(m.Ht)[0]
+            assert np.all(err <= 1.01 * inv_norm * np.linalg.norm(resid, axis=1) + 1e-12 * np.linalg.norm(ref, axis=1))
+
+
 def test_solve_factor_arguments_and_workspace_reuse():
     """Workspace size checks, rows = 0, a bad `which`, and one workspace reused by two
     calls of different sizes (the second smaller)."""
