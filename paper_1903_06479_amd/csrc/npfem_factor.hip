@@ -7,7 +7,7 @@
 // Both kernels give one wave 64 right-hand sides.  The right-hand sides are brought into
 // the order and transposed to [position][right-hand side] once, through an LDS tile, into
 // the caller's workspace, which then holds y and z; the result goes back the same way.
-// The solved positions still inside the band sit in an LDS ring (one 256-byte row per
+// The solved positions still inside the band sit in an LDS ring (one row of 64 values per
 // position).
 //   FP32: the matrix cores, blocks of 16 positions (band_solve_mfma_kernel).
 //   FP64: the vector units, one lane per right-hand side, blocks of 8 positions; the
@@ -27,13 +27,10 @@ namespace {
 constexpr int kRhs = 64;        // right-hand sides per wave (one per lane)
 constexpr int kTileRow = 65;    // padded row of the 64 x 64 transpose tile
 
-// acc[k] += sum over jj < B of C[jj][k] * ring[(base + jj) mod W], B a multiple of 16; the
-// ring holds W = B + 16 positions and base is a multiple of 8, so a run of 8 positions
-// that starts at a multiple of 8 never wraps: slots advance 8 at a time.
-// (the factor entries are stored negated).
-//
-// FP64: in groups of one position; the next group's factor entries (scalar loads) and
-// ring value (LDS) are requested before the current group's FMAs.
+// acc[k] += sum over jj < B of C[jj][k] * ring[(base + jj) mod W] (the factor entries are
+// stored negated; the ring holds W = B + 16 positions), one position at a time: the next
+// position's factor entries (scalar loads) and ring value (LDS) are requested before the
+// current position's FMAs.
 template <typename Real>
 __device__ __forceinline__ void band_dot(Real (&acc)[kFactorRows], const Real* __restrict__ C, const Real* win,
                                          int base, int W, int B, int lane) {
