@@ -59,6 +59,20 @@ def test_mesh_validation_errors():
         Mesh(w, f)
 
 
+def test_solve_entry_points_reject_a_null_plan():
+    """The product and factor-solve entry points check their plan before any device
+    call (no GPU is touched): a NULL plan is NPFEM_E_INVALID, and the workspace query
+    returns -1."""
+    from ctypes import c_void_p
+    L = N.lib()
+    nul = c_void_p(0)
+    assert L.npfem_solve_factor_workspace(nul, 0, 10) == -1
+    assert L.npfem_solve_factor(nul, 0, 0, nul, nul, 10, nul, 0, nul, nul) == -1
+    assert L.npfem_last_error() == b"solve_factor: NULL plan"
+    assert L.npfem_apply_inverse(nul, 0, 0, nul, nul, 10, nul, nul) == -1
+    assert L.npfem_last_error() == b"apply_inverse: NULL plan"
+
+
 @pytest.mark.parametrize("n", [258, 642])
 def test_host_rest_data_matches_oracle(n):
     m = oracle_model(n)
