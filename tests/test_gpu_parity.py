@@ -154,6 +154,37 @@ def test_solve_factor_second_mesh_and_row_counts(precision):
             assert np.all(err <= 1.01 * inv_norm * np.linalg.norm(resid, axis=1) + 1e-12 * np.linalg.norm(ref, axis=1))
 
 
+@pytest.mark.parametrize("kind,n,k_mat", [("sphere", 642, None), ("rbc", 642, 0.0), ("rbc", 258, 0.0)])
+def test_solve_factor_other_meshes_and_materials(kind, n, k_mat):
+    """The factor route on a different H~: the sphere mesh (another vertex graph and
+    band), and H~ without the material term (k_mat = 0, section 2.1.1), FP32, against the
+    oracle's solve of its own H~ within the backward-error bound of
+    test_solve_factor_matches_oracle."""
+    from paper_1903_06479_amd import Mesh, Plan, default_material, default_params
+    kw = {} if k_mat is None else {"k_mat": k_mat}
+    m = oracle_model(n, kind=kind, **kw)
+    mat = default_material(**({} if k_mat is None else {"k_mat": k_mat}))
+    plan = Plan([Mesh(m.X, m.tris)], DT, material=mat, params=default_params())
+    npad, b = plan.n_pad(0), plan.factor_bandwidth(0)
+    gamma = 1.01 * (3 * b + 6) * 2.0 ** -24
+    rng = np.random.default_rng(n + 7)
+    rows = 70
+    q = np.zeros((rows, npad))
+    q[:, :n] = rng.standard_normal((rows, n))
+    q = q.astype(np.float32).astype(np.float64)
+    out = plan.solve_factor(0, 0, T(q, torch.float32)).cpu().numpy().astype(np.float64)
+    assert np.abs(out[:, n:]).max() == 0.0
+    x = out[:, :n]
+    resid = np.abs(q[:, :n] - x @ m.Ht)
+    sd = np.sqrt(np.diag(m.Ht))
+    w = np.sort(np.abs(x) * sd, axis=1)[:, ::-1][:, :4 * b + 1].sum(axis=1)
+    assert np.all(resid <= gamma * np.outer(w, sd))
+    ref = m.solve_Ht(q[:, :n].T).T
+    err = np.linalg.norm(x - ref, axis=1)
+    inv_norm = 1.0 / np.linalg.eigvalsh(m.Ht)[0]
+    assert np.all(err <= 1.01 * inv_norm * np.linalg.norm(resid, axis=1) + 1e-12 * np.linalg.norm(ref, axis=1))
+
+
 def test_solve_factor_arguments_and_workspace_reuse():
     """Workspace size checks, rows = 0, a bad `which`, and one workspace reused by two
     calls of different sizes (the second smaller)."""
